@@ -1,0 +1,297 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed forms,
+limits, invariants, symmetries, or an independent brute-force assembly of the
+discrete equations. Together they are meant to catch a dropped term, a wrong
+sign or index, or a transposed operand anywhere in the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import bte_inputs as bi
+import oracle
+from oracle import dense
+
+FOUR_PI = 4.0 * math.pi
+
+
+# ---------------------------------------------------------------- P1 quadrature
+@pytest.mark.parametrize("n_mu", [2, 8, 32])
+def test_quadrature_gl_mu_moments(n_mu):
+    s, w = bi.quad_gl_mu(n_mu)
+    assert abs(w.sum() - FOUR_PI) < 1e-13
+    assert abs((w * s[:, 0]).sum()) < 1e-13
+    assert abs((w * s[:, 0] ** 2).sum() - FOUR_PI / 3) < 1e-13
+    assert np.allclose(np.linalg.norm(s, axis=1), 1.0, atol=1e-15)
+    # closed under mu -> -mu
+    assert np.allclose(np.sort(s[:, 0]), np.sort(-s[:, 0]), atol=1e-15)
+
+
+@pytest.mark.parametrize("nt,nph,axis", [(4, 4, 0), (8, 2, 2), (4, 2, 2), (2, 1, 2)])
+def test_quadrature_octant_moments(nt, nph, axis):
+    s, w = bi.quad_octant_gl(nt, nph, axis)
+    assert s.shape == (8 * nt * nph, 3)
+    assert abs(w.sum() - FOUR_PI) < 1e-12
+    assert np.all(w > 0)
+    assert np.allclose(np.linalg.norm(s, axis=1), 1.0, atol=1e-14)
+    assert np.abs((w[:, None] * s).sum(0)).max() < 1e-12
+    second = (w[:, None, None] * s[:, :, None] * s[:, None, :]).sum(0)
+    off = second - np.diag(np.diag(second))
+    assert np.abs(off).max() < 1e-12
+    # the product rule's second moments approach 4 pi / 3 as the rule refines
+    tol = {2: 0.2, 4: 2e-2, 8: 2e-2}[nt]
+    assert np.abs(np.diag(second) - FOUR_PI / 3).max() < tol * FOUR_PI / 3
+    # closed under each axis reflection
+    for d in range(3):
+        r = s.copy()
+        r[:, d] *= -1
+        for a in range(s.shape[0]):
+            k = np.argmin(np.linalg.norm(s - r[a], axis=1))
+            assert np.linalg.norm(s[k] - r[a]) < 1e-14 and abs(w[k] - w[a]) < 1e-15
+
+
+# ------------------------------------------------------ P2 single-sweep closed form
+def test_single_sweep_geometric_series():
+    """One sweep from a uniform T0 with a hot left wall: for mu > 0 the energy
+    relaxes as e_i - e0 = (e_wall - e0) r^(i+1), r = alpha/(1/tau + alpha),
+    alpha = v mu / h; directions with mu < 0 see the right wall at T0 and stay
+    at e0 exactly."""
+    p = bi.film_1d(n_cells=40, L=20e-9, Kn=0.5, T_h=301.0, T_c=300.0, n_mu=8)
+    r = oracle.solve(p, max_iters=1, tol=0.0, want_e=True)
+    e = r["e"][0]
+    C, v, tau, h = p.C[0], p.v[0], p.tau[0], p.h[0]
+    e0 = C * 300.0 / FOUR_PI
+    de_w = C * 1.0 / FOUR_PI
+    i = np.arange(p.ncell)
+    for a in range(p.M):
+        mu = p.s[a, 0]
+        if mu > 0:
+            alpha = v * mu / h
+            rr = alpha / (1.0 / tau + alpha)
+            expect = e0 + de_w * rr ** (i + 1)
+        else:
+            expect = np.full(p.ncell, e0)
+        assert np.abs(e[a] - expect).max() <= 1e-13 * e0
+    # and T after one sweep is the weighted sum of those closed forms
+    Texp = np.zeros(p.ncell)
+    for a in range(p.M):
+        mu = p.s[a, 0]
+        rr = (v * mu / h) / (1.0 / tau + v * mu / h) if mu > 0 else 0.0
+        Texp += p.w[a] * (300.0 + (rr ** (i + 1) if mu > 0 else 0.0))
+    Texp /= FOUR_PI
+    assert np.abs(r["T"] - Texp).max() < 1e-12
+
+
+def test_single_sweep_constant_source():
+    """Constant source, both walls at T0, one sweep: for mu > 0,
+    e_i - e0 = Qs tau (1 - r^(i+1)) with Qs = Q/(4 pi) (gray band)."""
+    n = 30
+    p = bi.film_1d(n_cells=n, L=15e-9, Kn=0.3, T_h=300.0, T_c=300.0, n_mu=4,
+                   Q=np.full(n, 3e18))
+    r = oracle.solve(p, max_iters=1, tol=0.0, want_e=True)
+    C, v, tau, h = p.C[0], p.v[0], p.tau[0], p.h[0]
+    Qs = 3e18 / FOUR_PI
+    i = np.arange(n)
+    e0 = C * 300.0 / FOUR_PI
+    for a in range(p.M):
+        mu = p.s[a, 0]
+        alpha = v * abs(mu) / h
+        rr = alpha / (1.0 / tau + alpha)
+        k = i if mu > 0 else (n - 1 - i)
+        expect = e0 + Qs * tau * (1.0 - rr ** (k + 1))
+        assert np.abs(r["e"][0, a] - expect).max() <= 1e-12 * abs(Qs * tau)
+
+
+# ------------------------------------------------------------- P3 brute force
+@pytest.mark.parametrize("seed,kinds", [(0, (0, 1)), (1, (0, 0)), (2, (0, 1))])
+def test_fixed_point_matches_dense_2d(seed, kinds):
+    p = bi.random_box_2d(5, 4, seed=seed, n_bands=3, n_theta=1, n_phi=1, kinds=kinds)
+    Td = dense.solve_dense(p)
+    r = oracle.solve(p, tol=0.0, max_iters=6000)
+    act = p.mask > 0
+    scale = np.abs(Td[act] - p.T_ref).max()
+    assert np.abs(r["T"][act] - Td[act]).max() < 1e-11 * scale
+
+
+def test_fixed_point_matches_dense_3d():
+    p = bi.random_box_3d(4, 3, 5, seed=5, n_bands=2, n_theta=1, n_phi=1)
+    Td = dense.solve_dense(p)
+    r = oracle.solve(p, tol=0.0, max_iters=6000)
+    act = p.mask > 0
+    scale = np.abs(Td[act] - p.T_ref).max()
+    assert scale > 1e-6
+    assert np.abs(r["T"][act] - Td[act]).max() < 1e-10 * scale
+
+
+def test_fixed_point_matches_dense_1d_nongray():
+    base = bi.film_1d(n_cells=12, L=12e-9, n_mu=6, T_h=302.0, T_c=299.0)
+    v, tau, C = bi.band_table_synthetic(4)
+    p = base.replace(v=v, tau=tau * 0.01, C=C, Q=np.linspace(0, 1e18, 12))
+    Td = dense.solve_dense(p)
+    r = oracle.solve(p, tol=0.0, max_iters=3000)
+    assert np.abs(r["T"] - Td).max() < 1e-11 * np.abs(Td - 300).max()
+
+
+# --------------------------------------------------------------- P4 ballistic
+def test_ballistic_limit():
+    p = bi.film_1d(n_cells=50, Kn=1e6, n_mu=32, T_h=301.0, T_c=299.0)
+    r = oracle.solve(p, tol=1e-13, max_iters=200)
+    assert np.abs(r["T"] - 300.0).max() < 1e-5
+    mu = p.s[:, 0]
+    half = float((p.w * np.where(mu > 0, mu, 0.0)).sum())
+    q_ball = p.C[0] * p.v[0] * 2.0 * half / FOUR_PI
+    assert np.abs(r["q"][:, 0] / q_ball - 1.0).max() < 1e-5
+
+
+# --------------------------------------------------------------- P5 diffusive
+def test_diffusive_interior_is_linear_fourier():
+    """Gray film at Kn = 0.01: e_a = C/(4 pi) (T - v tau mu_a T') with T linear
+    solves the upwind equations exactly, so the converged interior is linear in
+    x and carries q = -(C v^2 tau sum w mu^2 /(4 pi)) dT/dx."""
+    n, L = 400, 100e-9
+    p = bi.film_1d(n_cells=n, L=L, Kn=0.01, n_mu=16, T_h=301.0, T_c=299.0)
+    x = (np.arange(n) + 0.5) / n
+    r = oracle.solve(p, T_init=301.0 - 2.0 * x, tol=1e-14, tol_q=1e-14, max_iters=200000)
+    T = r["T"]
+    lo, hi = n // 4, 3 * n // 4
+    d2 = T[lo + 1:hi + 1] - 2 * T[lo:hi] + T[lo - 1:hi - 1]
+    slope = (T[hi] - T[lo]) / ((hi - lo) * p.h[0])
+    assert np.abs(d2).max() < 1e-9 * abs(slope * p.h[0])
+    k = p.C[0] * p.v[0] ** 2 * p.tau[0] * float((p.w * p.s[:, 0] ** 2).sum()) / FOUR_PI
+    q = r["q"][lo:hi, 0]
+    assert np.abs(q / (-k * slope) - 1.0).max() < 1e-8
+
+
+# ------------------------------------------------------ P7 energy conservation
+def _face_flux_divergence(p, r):
+    """Discrete divergence of the band/direction-summed upwind face fluxes of the
+    oracle's final angular field, per active cell (W/m^3)."""
+    e = r["e"]
+    eb = r.get("eb")
+    n0, n1, n2 = p.n
+    act = np.flatnonzero(p.mask)
+    # boundary faces in the oracle's order: active cells ascending, faces ascending
+    slot = {}
+    for c in act:
+        for f in range(2 * p.dim):
+            if _nb(p, c, f) < 0:
+                slot[(c, f)] = len(slot)
+    div = np.zeros(p.ncell)
+    for c in act:
+        tot = 0.0
+        for f in range(2 * p.dim):
+            d = f // 2
+            sn = p.s[:, d] if f % 2 else -p.s[:, d]
+            nb = _nb(p, c, f)
+            flux = 0.0
+            for b in range(p.B):
+                if nb >= 0:
+                    eface = np.where(sn > 0, e[b, :, c], e[b, :, nb])
+                else:
+                    eface = np.where(sn > 0, e[b, :, c], eb[b, slot[(c, f)]])
+                flux += p.v[b] * float((p.w * sn * eface).sum())
+            tot += flux / p.h[d]
+        div[c] = tot
+    return div
+
+
+def _nb(p, c, f):
+    n0, n1, n2 = p.n
+    idx = [c % n0, (c // n0) % n1, c // (n0 * n1)]
+    d = f // 2
+    idx[d] += 1 if f % 2 else -1
+    if idx[d] < 0 or idx[d] >= p.n[d]:
+        return -1
+    nb = idx[0] + n0 * (idx[1] + n1 * idx[2])
+    return nb if p.mask[nb] else -1
+
+
+def test_energy_balance_per_cell_with_diffuse_walls():
+    """At the fixed point, the discrete divergence of the total heat flux equals
+    the heat source in every cell (summing the per-ordinate balances over bands
+    and directions, the scattering terms cancel by the T_L definition and the
+    source shares sum to Q), and a diffuse wall carries no net flux."""
+    p = bi.random_box_2d(6, 5, seed=3, n_bands=3, n_theta=2, n_phi=1, kinds=(0, 1))
+    r = oracle.solve(p, tol=0.0, max_iters=4000, want_e=True, want_eb=True)
+    div = _face_flux_divergence(p, r)
+    act = p.mask > 0
+    Qmax = np.abs(p.Q).max()
+    assert np.abs(div[act] - p.Q[act]).max() < 1e-9 * Qmax
+    # net flux through the diffuse faces vanishes face by face
+    e, eb = r["e"], r["eb"]
+    k = 0
+    for c in np.flatnonzero(p.mask):
+        for f in range(4):
+            if _nb(p, c, f) >= 0:
+                continue
+            if p.bc_kind[p.face_bc[c, f]] == 1:
+                d = f // 2
+                sn = p.s[:, d] if f % 2 else -p.s[:, d]
+                net = sum(p.v[b] * float((p.w * sn * np.where(sn > 0, e[b, :, c], eb[b, k])).sum())
+                          for b in range(p.B))
+                out = sum(p.v[b] * float((p.w * np.maximum(sn, 0) * e[b, :, c]).sum())
+                          for b in range(p.B))
+                assert abs(net) < 1e-10 * abs(out) + 1e-20
+            k += 1
+
+
+def test_1d_face_flux_uniform_without_source():
+    p = bi.film_1d(n_cells=60, L=30e-9, Kn=1.0, n_mu=16)
+    r = oracle.solve(p, tol=1e-14, max_iters=2000, want_e=True, want_eb=True)
+    div = _face_flux_divergence(p, r)
+    q_scale = np.abs(r["q"]).max()
+    assert np.abs(div).max() * p.h[0] < 1e-10 * q_scale
+
+
+def test_global_energy_balance_3d():
+    p = bi.finfet_3d(scale=16, n_bands=2, n_theta=1, n_phi=1)
+    r = oracle.solve(p, tol=0.0, max_iters=3000, want_e=True, want_eb=True)
+    div = _face_flux_divergence(p, r)
+    vol = p.h[0] * p.h[1] * p.h[2]
+    assert abs(div.sum() * vol - p.Q.sum() * vol) < 1e-9 * p.Q.sum() * vol
+
+
+# ------------------------------------------------------------ P8 symmetry
+def test_film_antisymmetry():
+    p = bi.film_1d()
+    r = oracle.solve(p, tol=1e-13)
+    dT = r["T"] - 300.0
+    assert np.abs(dT + dT[::-1]).max() < 1e-12 * np.abs(dT).max()
+
+
+def test_square_d4_symmetry():
+    p = bi.square_2d(16, L=0.2e-6, n_bands=3, n_theta=2, n_phi=2, centered=True)
+    r = oracle.solve(p, tol=1e-13, max_iters=5000)
+    T = r["T"].reshape(16, 16) - 300.0
+    sc = np.abs(T).max()
+    for U in (T[:, ::-1], T[::-1, :], T.T, T[::-1, ::-1].T):
+        assert np.abs(T - U).max() < 1e-12 * sc
+
+
+# ---------------------------------------------- P12 equilibrium and linearity
+def test_equilibrium_is_exact():
+    p = bi.random_box_2d(6, 5, seed=4, n_bands=3, n_theta=2, n_phi=1, kinds=(0, 1),
+                         T_walls=(307.0, 307.0), Q0=0.0)
+    r = oracle.solve(p, T_init=np.full(p.ncell, 300.0), tol=0.0, max_iters=3000)
+    act = p.mask > 0
+    assert np.abs(r["T"][act] - 307.0).max() < 1e-10
+
+
+def test_linearity_and_superposition():
+    p = bi.square_2d(12, L=0.1e-6, n_bands=3, n_theta=2, n_phi=1)
+    Q1 = p.Q
+    Q2 = np.roll(p.Q, 17)
+    r1 = oracle.solve(p, Q=Q1, tol=1e-14, max_iters=3000)["T"] - 300
+    r2 = oracle.solve(p, Q=Q2, tol=1e-14, max_iters=3000)["T"] - 300
+    r3 = oracle.solve(p, Q=2.5 * Q1 - Q2, tol=1e-14, max_iters=3000)["T"] - 300
+    sc = np.abs(r3).max()
+    assert np.abs(r3 - (2.5 * r1 - r2)).max() < 1e-11 * sc
+
+
+def test_thread_count_does_not_change_result():
+    p = bi.square_2d(16, L=0.3e-6, n_bands=3, n_theta=2, n_phi=1)
+    a = oracle.solve(p, tol=0.0, max_iters=7, threads=1)
+    b = oracle.solve(p, tol=0.0, max_iters=7, threads=4)
+    assert np.array_equal(a["T"], b["T"]) and np.array_equal(a["q"], b["q"])

@@ -1,0 +1,217 @@
+/*
+ * bte.h -- C ABI of the MI355X phonon-BTE source-iteration library.
+ *
+ * The library solves the steady, nongray phonon Boltzmann transport equation in
+ * the relaxation-time approximation (paper Methods, "Phonon BTE", Eq. 1 with the
+ * relaxation sign of Eq. eq:bte-2), discretized by spectral bands (Eqs. 8-13)
+ * times discrete ordinates (Eq. 14) and first-order upwind finite volumes on a
+ * Cartesian voxel mask (Eq. eq:fvm-1 with upwind face values), by source
+ * iteration: every iteration sweeps every (band, direction) pair exactly (the
+ * first-order upwind matrix A of Eq. A_matrix is triangular in upwind order)
+ * and updates the lattice temperature from the weighted band/direction sum
+ * (Eq. updatee0_t), until the residuals of Eq. 22 fall below the targets
+ * (Methods, "Iterative matrix formulation and solution scheme").
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a bte_status; bte_last_error() describes the most
+ *     recent failure on the calling thread (static, thread-local storage).
+ *   - Cells are indexed c = i + n0*(j + n1*k) (x fastest). Cell arrays cover
+ *     the whole bounding box; inactive cells are ignored on input and written
+ *     as 0 on output.
+ *   - Faces of a cell are numbered 0..5 = -x, +x, -y, +y, -z, +z.
+ *   - Pointers named h_* are host pointers; d_* are device pointers on the
+ *     device that was current when the handle was created. The caller owns all
+ *     memory it passes; the library never frees it and never retains it beyond
+ *     the call. The library owns the device memory of a handle (allocated in
+ *     bte_create / bte_batch_create, freed by bte_destroy).
+ *   - hip_stream is a hipStream_t (NULL = the null stream). Work is enqueued on
+ *     it; calls that report convergence synchronise with it before returning.
+ *   - Handles are not thread-safe; use one handle from one thread at a time.
+ *   - Temperatures are absolute (K). The library works internally with
+ *     deviations from T_ref, which is exact because the equations are linear in
+ *     (e, T) when C does not depend on T.
+ */
+#ifndef BTE_H
+#define BTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BTE_OK = 0,
+  BTE_ERR_INVALID = 1,        /* bad argument; outputs untouched */
+  BTE_ERR_HIP = 2,            /* HIP runtime error (message in bte_last_error) */
+  BTE_ERR_NOT_CONVERGED = 3,  /* max_iters reached; outputs hold the last iterate */
+  BTE_ERR_NONFINITE = 4,      /* a non-finite temperature or flux appeared */
+  BTE_ERR_STATE = 5           /* call order violated (e.g. adjoint before solve) */
+} bte_status;
+
+/* Boundary-condition kinds (paper Methods, "Boundary conditions"). */
+enum {
+  BTE_BC_ISOTHERMAL = 0, /* thermalizing wall at bc_T (Eq. 5) */
+  BTE_BC_DIFFUSE = 1,    /* diffusely reflecting adiabatic wall (Eq. 6) */
+  BTE_BC_SPECULAR = 2    /* specular wall (Eq. 7): rejected with BTE_ERR_INVALID */
+};
+
+/* Arithmetic of the sweeps. FP64: everything in double. FP32: the transport
+   sweep in float, band/direction partial sums promoted to double across
+   ordinate groups, temperatures and residuals in double. */
+enum { BTE_PREC_FP64 = 0, BTE_PREC_FP32 = 1 };
+
+typedef struct {
+  int dim;                  /* 1, 2 or 3 */
+  int n[3];                 /* cells per axis; unused axes must be 1 */
+  double h[3];              /* cell size per axis (m); unused axes ignored */
+  const uint8_t* h_mask;    /* [ncell] 1 = active; NULL = all active */
+  const uint8_t* h_face_bc; /* [ncell*6] bc id of face f of cell c when that face
+                               is a boundary (domain edge or inactive neighbour);
+                               other entries ignored; NULL = every boundary face bc 0 */
+  int n_bc;                 /* number of boundary conditions (1..255) */
+  const int* h_bc_kind;     /* [n_bc] BTE_BC_* */
+  const double* h_bc_T;     /* [n_bc] wall temperature (K), isothermal walls */
+} bte_geometry;
+
+typedef struct {
+  int n_bands;              /* B >= 1 */
+  const double* h_v;        /* [B] group velocity (m/s), > 0 */
+  const double* h_tau;      /* [B] relaxation time (s), > 0 */
+  const double* h_C;        /* [B] volumetric heat capacity (J m^-3 K^-1), > 0 */
+} bte_bands;
+
+typedef struct {
+  int n_dirs;               /* M >= 1 */
+  const double* h_s;        /* [M*3] unit directions (x, y, z) */
+  const double* h_w;        /* [M] weights, > 0, summing to 4*pi */
+} bte_quadrature;
+
+/* Kernel shape of the sweep (chosen by bte_autotune, or set by hand).
+   G: ordinates per lane (1, 2, 4 or 8); R: waves per workgroup that pipeline
+   successive 64-row strips (2D/1D only; 1..16); P: waves per workgroup that
+   sweep different ordinate groups of one quadrant in lockstep and share one
+   partial sum per cell (1..8); C: steps between workgroup barriers (4..64,
+   multiple of 4). Zero fields mean "library default". */
+typedef struct { int G, R, P, C; } bte_plan;
+
+typedef struct {
+  double tol_T;        /* target eps_T (Eq. 22, normalised by max |T - T_ref|); <= 0: run max_iters */
+  double tol_q;        /* target eps_q (Eq. 22); <= 0: run max_iters */
+  int max_iters;       /* >= 1 */
+  int check_every;     /* iterations between convergence checks (>= 1); 0 = default (8) */
+  int use_graph;       /* 1 = replay a captured hipGraph of check_every iterations */
+  int store_state;     /* bte_solve: keep what bte_adjoint needs (the angular field) */
+} bte_opts;
+
+typedef struct {
+  int iters;           /* iterations performed */
+  double eps_T, eps_q; /* residuals at the last check */
+  double seconds;      /* wall time of the iteration loop */
+  int status;          /* bte_status of this solve */
+} bte_report;
+
+typedef struct bte_ctx* bte_handle;
+
+/* Library version string (static storage). */
+const char* bte_version(void);
+
+/* Description of the most recent failure on this thread (static storage). */
+const char* bte_last_error(void);
+
+/* Host-only validation of a problem (no device call). Returns BTE_OK or
+   BTE_ERR_INVALID for: dim not in 1..3; n < 1 or h <= 0 on a used axis, or
+   n != 1 on an unused axis; no active cell; n_bc out of range, a bc kind other
+   than isothermal/diffuse, a face_bc entry >= n_bc on a boundary face;
+   no isothermal boundary face (no unique steady state: the T_L update
+   conserves energy, so heat can leave only through isothermal walls);
+   B < 1, any v, tau or C <= 0 or non-finite; M < 1, |s| != 1 (1e-12),
+   w <= 0, |sum w - 4 pi| > 1e-10 * 4 pi, or a quadrature not closed under the
+   reflection of each grid axis. */
+bte_status bte_validate(const bte_geometry* geom, const bte_bands* bands,
+                        const bte_quadrature* quad);
+
+/* Gauss-Legendre quadrature in mu = cos(theta) for a 1D slab: s_a = (mu_a,
+   sqrt(1 - mu_a^2), 0), w_a = 2 pi g_a. h_s: [n_mu*3], h_w: [n_mu]. */
+bte_status bte_quadrature_gl_mu(int n_mu, double* h_s, double* h_w);
+
+/* Octant-product Gauss-Legendre quadrature (paper Eq. 14): per octant an
+   n_theta x n_phi product of Gauss-Legendre rules in theta and phi on (0, pi/2)
+   with weights beta_theta * beta_phi * sin(theta), rescaled so they sum to 4 pi.
+   polar_axis 0 gives s = (cos t, sin t cos p, sin t sin p) as in the paper; 2
+   puts the polar axis on z. h_s: [8*n_theta*n_phi*3], h_w: [8*n_theta*n_phi]. */
+bte_status bte_quadrature_octant_gl(int n_theta, int n_phi, int polar_axis, double* h_s,
+                                    double* h_w);
+
+/* Create a solver for one problem on the current device. Validates as
+   bte_validate, derives the per-band and per-ordinate constants, the boundary
+   face tables and the sweep schedule, and allocates the device state.
+   T_ref: reference temperature of the deviational variables (K). */
+bte_status bte_create(const bte_geometry* geom, const bte_bands* bands,
+                      const bte_quadrature* quad, double T_ref, int precision,
+                      bte_handle* out);
+
+/* Replace the relaxation times (e.g. between optimisation steps). h_tau: [B]. */
+bte_status bte_set_tau(bte_handle h, const double* h_tau);
+
+/* Set / get the sweep kernel shape. */
+bte_status bte_set_plan(bte_handle h, const bte_plan* plan);
+bte_status bte_get_plan(bte_handle h, bte_plan* plan);
+
+/* Time candidate kernel shapes on this problem (n_iters sweeps each, after one
+   warm-up) and keep the fastest; writes it to *best (may be NULL).
+   d_Q: [ncell] heat source used for the timing runs (NULL = zero). */
+bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_stream,
+                        bte_plan* best);
+
+/* Solve. d_Q: [ncell] heat source (W/m^3); d_T_init: [ncell] initial
+   temperature (K) or NULL for T_ref everywhere (a previous result resumes the
+   iteration: warm start); d_T: [ncell] output temperature T_L (K);
+   d_q: [ncell*dim] output heat flux (W/m^2, grid axes) or NULL.
+   Returns BTE_OK when converged, BTE_ERR_NOT_CONVERGED after max_iters (outputs
+   hold the last iterate), BTE_ERR_NONFINITE on a non-finite iterate. */
+bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, double* d_T,
+                     double* d_q, const bte_opts* opts, void* hip_stream, bte_report* h_rep);
+
+/* Adjoint of the converged source-iteration fixed point (needs a previous
+   bte_solve on h with opts->store_state = 1; isothermal walls only).
+   Given d_dJdT = dJ/dT [ncell], iterates lambda = dJ/dT + sum_b k_b sum_a psi
+   with psi = transpose sweeps (direction -s_a, zero inflow) of lambda, then
+   writes h_dJdtau [B] (host) and d_dJdQ [ncell] (device); either may be NULL. */
+bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, double* d_dJdQ,
+                       const bte_opts* opts, void* hip_stream, bte_report* h_rep);
+
+/* Average device time (ms) of one launch of the forward sweep kernel on the
+   current state, measured with HIP events around n_launches back-to-back
+   launches on hip_stream; also returns the number of cell x ordinate x band
+   updates one launch performs. Requires a previous bte_solve. */
+bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double* h_ms,
+                          double* h_updates);
+
+/* Batched solver: n_inst problems of the same dimension, band table and
+   quadrature, swept by one persistent launch per iteration with per-instance
+   convergence and retirement. geoms: [n_inst]. */
+bte_status bte_batch_create(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
+                            const bte_quadrature* quad, double T_ref, int precision,
+                            bte_handle* out);
+
+/* d_Q[i], d_T[i], d_q[i]: device arrays of instance i (d_q may be NULL or hold
+   NULL entries). h_reps: [n_inst] or NULL. Returns BTE_OK when every instance
+   converged, else the worst status. */
+bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const* d_T,
+                           double* const* d_q, const bte_opts* opts, void* hip_stream,
+                           bte_report* h_reps);
+
+/* Batched adjoint (after bte_batch_solve with store_state). h_dJdtau: [n_inst*B]. */
+bte_status bte_batch_adjoint(bte_handle h, const double* const* d_dJdT, double* h_dJdtau,
+                             double* const* d_dJdQ, const bte_opts* opts, void* hip_stream,
+                             bte_report* h_reps);
+
+/* Free the handle and its device memory. NULL is allowed. */
+bte_status bte_destroy(bte_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTE_H */

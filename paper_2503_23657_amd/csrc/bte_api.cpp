@@ -1,0 +1,1216 @@
+// C ABI of the sweep library: problem set-up, device state, the iteration loop
+// (replayed as a hipGraph), the adjoint, batching and the kernel-shape tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bte.h"
+#include "bte_device.h"
+#include "bte_launch.h"
+#include "bte_setup.h"
+
+using namespace bte;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char* f, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, f);
+  vsnprintf(buf, sizeof(buf), f, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) {                                                             \
+      set_err("HIP error '%s' at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__);   \
+      return BTE_ERR_HIP;                                                               \
+    }                                                                                   \
+  } while (0)
+
+const double kPi = 3.14159265358979323846;
+
+// Device allocations owned by a handle.
+struct DevPool {
+  std::vector<void*> ptrs;
+  ~DevPool() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = reinterpret_cast<T*>(p);
+    return hipSuccess;
+  }
+  template <typename T>
+  hipError_t upload(T** out, const std::vector<T>& v) {
+    hipError_t e = alloc(out, v.size());
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+      }
+  }
+};
+
+struct Inst {
+  HostInst hi;
+  Schedule sch;
+  int grp0 = 0;   // global index of the first group
+  int job0 = 0;   // global index of the first job
+  int n_grp = 0, n_jobs = 0;
+  int n_fblocks = 0;
+  // plan-independent device data
+  unsigned char* d_active = nullptr;
+  double* d_X[2] = {nullptr, nullptr};
+  double* d_Xa[2] = {nullptr, nullptr};
+  double* d_qmag = nullptr;
+  double* d_qbuf = nullptr;     // internal heat-flux output
+  double* d_dqbuf = nullptr;    // internal dJ/dQ output
+  double* d_blockpart = nullptr;
+  int* d_bf_bc = nullptr;
+  int* d_bf_cell = nullptr;
+  int* d_bc_kind = nullptr;
+  double* d_bc_T = nullptr;
+  int* d_dface = nullptr;
+  double* d_inv_half = nullptr;
+  void* d_ubf = nullptr;        // forward inflow table
+  void* d_ubf0 = nullptr;       // zeros (adjoint)
+  // plan-dependent device data (owned by the plan pool)
+  int2* d_sched = nullptr;
+  int* d_pos = nullptr;
+  int* d_in_slot = nullptr;
+  int* d_in_chunk = nullptr;
+  int* d_out_base = nullptr;
+  int* d_pre_slot = nullptr;
+  int* d_ofk = nullptr;
+  int2* d_grp_ob = nullptr;
+  void* d_xq[2] = {nullptr, nullptr};
+  void* d_xqa[2] = {nullptr, nullptr};
+  void* d_outv = nullptr;
+  void* d_part = nullptr;
+  void* d_store = nullptr;
+  double* d_tgrad = nullptr;
+  std::vector<int> grp_band;    // instance-local group -> band
+  bool stored = false;
+  int fwd_parity = 0;           // parity of the converged forward state
+};
+
+}  // namespace
+
+struct bte_ctx {
+  int precision = BTE_PREC_FP64;
+  double T_ref = 300.0;
+  int dim = 0, B = 0;
+  std::vector<double> v, tau, C;
+  std::vector<Ordinate> ords;
+  double t0 = 1e-12;
+  Plan plan;
+  bool plan_set = false;
+  std::vector<Inst> inst;
+  bool has_diffuse = false;
+  int n_cu = 256;
+  DevPool pool;                        // plan-independent
+  std::unique_ptr<DevPool> ppool;      // plan-dependent
+  // shared device arrays (plan-dependent)
+  InstDev* d_inst_f = nullptr;
+  InstDev* d_inst_a = nullptr;
+  JobDev* d_jobs_f = nullptr;
+  JobDev* d_jobs_a = nullptr;
+  int n_jobs = 0;
+  int4* d_gi_f = nullptr;
+  int4* d_gi_a = nullptr;
+  void* d_gt_f = nullptr;
+  void* d_gt_a = nullptr;
+  void* d_zg = nullptr;
+  long long zg_stride = 0;
+  int* d_counters = nullptr;
+  FinInst* d_fin_f = nullptr;
+  FinInst* d_fin_a = nullptr;
+  int2* d_fblocks = nullptr;
+  int* d_nblocks = nullptr;
+  int n_fblocks = 0;
+  StatusDev* d_st_f = nullptr;
+  StatusDev* d_st_a = nullptr;
+  StatusDev* h_st = nullptr;           // pinned
+  SweepArgs sa{};
+  size_t lds = 0;
+  int block = 64, grid = 1;
+  int nacc_max = 1;
+  hipStream_t cap_stream = nullptr;
+  std::map<long long, hipGraphExec_t> graphs;
+  std::map<long long, hipGraph_t> graph_src;
+  std::vector<FinInst> fin_f, fin_a;   // host copies
+};
+
+namespace {
+
+size_t elem(int prec) { return prec == BTE_PREC_FP32 ? 4 : 8; }
+
+void clear_graphs(bte_ctx* h) {
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : h->graph_src) (void)hipGraphDestroy(kv.second);
+  h->graphs.clear();
+  h->graph_src.clear();
+}
+
+std::vector<char> to_prec(const std::vector<double>& x, int prec) {
+  std::vector<char> out(x.size() * elem(prec));
+  if (prec == BTE_PREC_FP32) {
+    float* f = reinterpret_cast<float*>(out.data());
+    for (size_t i = 0; i < x.size(); ++i) f[i] = (float)x[i];
+  } else {
+    memcpy(out.data(), x.data(), x.size() * 8);
+  }
+  return out;
+}
+
+double total_D(const bte_ctx* h) {
+  double D = 0.0;
+  for (int b = 0; b < h->B; ++b) D += h->C[b] / h->tau[b];
+  return D;
+}
+
+// (Re)build everything that depends on the plan or on tau.
+bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
+  Plan pl = pl_in;
+  if (h->dim == 3) pl.R = 1;
+  if (pl.G != 1 && pl.G != 2 && pl.G != 4) {
+    set_err("plan G must be 1, 2 or 4");
+    return BTE_ERR_INVALID;
+  }
+  if (pl.R < 1 || pl.P < 1 || pl.R * pl.P > 8) {
+    set_err("plan needs R >= 1, P >= 1, R*P <= 8");
+    return BTE_ERR_INVALID;
+  }
+  if (pl.C < 8 || pl.C > 64 || pl.C % 8 || pl.C % pl.P) {
+    set_err("plan C must be a multiple of 8 in 8..64 and of P");
+    return BTE_ERR_INVALID;
+  }
+  clear_graphs(h);
+  h->ppool.reset(new DevPool());
+  DevPool& pp = *h->ppool;
+  const int prec = h->precision;
+  const size_t es = elem(prec);
+  const GroupSet gs = build_groups(h->ords, h->B, h->dim, pl.G, pl.P);
+  const int n_grp_inst = (int)gs.band.size();
+  const int n_bund = (int)gs.bundle_first.size();
+  const int n_oct = 1 << h->dim;
+  std::vector<InstDev> idf(h->inst.size()), ida(h->inst.size());
+  std::vector<JobDev> jf, ja;
+  std::vector<int4> gif, gia;
+  std::vector<double> gtf, gta;
+  int W_max = 1, e_max = 1, o_max = 1;
+  int grp_tot = 0;
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    std::string err;
+    if (!build_schedule(I.hi, pl, I.sch, err)) {
+      set_err("%s", err.c_str());
+      return BTE_ERR_INVALID;
+    }
+    const Schedule& S = I.sch;
+    W_max = std::max(W_max, S.W);
+    e_max = std::max(e_max, S.e_max);
+    o_max = std::max(o_max, S.o_max);
+    I.grp0 = grp_tot;
+    I.n_grp = n_grp_inst;
+    I.n_jobs = n_bund;
+    I.grp_band = gs.band;
+    grp_tot += n_grp_inst;
+    // group tables
+    std::vector<double> cf, ca;
+    group_coefficients(gs, h->ords, I.hi, h->v, h->tau, h->C, h->t0, false, cf);
+    group_coefficients(gs, h->ords, I.hi, h->v, h->tau, h->C, h->t0, true, ca);
+    gtf.insert(gtf.end(), cf.begin(), cf.end());
+    gta.insert(gta.end(), ca.begin(), ca.end());
+    for (int g = 0; g < n_grp_inst; ++g) {
+      gif.push_back(make_int4(gs.band[g], gs.oct[g], g, 0));
+      gia.push_back(make_int4(gs.band[g], gs.oct[g] ^ (n_oct - 1), g, 0));
+    }
+    // device arrays of the schedule
+    HIPCHK(pp.upload(&I.d_sched, S.sched));
+    HIPCHK(pp.upload(&I.d_pos, S.pos));
+    HIPCHK(pp.upload(&I.d_in_slot, S.in_slot));
+    HIPCHK(pp.upload(&I.d_in_chunk, S.in_chunk));
+    HIPCHK(pp.upload(&I.d_out_base, S.out_base));
+    HIPCHK(pp.upload(&I.d_pre_slot, S.pre_slot));
+    HIPCHK(pp.upload(&I.d_ofk, S.ofk));
+    std::vector<int2> gob(n_oct * h->B);
+    for (int i = 0; i < n_oct * h->B; ++i) gob[i] = make_int2(gs.ob_first[i], gs.ob_count[i]);
+    HIPCHK(pp.upload(&I.d_grp_ob, gob));
+    const size_t nposb = (size_t)S.pos_per_oct * S.n_oct * 2 * es;
+    for (int b = 0; b < 2; ++b) {
+      char* p1;
+      char* p2;
+      HIPCHK(pp.alloc(&p1, nposb));
+      HIPCHK(pp.alloc(&p2, nposb));
+      HIPCHK(hipMemset(p1, 0, nposb));
+      HIPCHK(hipMemset(p2, 0, nposb));
+      I.d_xq[b] = p1;
+      I.d_xqa[b] = p2;
+    }
+    char* ov;
+    HIPCHK(pp.alloc(&ov, (size_t)n_grp_inst * S.n_out_stride * es));
+    I.d_outv = ov;
+    char* pt;
+    HIPCHK(pp.alloc(&pt, (size_t)kNAcc * n_bund * I.hi.ncell * es));
+    I.d_part = pt;
+    I.d_store = nullptr;
+    I.stored = false;
+    HIPCHK(pp.alloc(&I.d_tgrad, (size_t)n_grp_inst * 2));
+    // descriptors
+    for (int adj = 0; adj < 2; ++adj) {
+      InstDev& d = adj ? ida[k] : idf[k];
+      memset(&d, 0, sizeof(d));
+      d.dim = I.hi.dim;
+      d.nx = I.hi.n[0];
+      d.ny = I.hi.n[1];
+      d.nz = I.hi.n[2];
+      d.ncell = I.hi.ncell;
+      d.n_bface = (int)I.hi.bf_cell.size();
+      d.n_jobs = n_bund;
+      d.n_grp = n_grp_inst;
+      d.T = S.T;
+      d.n_oct = S.n_oct;
+      d.W = S.W;
+      d.e_max = S.e_max;
+      d.o_max = S.o_max;
+      d.pos_per_oct = S.pos_per_oct;
+      d.sched = I.d_sched;
+      d.pos = I.d_pos;
+      d.in_slot = I.d_in_slot;
+      d.in_chunk = I.d_in_chunk;
+      d.out_base = I.d_out_base;
+      d.pre_slot = I.d_pre_slot;
+      d.xq[0] = adj ? I.d_xqa[0] : I.d_xq[0];
+      d.xq[1] = adj ? I.d_xqa[1] : I.d_xq[1];
+      d.xf = I.d_xq[0];
+      d.ubf = adj ? I.d_ubf0 : I.d_ubf;
+      d.outv = I.d_outv;
+      d.part = I.d_part;
+      d.store_u = nullptr;
+      d.tgrad = I.d_tgrad;
+      d.status = reinterpret_cast<int*>((adj ? h->d_st_a : h->d_st_f) + k);
+      d.lag = S.lag;
+      d.ring = S.ring;
+      d.n_out_stride = S.n_out_stride;
+    }
+    for (int b = 0; b < n_bund; ++b) {
+      const int o = gs.bundle_oct[b];
+      jf.push_back(JobDev{(int)k, I.grp0 + gs.bundle_first[b], b, o});
+      ja.push_back(JobDev{(int)k, I.grp0 + gs.bundle_first[b], b, o ^ (n_oct - 1)});
+    }
+  }
+  // larger instances first (the queue hands out jobs in order)
+  auto work = [&](const JobDev& j) { return (long long)h->inst[j.inst].sch.T * h->inst[j.inst].sch.R; };
+  std::stable_sort(jf.begin(), jf.end(), [&](const JobDev& a, const JobDev& b) { return work(a) > work(b); });
+  std::stable_sort(ja.begin(), ja.end(), [&](const JobDev& a, const JobDev& b) { return work(a) > work(b); });
+  h->n_jobs = (int)jf.size();
+  HIPCHK(pp.upload(&h->d_inst_f, idf));
+  HIPCHK(pp.upload(&h->d_inst_a, ida));
+  HIPCHK(pp.upload(&h->d_jobs_f, jf));
+  HIPCHK(pp.upload(&h->d_jobs_a, ja));
+  HIPCHK(pp.upload(&h->d_gi_f, gif));
+  HIPCHK(pp.upload(&h->d_gi_a, gia));
+  {
+    std::vector<char> a = to_prec(gtf, prec), b = to_prec(gta, prec);
+    char* pa;
+    char* pb;
+    HIPCHK(pp.upload(&pa, a));
+    HIPCHK(pp.upload(&pb, b));
+    h->d_gt_f = pa;
+    h->d_gt_a = pb;
+  }
+  // LDS carve-up
+  const bool L3 = h->dim == 3;
+  const int R = L3 ? 1 : pl.R, P = pl.P, G = pl.G, Cc = pl.C;
+  h->nacc_max = std::max(1 + h->dim, 2);
+  auto al = [](size_t x) { return (x + 15) / 16 * 16; };
+  size_t off = 0;
+  SweepArgs& sa = h->sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.lds_zring = (int)off;
+  off += al(L3 ? 0 : (size_t)P * R * W_max * G * es);
+  sa.lds_yring = (int)off;
+  off += al(L3 ? (size_t)P * 8 * W_max * G * es : 0);
+  sa.lds_xb = (int)off;
+  off += al(L3 ? (size_t)P * 72 * G * es : 0);
+  sa.lds_stage = (int)off;
+  off += al((size_t)P * R * h->nacc_max * Cc * 65 * es);
+  sa.lds_cid = (int)off;
+  off += al((size_t)R * Cc * 65 * 4);
+  sa.lds_in = (int)off;
+  off += al((size_t)P * R * 2 * e_max * es);
+  sa.lds_out = (int)off;
+  off += al((size_t)P * R * o_max * es);
+  sa.lds_total = (int)off;
+  if (off > 160 * 1024 - 64) {
+    set_err("plan needs %zu bytes of LDS (limit 160 KiB): reduce P, R, C or G", off);
+    return BTE_ERR_INVALID;
+  }
+  h->lds = off;
+  sa.inst = h->d_inst_f;
+  sa.jobs = h->d_jobs_f;
+  sa.n_jobs = h->n_jobs;
+  sa.counters = h->d_counters;
+  sa.grp_i = h->d_gi_f;
+  sa.grp_t = h->d_gt_f;
+  sa.B = h->B;
+  sa.R = R;
+  sa.P = P;
+  sa.C = Cc;
+  sa.zring_len = W_max;
+  sa.W_max = W_max;
+  sa.e_max = e_max;
+  sa.o_max = o_max;
+  h->block = R * P * 64;
+  int bpc = sweep_blocks_per_cu(prec, L3, G, 1, SWEEP_PLAIN, h->block, h->lds);
+  if (bpc < 1) bpc = 1;
+  h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
+  if (L3) {
+    int ring = 1;
+    for (auto& I : h->inst) ring = std::max(ring, I.sch.ring);
+    h->zg_stride = (long long)ring * 8 * G;
+    char* zg;
+    const size_t zb = (size_t)h->grid * P * h->zg_stride * es;
+    HIPCHK(pp.alloc(&zg, zb));
+    HIPCHK(hipMemset(zg, 0, zb));
+    h->d_zg = zg;
+    sa.zg = zg;
+    sa.zg_stride = h->zg_stride;
+  }
+  h->plan = pl;
+  h->plan.R = R;
+  return BTE_OK;
+}
+
+// Plan-independent per-instance device data.
+bte_status build_static(bte_ctx* h) {
+  DevPool& pp = h->pool;
+  const int prec = h->precision;
+  const size_t es = elem(prec);
+  const int n = (int)h->inst.size();
+  HIPCHK(pp.alloc(&h->d_st_f, n));
+  HIPCHK(pp.alloc(&h->d_st_a, n));
+  HIPCHK(hipMemset(h->d_st_f, 0, n * sizeof(StatusDev)));
+  HIPCHK(hipMemset(h->d_st_a, 0, n * sizeof(StatusDev)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->h_st), sizeof(StatusDev) * 2 * n, hipHostMallocDefault));
+  HIPCHK(pp.alloc(&h->d_counters, 4));
+  HIPCHK(hipMemset(h->d_counters, 0, 16));
+  std::vector<int2> fb;
+  std::vector<int> nbi;
+  h->fin_f.resize(n);
+  h->fin_a.resize(n);
+  for (int k = 0; k < n; ++k) {
+    Inst& I = h->inst[k];
+    const HostInst& hi = I.hi;
+    HIPCHK(pp.upload(&I.d_active, std::vector<unsigned char>(hi.active.begin(), hi.active.end())));
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(pp.alloc(&I.d_X[b], hi.ncell));
+      HIPCHK(pp.alloc(&I.d_Xa[b], hi.ncell));
+    }
+    HIPCHK(pp.alloc(&I.d_qmag, hi.ncell));
+    HIPCHK(pp.alloc(&I.d_qbuf, (size_t)hi.ncell * hi.dim));
+    HIPCHK(pp.alloc(&I.d_dqbuf, hi.ncell));
+    I.n_fblocks = (hi.ncell + 255) / 256;
+    HIPCHK(pp.alloc(&I.d_blockpart, (size_t)I.n_fblocks * 4));
+    for (int b = 0; b < I.n_fblocks; ++b) fb.push_back(make_int2(k, b));
+    nbi.push_back(I.n_fblocks);
+    HIPCHK(pp.upload(&I.d_bf_bc, hi.bf_bc));
+    HIPCHK(pp.upload(&I.d_bf_cell, hi.bf_cell));
+    HIPCHK(pp.upload(&I.d_bc_kind, hi.bc_kind));
+    HIPCHK(pp.upload(&I.d_bc_T, hi.bc_T));
+    HIPCHK(pp.upload(&I.d_dface, hi.dface));
+    std::vector<double> ih(hi.dface.size());
+    for (size_t i = 0; i < hi.dface.size(); ++i) {
+      const int f = hi.bf_face[hi.dface[i]];
+      ih[i] = 1.0 / half_range(h->ords, f / 2);
+    }
+    HIPCHK(pp.upload(&I.d_inv_half, ih));
+    const size_t nu = (size_t)h->B * std::max<size_t>(hi.bf_cell.size(), 1);
+    char* u1;
+    char* u0;
+    HIPCHK(pp.alloc(&u1, nu * es));
+    HIPCHK(pp.alloc(&u0, nu * es));
+    HIPCHK(hipMemset(u1, 0, nu * es));
+    HIPCHK(hipMemset(u0, 0, nu * es));
+    I.d_ubf = u1;
+    I.d_ubf0 = u0;
+    if (!hi.dface.empty()) h->has_diffuse = true;
+    FinInst& ff = h->fin_f[k];
+    ff.X[0] = I.d_X[0];
+    ff.X[1] = I.d_X[1];
+    ff.g = nullptr;
+    ff.q = I.d_qbuf;
+    ff.qmag_prev = I.d_qmag;
+    ff.blockpart = I.d_blockpart;
+    ff.active = I.d_active;
+    FinInst& fa = h->fin_a[k];
+    fa = ff;
+    fa.X[0] = I.d_Xa[0];
+    fa.X[1] = I.d_Xa[1];
+    fa.q = I.d_dqbuf;
+  }
+  h->n_fblocks = (int)fb.size();
+  HIPCHK(pp.upload(&h->d_fblocks, fb));
+  HIPCHK(pp.upload(&h->d_nblocks, nbi));
+  HIPCHK(pp.upload(&h->d_fin_f, h->fin_f));
+  HIPCHK(pp.upload(&h->d_fin_a, h->fin_a));
+  HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  return BTE_OK;
+}
+
+bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
+                         const bte_quadrature* quad, double T_ref, int precision, bte_handle* out) {
+  if (!out) {
+    set_err("null output handle");
+    return BTE_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (precision != BTE_PREC_FP32 && precision != BTE_PREC_FP64) {
+    set_err("precision must be BTE_PREC_FP32 or BTE_PREC_FP64");
+    return BTE_ERR_INVALID;
+  }
+  if (!std::isfinite(T_ref)) {
+    set_err("T_ref must be finite");
+    return BTE_ERR_INVALID;
+  }
+  if (n_inst < 1 || !geoms) {
+    set_err("need at least one geometry");
+    return BTE_ERR_INVALID;
+  }
+  for (int k = 0; k < n_inst; ++k) {
+    const std::string e = validate_problem(&geoms[k], bands, quad);
+    if (!e.empty()) {
+      set_err("instance %d: %s", k, e.c_str());
+      return BTE_ERR_INVALID;
+    }
+    if (geoms[k].dim != geoms[0].dim) {
+      set_err("all instances of a batch must have the same dimension");
+      return BTE_ERR_INVALID;
+    }
+  }
+  std::unique_ptr<bte_ctx> h(new bte_ctx());
+  h->precision = precision;
+  h->T_ref = T_ref;
+  h->dim = geoms[0].dim;
+  h->B = bands->n_bands;
+  h->v.assign(bands->h_v, bands->h_v + h->B);
+  h->tau.assign(bands->h_tau, bands->h_tau + h->B);
+  h->C.assign(bands->h_C, bands->h_C + h->B);
+  h->t0 = *std::min_element(h->tau.begin(), h->tau.end());
+  h->ords = fold_ordinates(quad, h->dim);
+  h->inst.resize(n_inst);
+  for (int k = 0; k < n_inst; ++k) build_instance(&geoms[k], h->inst[k].hi);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  h->n_cu = std::max(1, prop.multiProcessorCount);
+  bte_status s = build_static(h.get());
+  if (s != BTE_OK) return s;
+  Plan pl;
+  if (h->dim == 3) {
+    pl.G = 2;
+    pl.R = 1;
+    pl.P = 4;
+    pl.C = 16;
+  } else if (h->dim == 1) {
+    pl.G = 1;
+    pl.R = 1;
+    pl.P = 1;
+    pl.C = 16;
+  } else {
+    pl.G = precision == BTE_PREC_FP32 ? 4 : 2;
+    pl.R = std::min(8, std::max(1, (h->inst[0].hi.n[1] + 63) / 64));
+    pl.P = 1;
+    pl.C = 16;
+  }
+  s = build_plan(h.get(), pl);
+  if (s != BTE_OK) return s;
+  *out = h.release();
+  return BTE_OK;
+}
+
+// ---------------------------------------------------------------- the loop
+struct LoopCfg {
+  bool adj;
+  int nacc_q;  // accumulator planes in flux iterations
+};
+
+bte_status enqueue_sweep(bte_ctx* h, bool adj, int nacc, int mode, int force, hipStream_t st) {
+  SweepArgs a = h->sa;
+  a.inst = adj ? h->d_inst_a : h->d_inst_f;
+  a.jobs = adj ? h->d_jobs_a : h->d_jobs_f;
+  a.grp_i = adj ? h->d_gi_a : h->d_gi_f;
+  a.grp_t = adj ? h->d_gt_a : h->d_gt_f;
+  a.force = force;
+  HIPCHK(launch_sweep(h->precision, h->dim == 3, h->plan.G, nacc, mode, a, h->grid, h->block, h->lds, st));
+  return BTE_OK;
+}
+
+bte_status enqueue_finalize(bte_ctx* h, bool adj, int flags, const bte_opts& o, hipStream_t st) {
+  FinArgs f;
+  f.inst = adj ? h->d_inst_a : h->d_inst_f;
+  f.blocks = h->d_fblocks;
+  f.n_blocks_total = h->n_fblocks;
+  f.n_blocks_inst = h->d_nblocks;
+  f.flags = flags | (adj ? FIN_ADJ : 0);
+  f.tol_T = o.tol_T;
+  f.tol_q = adj ? 1.0 : o.tol_q;
+  HIPCHK(launch_finalize(h->precision, f, adj ? h->d_fin_a : h->d_fin_f, st));
+  return BTE_OK;
+}
+
+bte_status enqueue_walls(bte_ctx* h, hipStream_t st) {
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    if (I.hi.dface.empty()) continue;
+    WallArgs w;
+    w.inst = h->d_inst_f;
+    w.inst_id = (int)k;
+    w.n_dface = (int)I.hi.dface.size();
+    w.dface_slot = I.d_dface;
+    w.inv_half = I.d_inv_half;
+    w.ofk = I.d_ofk;
+    w.grp_ob = I.d_grp_ob;
+    w.B = h->B;
+    HIPCHK(launch_wall_update(h->precision, w, st));
+  }
+  return BTE_OK;
+}
+
+// n iterations; the last one checks convergence, the last two carry the flux.
+bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStream_t st) {
+  const int nq = 1 + h->dim;
+  for (int k = 0; k < n; ++k) {
+    const bool last = k == n - 1, second = k == n - 2;
+    const bool qit = !adj && (last || second);
+    bte_status s = enqueue_sweep(h, adj, qit ? nq : 1, SWEEP_PLAIN, 0, st);
+    if (s != BTE_OK) return s;
+    int fl = 0;
+    if (qit) fl |= FIN_Q;
+    if (last) fl |= FIN_CHECK | FIN_QPREV;
+    s = enqueue_finalize(h, adj, fl, o, st);
+    if (s != BTE_OK) return s;
+    if (!adj && h->has_diffuse) {
+      s = enqueue_walls(h, st);
+      if (s != BTE_OK) return s;
+    }
+  }
+  return BTE_OK;
+}
+
+bte_status launch_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStream_t st) {
+  if (!o.use_graph) return enqueue_chunk(h, adj, n, o, st);
+  const long long key = ((long long)adj << 40) | ((long long)n << 8) |
+                        (o.tol_T > 0 ? 1 : 0) | ((o.tol_q > 0 ? 1 : 0) << 1);
+  // tolerances are graph-captured kernel arguments: include their bits in the key
+  long long key2 = key ^ (long long)std::hash<double>()(o.tol_T) ^ ((long long)std::hash<double>()(o.tol_q) << 1);
+  auto it = h->graphs.find(key2);
+  if (it == h->graphs.end()) {
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    bte_status s = enqueue_chunk(h, adj, n, o, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (s != BTE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    HIPCHK(e);
+    hipGraphExec_t ex = nullptr;
+    HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    h->graphs[key2] = ex;
+    h->graph_src[key2] = g;
+    it = h->graphs.find(key2);
+  }
+  HIPCHK(hipGraphLaunch(it->second, st));
+  return BTE_OK;
+}
+
+bte_status read_status(bte_ctx* h, bool adj, hipStream_t st) {
+  const size_t n = h->inst.size();
+  HIPCHK(hipMemcpyAsync(h->h_st, adj ? h->d_st_a : h->d_st_f, n * sizeof(StatusDev),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return BTE_OK;
+}
+
+// Iterate until every instance is done or max_iters iterations ran.
+bte_status run_loop(bte_ctx* h, bool adj, const bte_opts& o, hipStream_t st, double* secs) {
+  const int K = o.check_every > 0 ? o.check_every : 8;
+  const auto t0 = std::chrono::steady_clock::now();
+  int it = 0;
+  while (it < o.max_iters) {
+    const int n = std::min(K, o.max_iters - it);
+    bte_status s = launch_chunk(h, adj, n, o, st);
+    if (s != BTE_OK) return s;
+    it += n;
+    s = read_status(h, adj, st);
+    if (s != BTE_OK) return s;
+    bool all_done = true;
+    for (size_t k = 0; k < h->inst.size(); ++k) all_done = all_done && h->h_st[k].done;
+    if (all_done) break;
+  }
+  *secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return BTE_OK;
+}
+
+bte_status check_opts(const bte_opts* o) {
+  if (!o) {
+    set_err("null options");
+    return BTE_ERR_INVALID;
+  }
+  if (o->max_iters < 1) {
+    set_err("max_iters must be >= 1");
+    return BTE_ERR_INVALID;
+  }
+  if (o->check_every < 0) {
+    set_err("check_every must be >= 0");
+    return BTE_ERR_INVALID;
+  }
+  return BTE_OK;
+}
+
+bte_status fill_report(bte_ctx* h, size_t k, double secs, bte_report* rep, bool adj, const bte_opts& o) {
+  const StatusDev& s = h->h_st[k];
+  bte_status st = BTE_OK;
+  if (s.nonfinite) st = BTE_ERR_NONFINITE;
+  else if (!s.done) st = BTE_ERR_NOT_CONVERGED;
+  (void)o;
+  (void)adj;
+  if (rep) {
+    rep->iters = s.iter;
+    rep->eps_T = s.eps_T;
+    rep->eps_q = s.eps_q;
+    rep->seconds = secs;
+    rep->status = st;
+  }
+  return st;
+}
+
+bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d_T_init, hipStream_t st) {
+  Inst& I = h->inst[k];
+  InitArgs a;
+  a.inst = h->d_inst_f;
+  a.inst_id = (int)k;
+  a.X0 = d_T_init;
+  a.T_ref = h->T_ref;
+  a.Q = d_Q;
+  a.active = I.d_active;
+  a.X[0] = I.d_X[0];
+  a.X[1] = I.d_X[1];
+  a.adjoint = 0;
+  HIPCHK(launch_init_state(h->precision, a, I.hi.ncell, st));
+  HIPCHK(launch_zero(I.d_qmag, (size_t)I.hi.ncell * 8, st));
+  UbfInitArgs u;
+  u.ubf = I.d_ubf;
+  u.n_bface = (int)I.hi.bf_cell.size();
+  u.B = h->B;
+  u.bf_bc = I.d_bf_bc;
+  u.bf_cell = I.d_bf_cell;
+  u.bc_kind = I.d_bc_kind;
+  u.bc_T = I.d_bc_T;
+  u.T_init = d_T_init;
+  u.T_ref = h->T_ref;
+  u.zero = 0;
+  HIPCHK(launch_ubf_init(h->precision, u, st));
+  HIPCHK(launch_status_reset(h->d_st_f + k, (double)I.hi.n_active, st));
+  I.stored = false;
+  return BTE_OK;
+}
+
+bte_status store_state(bte_ctx* h, hipStream_t st) {
+  // one more forward sweep from the converged state that writes u per ordinate
+  const size_t es = elem(h->precision);
+  std::vector<InstDev> idf(h->inst.size());
+  HIPCHK(hipMemcpy(idf.data(), h->d_inst_f, idf.size() * sizeof(InstDev), hipMemcpyDeviceToHost));
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    if (!I.d_store) {
+      char* p;
+      HIPCHK(h->ppool->alloc(&p, (size_t)I.n_grp * I.hi.ncell * h->plan.G * es));
+      I.d_store = p;
+    }
+    idf[k].store_u = I.d_store;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_inst_f, idf.data(), idf.size() * sizeof(InstDev), hipMemcpyHostToDevice, st));
+  bte_status s = enqueue_sweep(h, false, 1, SWEEP_STORE, 1, st);
+  if (s != BTE_OK) return s;
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    h->inst[k].stored = true;
+    h->inst[k].fwd_parity = h->h_st[k].iter & 1;
+  }
+  return BTE_OK;
+}
+
+bte_status default_opts(const bte_opts* o, bte_opts& out) {
+  bte_status s = check_opts(o);
+  if (s != BTE_OK) return s;
+  out = *o;
+  if (out.check_every == 0) out.check_every = 8;
+  return BTE_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* bte_version(void) { return "bte-mi355x 0.1"; }
+
+const char* bte_last_error(void) { return g_err.c_str(); }
+
+bte_status bte_validate(const bte_geometry* geom, const bte_bands* bands, const bte_quadrature* quad) {
+  const std::string e = validate_problem(geom, bands, quad);
+  if (!e.empty()) {
+    set_err("%s", e.c_str());
+    return BTE_ERR_INVALID;
+  }
+  return BTE_OK;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
+// Legendre three-term recurrence.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  if (n == 1) {
+    x[0] = 0.0;
+    w[0] = 2.0;
+  }
+}
+
+bte_status bte_quadrature_gl_mu(int n_mu, double* h_s, double* h_w) {
+  if (n_mu < 1 || !h_s || !h_w) {
+    set_err("n_mu >= 1 and output arrays required");
+    return BTE_ERR_INVALID;
+  }
+  std::vector<double> x, w;
+  gauss_legendre(n_mu, x, w);
+  for (int a = 0; a < n_mu; ++a) {
+    h_s[3 * a] = x[a];
+    h_s[3 * a + 1] = std::sqrt(std::max(0.0, 1.0 - x[a] * x[a]));
+    h_s[3 * a + 2] = 0.0;
+    h_w[a] = 2.0 * kPi * w[a];
+  }
+  return BTE_OK;
+}
+
+bte_status bte_quadrature_octant_gl(int n_theta, int n_phi, int polar_axis, double* h_s, double* h_w) {
+  if (n_theta < 1 || n_phi < 1 || polar_axis < 0 || polar_axis > 2 || !h_s || !h_w) {
+    set_err("n_theta, n_phi >= 1, polar_axis in 0..2 and output arrays required");
+    return BTE_ERR_INVALID;
+  }
+  std::vector<double> xt, gt, xp, gp;
+  gauss_legendre(n_theta, xt, gt);
+  gauss_legendre(n_phi, xp, gp);
+  int a = 0;
+  double tot = 0.0;
+  for (int sx = 0; sx < 2; ++sx)
+    for (int sy = 0; sy < 2; ++sy)
+      for (int sz = 0; sz < 2; ++sz)
+        for (int it = 0; it < n_theta; ++it)
+          for (int ip = 0; ip < n_phi; ++ip) {
+            const double t = (xt[it] + 1.0) * kPi / 4.0, p = (xp[ip] + 1.0) * kPi / 4.0;
+            const double c = std::cos(t), sc = std::sin(t) * std::cos(p), ss = std::sin(t) * std::sin(p);
+            double v[3];
+            if (polar_axis == 0) { v[0] = c; v[1] = sc; v[2] = ss; }
+            else if (polar_axis == 2) { v[0] = sc; v[1] = ss; v[2] = c; }
+            else { v[0] = ss; v[1] = c; v[2] = sc; }
+            v[0] *= sx ? -1.0 : 1.0;
+            v[1] *= sy ? -1.0 : 1.0;
+            v[2] *= sz ? -1.0 : 1.0;
+            const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int d = 0; d < 3; ++d) h_s[3 * a + d] = v[d] / nn;
+            h_w[a] = gt[it] * kPi / 4.0 * gp[ip] * kPi / 4.0 * std::sin(t);
+            tot += h_w[a];
+            ++a;
+          }
+  for (int k = 0; k < a; ++k) h_w[k] *= 4.0 * kPi / tot;
+  return BTE_OK;
+}
+
+bte_status bte_create(const bte_geometry* geom, const bte_bands* bands, const bte_quadrature* quad,
+                      double T_ref, int precision, bte_handle* out) {
+  return create_common(1, geom, bands, quad, T_ref, precision, out);
+}
+
+bte_status bte_batch_create(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
+                            const bte_quadrature* quad, double T_ref, int precision, bte_handle* out) {
+  return create_common(n_inst, geoms, bands, quad, T_ref, precision, out);
+}
+
+bte_status bte_set_tau(bte_handle h, const double* h_tau) {
+  if (!h || !h_tau) {
+    set_err("null handle or tau");
+    return BTE_ERR_INVALID;
+  }
+  for (int b = 0; b < h->B; ++b)
+    if (!(h_tau[b] > 0 && std::isfinite(h_tau[b]))) {
+      set_err("tau[%d] must be > 0", b);
+      return BTE_ERR_INVALID;
+    }
+  h->tau.assign(h_tau, h_tau + h->B);
+  return build_plan(h, h->plan);
+}
+
+bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
+  if (!h || !plan) {
+    set_err("null handle or plan");
+    return BTE_ERR_INVALID;
+  }
+  Plan p = h->plan;
+  if (plan->G) p.G = plan->G;
+  if (plan->R) p.R = plan->R;
+  if (plan->P) p.P = plan->P;
+  if (plan->C) p.C = plan->C;
+  const Plan old = h->plan;
+  bte_status s = build_plan(h, p);
+  if (s != BTE_OK) {
+    const std::string e = g_err;
+    (void)build_plan(h, old);
+    g_err = e;
+  }
+  return s;
+}
+
+bte_status bte_get_plan(bte_handle h, bte_plan* plan) {
+  if (!h || !plan) {
+    set_err("null handle or plan");
+    return BTE_ERR_INVALID;
+  }
+  plan->G = h->plan.G;
+  plan->R = h->plan.R;
+  plan->P = h->plan.P;
+  plan->C = h->plan.C;
+  return BTE_OK;
+}
+
+bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, double* d_T, double* d_q,
+                     const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+  if (!h || !d_T) {
+    set_err("null handle or output");
+    return BTE_ERR_INVALID;
+  }
+  if (h->inst.size() != 1) {
+    set_err("bte_solve needs a single-instance handle (use bte_batch_solve)");
+    return BTE_ERR_STATE;
+  }
+  bte_opts o;
+  bte_status s = default_opts(opts, o);
+  if (s != BTE_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  Inst& I = h->inst[0];
+  h->fin_f[0].q = d_q ? d_q : I.d_qbuf;
+  HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), sizeof(FinInst), hipMemcpyHostToDevice, st));
+  s = init_forward(h, 0, d_Q, d_T_init, st);
+  if (s != BTE_OK) return s;
+  double secs = 0.0;
+  s = run_loop(h, false, o, st, &secs);
+  if (s != BTE_OK) return s;
+  if (o.store_state) {
+    s = store_state(h, st);
+    if (s != BTE_OK) return s;
+  }
+  HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, h->T_ref, 1.0, d_T, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return fill_report(h, 0, secs, h_rep, false, o);
+}
+
+bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const* d_T, double* const* d_q,
+                           const bte_opts* opts, void* hip_stream, bte_report* h_reps) {
+  if (!h || !d_T || !d_Q) {
+    set_err("null handle or arrays");
+    return BTE_ERR_INVALID;
+  }
+  bte_opts o;
+  bte_status s = default_opts(opts, o);
+  if (s != BTE_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    if (!d_T[k]) {
+      set_err("null output of instance %zu", k);
+      return BTE_ERR_INVALID;
+    }
+    h->fin_f[k].q = (d_q && d_q[k]) ? d_q[k] : h->inst[k].d_qbuf;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), h->fin_f.size() * sizeof(FinInst),
+                        hipMemcpyHostToDevice, st));
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    s = init_forward(h, k, d_Q[k], nullptr, st);
+    if (s != BTE_OK) return s;
+  }
+  double secs = 0.0;
+  s = run_loop(h, false, o, st, &secs);
+  if (s != BTE_OK) return s;
+  if (o.store_state) {
+    s = store_state(h, st);
+    if (s != BTE_OK) return s;
+  }
+  bte_status worst = BTE_OK;
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    HIPCHK(launch_output(I.d_X[h->h_st[k].iter & 1], I.d_active, I.hi.ncell, h->T_ref, 1.0, d_T[k], st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    const bte_status r = fill_report(h, k, secs, h_reps ? h_reps + k : nullptr, false, o);
+    if (r != BTE_OK && (worst == BTE_OK || r == BTE_ERR_NONFINITE)) worst = r;
+  }
+  return worst;
+}
+
+static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, double* h_dJdtau,
+                                 double* const* d_dJdQ, const bte_opts* opts, void* hip_stream,
+                                 bte_report* h_reps) {
+  if (!h || !d_dJdT) {
+    set_err("null handle or dJ/dT");
+    return BTE_ERR_INVALID;
+  }
+  if (h->has_diffuse) {
+    set_err("the adjoint supports isothermal walls only");
+    return BTE_ERR_INVALID;
+  }
+  for (auto& I : h->inst)
+    if (!I.stored) {
+      set_err("bte_adjoint needs a previous solve with store_state = 1");
+      return BTE_ERR_STATE;
+    }
+  bte_opts o;
+  bte_status s = default_opts(opts, o);
+  if (s != BTE_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t n = h->inst.size();
+  // adjoint descriptors: forward state and stored field for the tau pass
+  std::vector<InstDev> ida(n);
+  HIPCHK(hipMemcpy(ida.data(), h->d_inst_a, n * sizeof(InstDev), hipMemcpyDeviceToHost));
+  for (size_t k = 0; k < n; ++k) {
+    Inst& I = h->inst[k];
+    ida[k].xf = I.d_xq[I.fwd_parity];
+    ida[k].store_u = I.d_store;
+    h->fin_a[k].g = d_dJdT[k];
+    h->fin_a[k].q = (d_dJdQ && d_dJdQ[k]) ? d_dJdQ[k] : I.d_dqbuf;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_inst_a, ida.data(), n * sizeof(InstDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_fin_a, h->fin_a.data(), n * sizeof(FinInst), hipMemcpyHostToDevice, st));
+  for (size_t k = 0; k < n; ++k) {
+    Inst& I = h->inst[k];
+    InitArgs a;
+    a.inst = h->d_inst_a;
+    a.inst_id = (int)k;
+    a.X0 = d_dJdT[k];
+    a.T_ref = 0.0;
+    a.Q = nullptr;
+    a.active = I.d_active;
+    a.X[0] = I.d_Xa[0];
+    a.X[1] = I.d_Xa[1];
+    a.adjoint = 1;
+    HIPCHK(launch_init_state(h->precision, a, I.hi.ncell, st));
+    HIPCHK(launch_status_reset(h->d_st_a + k, (double)I.hi.n_active, st));
+    HIPCHK(launch_zero(I.d_tgrad, (size_t)I.n_grp * 2 * 8, st));
+  }
+  double secs = 0.0;
+  s = run_loop(h, true, o, st, &secs);
+  if (s != BTE_OK) return s;
+  std::vector<int> conv(n);
+  for (size_t k = 0; k < n; ++k) conv[k] = h->h_st[k].done;
+  // final pass: reopen every instance, sweep with the tau sums and dJ/dQ
+  for (size_t k = 0; k < n; ++k) HIPCHK(launch_zero(&h->d_st_a[k].done, 4, st));
+  s = enqueue_sweep(h, true, 2, SWEEP_TAUGRAD, 0, st);
+  if (s != BTE_OK) return s;
+  s = enqueue_finalize(h, true, FIN_Q, o, st);
+  if (s != BTE_OK) return s;
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<StatusDev> sa(n);
+  HIPCHK(hipMemcpy(sa.data(), h->d_st_a, n * sizeof(StatusDev), hipMemcpyDeviceToHost));
+  const double D = total_D(h);
+  bte_status worst = BTE_OK;
+  for (size_t k = 0; k < n; ++k) {
+    Inst& I = h->inst[k];
+    const int nc = I.hi.ncell;
+    // lambda used by the final pass (before its own update) and the forward Delta T
+    std::vector<double> lam(nc), dT(nc), tg((size_t)I.n_grp * 2);
+    const int lp = (sa[k].iter - 1) & 1;
+    HIPCHK(hipMemcpy(lam.data(), I.d_Xa[lp], nc * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(dT.data(), I.d_X[I.fwd_parity], nc * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(tg.data(), I.d_tgrad, tg.size() * 8, hipMemcpyDeviceToHost));
+    double L = 0.0;
+    for (int c = 0; c < nc; ++c)
+      if (I.hi.active[c]) L += lam[c] * dT[c];
+    if (h_dJdtau) {
+      std::vector<double> T1(h->B, 0.0), T2(h->B, 0.0);
+      for (int g = 0; g < I.n_grp; ++g) {
+        T1[I.grp_band[g]] += tg[2 * g];
+        T2[I.grp_band[g]] += tg[2 * g + 1];
+      }
+      for (int b = 0; b < h->B; ++b) {
+        const double tb = h->tau[b];
+        h_dJdtau[k * h->B + b] = (1.0 / tb) * ((h->t0 / tb) * T1[b] - T2[b] + h->C[b] / (tb * D) * L);
+      }
+    }
+    h->h_st[k] = sa[k];
+    h->h_st[k].done = conv[k];
+    const bte_status r = fill_report(h, k, secs, h_reps ? h_reps + k : nullptr, true, o);
+    if (r != BTE_OK && (worst == BTE_OK || r == BTE_ERR_NONFINITE)) worst = r;
+  }
+  return worst;
+}
+
+bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, double* d_dJdQ,
+                       const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+  if (h && h->inst.size() != 1) {
+    set_err("bte_adjoint needs a single-instance handle (use bte_batch_adjoint)");
+    return BTE_ERR_STATE;
+  }
+  double* dq[1] = {d_dJdQ};
+  const double* g[1] = {d_dJdT};
+  return adjoint_common(h, d_dJdT ? g : nullptr, h_dJdtau, dq, opts, hip_stream, h_rep);
+}
+
+bte_status bte_batch_adjoint(bte_handle h, const double* const* d_dJdT, double* h_dJdtau,
+                             double* const* d_dJdQ, const bte_opts* opts, void* hip_stream,
+                             bte_report* h_reps) {
+  return adjoint_common(h, d_dJdT, h_dJdtau, d_dJdQ, opts, hip_stream, h_reps);
+}
+
+bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double* h_ms, double* h_updates) {
+  if (!h || n_launches < 1 || !h_ms) {
+    set_err("null handle/output or n_launches < 1");
+    return BTE_ERR_INVALID;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  bte_status s = enqueue_sweep(h, false, 1, SWEEP_PLAIN, 1, st);  // warm-up
+  if (s != BTE_OK) return s;
+  HIPCHK(hipEventRecord(e0, st));
+  for (int i = 0; i < n_launches && s == BTE_OK; ++i) s = enqueue_sweep(h, false, 1, SWEEP_PLAIN, 1, st);
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != BTE_OK) return s;
+  *h_ms = ms / n_launches;
+  if (h_updates) {
+    double u = 0.0;
+    for (auto& I : h->inst) u += (double)I.hi.n_active * h->ords.size() * h->B;
+    *h_updates = u;
+  }
+  return BTE_OK;
+}
+
+bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_stream, bte_plan* best) {
+  if (!h || n_iters < 1) {
+    set_err("null handle or n_iters < 1");
+    return BTE_ERR_INVALID;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<Plan> cand;
+  const int Gs[3] = {1, 2, 4};
+  const int Cs[2] = {16, 32};
+  if (h->dim == 3) {
+    for (int G : Gs)
+      for (int P : {1, 2, 4, 8})
+        for (int C : Cs) cand.push_back(Plan{G, 1, P, C});
+  } else {
+    const int nS = (h->inst[0].hi.n[1] + 63) / 64;
+    for (int G : Gs)
+      for (int R = 1; R <= std::min(8, nS); R *= 2)
+        for (int P : {1, 2, 4})
+          for (int C : Cs)
+            if (R * P <= 8) cand.push_back(Plan{G, R, P, C});
+  }
+  const Plan keep = h->plan;
+  double best_ms = 1e300;
+  Plan bestp = keep;
+  for (const Plan& p : cand) {
+    if (build_plan(h, p) != BTE_OK) continue;
+    bool ok = true;
+    for (size_t k = 0; k < h->inst.size() && ok; ++k)
+      ok = init_forward(h, k, d_Q, nullptr, st) == BTE_OK;
+    double ms = 0.0;
+    if (ok) ok = bte_time_sweep(h, n_iters, hip_stream, &ms, nullptr) == BTE_OK;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      bestp = h->plan;
+    }
+  }
+  bte_status s = build_plan(h, bestp);
+  if (s != BTE_OK) return s;
+  if (best) {
+    best->G = bestp.G;
+    best->R = bestp.R;
+    best->P = bestp.P;
+    best->C = bestp.C;
+  }
+  return BTE_OK;
+}
+
+bte_status bte_destroy(bte_handle h) {
+  if (!h) return BTE_OK;
+  clear_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->h_st) (void)hipHostFree(h->h_st);
+  delete h;
+  return BTE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Structures shared by the host runtime and the HIP kernels of the sweep library.
+//
+// Terminology used throughout the sources:
+//   octant    sign pattern of a direction along the grid axes (2^dim of them);
+//             every ordinate of an octant sweeps the grid in the same upwind order.
+//   group     G ordinates of one band and one octant, swept together by one wave
+//             (one ordinate per register slot of every lane).
+//   bundle    P groups of one octant swept in lockstep by the P waves of a
+//             workgroup; their band/direction partial sums are added per cell
+//             before they leave the workgroup.
+//   job       (instance, bundle): the unit of work a workgroup takes from the
+//             persistent queue.
+//   kernel axes (i, j, k): i is swept inside a lane (x); lanes form an LJ x LK
+//             block over (j, k) (2D/1D: LJ = 1, LK = 64 with k = y; 3D: LJ = 8,
+//             LK = 8 with j = y, k = z). A strip is a row of LK cells in k. In
+//             2D the R waves of a workgroup pipeline successive strips through an
+//             LDS ring; in 3D one wave streams every strip, its J-blocks of LJ
+//             cells in j and, inside a block, the cells in i ("virtual column"
+//             v = J*W + i), the link between strips going through a global ring.
+//   schedule  for each octant and each of the R wave slots, which cell lane l
+//             processes at clock step t (the "skewed" layout): position
+//             p = (slot*T + t)*64 + l. Every per-step input of the sweep is
+//             stored in this layout, so a wave's loads for one step are one
+//             contiguous 64-element read.
+//   variables the sweep works in temperature units: u = 4 pi e~ / C_b (K), with
+//             e~ the deviational energy, and in time units of t0. The swept
+//             quantity is f = u / inv with inv = 1/(t0/tau_b + sum_d t0 v_b |s_d|/h_d);
+//             f = S + sum_d a_d f_upwind,d, a_d = t0 v_b |s_d| / h_d * inv, and the
+//             source S = kS * X + cQ * Q (X = Delta T forward, lambda adjoint).
+#pragma once
+#include <stdint.h>
+
+namespace bte {
+
+constexpr int kWave = 64;
+constexpr int kMaxG = 8;
+constexpr int kNAcc = 4;  // partial-sum planes: [0] temperature, [1..dim] heat flux (or [1] dJ/dQ)
+
+// per-position flag bits of the schedule
+constexpr uint32_t F_ACTIVE = 1u << 0;
+constexpr uint32_t F_IN_X = 1u << 1;   // upwind face on axis x is a boundary: consume one inflow entry
+constexpr uint32_t F_IN_Y = 1u << 2;
+constexpr uint32_t F_IN_Z = 1u << 3;
+constexpr uint32_t F_OUT_X = 1u << 4;  // downwind face on axis x is a diffuse wall: emit one outflow entry
+constexpr uint32_t F_OUT_Y = 1u << 5;
+constexpr uint32_t F_OUT_Z = 1u << 6;
+// bits 7..22 of the flags: i index of the position's cell in sweep orientation
+constexpr int F_COL_SHIFT = 7;
+constexpr uint32_t F_COL_MASK = 0xFFFFu;
+
+// group coefficient record: GS(G) values of the sweep type, in this order
+//   kS, cQ, a[3][G], den[G], wacc[kNAcc][G], wo[3][G], wt[2][G], inv[G]
+__host__ __device__ constexpr int grp_stride(int G) { return 2 + G * (3 + 1 + kNAcc + 3 + 2 + 1); }
+__host__ __device__ constexpr int go_a(int G, int d) { return 2 + d * G; }
+__host__ __device__ constexpr int go_den(int G) { return 2 + 3 * G; }
+__host__ __device__ constexpr int go_wacc(int G, int a) { return 2 + 4 * G + a * G; }
+__host__ __device__ constexpr int go_wo(int G, int d) { return 2 + (4 + kNAcc) * G + d * G; }
+__host__ __device__ constexpr int go_wt(int G, int t) { return 2 + (7 + kNAcc) * G + t * G; }
+__host__ __device__ constexpr int go_inv(int G) { return 2 + (9 + kNAcc) * G; }
+
+// Per-instance descriptor (device memory). Pointers are device pointers.
+struct InstDev {
+  int dim, nx, ny, nz;
+  int ncell;        // bounding-box cells
+  int n_bface;      // boundary faces
+  int n_jobs;       // jobs of this instance
+  int n_grp;        // groups of this instance
+  int T;            // schedule clock steps (multiple of C)
+  int n_oct;        // 2^dim
+  int W;            // 2D: cells per strip row (nx); 3D: max pencil length
+  int e_max;        // max inflow entries of one wave slot in one chunk (all axes)
+  int o_max;        // max outflow entries of one wave slot in one chunk (all axes)
+  int band_dummy;   // unused padding
+  long long pos_per_oct;  // R*T*64
+  // schedule (per octant, R slots): cell index (-1 idle/inactive) and flags
+  const int2* sched;        // [n_oct][R][T][64] (cell, flags)
+  const int* pos;           // [n_oct][ncell] position of cell c in octant o's layout (-1 inactive)
+  // inflow stream: boundary-face slots in consumption order, per (octant, slot)
+  const int* in_slot;       // concatenated
+  const int* in_chunk;      // [n_oct][R][nchunks+1] start offset of each chunk (absolute into in_slot)
+  const int* out_base;      // [n_oct][R] start offset of the outflow stream (absolute)
+  const int* pre_slot;      // 2D: [n_oct][W] face slot of the strip-0 lane-0 upwind y face per column (-1)
+  // state in the skewed layout: (X, Q) pairs per position, sweep precision, ping-pong
+  void* xq[2];              // [n_oct][R*T*64] T2
+  const void* xf;           // tau-gradient pass: forward (Delta T, Q) pairs per position
+  const void* ubf;          // [B][n_bface] inflow u of every boundary face (K); zeros for the adjoint
+  void* outv;               // [n_grp][n_out_entries_of_octant] outflow stream values
+  void* part;               // [kNAcc][n_jobs][ncell] partial sums (sweep precision)
+  void* store_u;            // [n_grp][ncell][G] angular field u (forward, when stored)
+  double* tgrad;            // [n_grp][2] tau-gradient partial sums
+  int* status;              // StatusDev
+  int lag;                  // 3D: clock lag between a z-front write and its read
+  int ring;                 // 3D: global z-ring length in steps (power of two)
+  int n_out_stride;         // stride of one group's row of outv
+  int pad1;
+};
+
+// Job: instance, first group of the bundle (global index), instance-local job
+// index (row of the partial-sum buffer) and octant.
+struct JobDev {
+  int inst;
+  int grp;
+  int jl;
+  int oct;
+};
+
+// Per-instance status (device).
+struct StatusDev {
+  int iter;         // completed iterations
+  int done;         // 1: converged or stopped; kernels skip the instance
+  int nonfinite;    // 1: a non-finite value appeared
+  int ticket;       // block ticket for the finalize reduction
+  int checked;      // iteration index of the last residual check
+  int pad[3];
+  double eps_T, eps_q;
+  double lam_dT;    // sum_c lambda_c * DeltaT_c (adjoint)
+  double red[4];    // scratch
+};
+
+struct SweepArgs {
+  const InstDev* inst;
+  const JobDev* jobs;
+  int n_jobs;
+  int* counters;        // [2]: job ticket, exit ticket (self-resetting)
+  const int4* grp_i;    // [n_grp_total] (band, octant, instance-local group, 0)
+  const void* grp_t;    // [n_grp_total][grp_stride(G)]
+  int B;
+  int R, P, C;
+  int lds_zring;        // byte offsets into dynamic LDS
+  int lds_yring;
+  int lds_xb;
+  int lds_stage;
+  int lds_cid;
+  int lds_in;
+  int lds_out;
+  int lds_total;
+  int zring_len;        // entries per slot of the z-ring (2D: W_max columns; 3D: ring length)
+  int W_max;
+  int e_max, o_max;
+  int force;            // 1: sweep even instances marked done (timing / store passes)
+  void* zg;             // 3D: global z-rings, one per (workgroup, wave p)
+  long long zg_stride;  // elements per (workgroup, wave p)
+};
+
+
+// ---------------------------------------------------------------- aux kernels
+enum { FIN_Q = 1, FIN_CHECK = 2, FIN_ADJ = 4, FIN_QPREV = 8 };
+
+struct FinArgs {
+  const InstDev* inst;
+  const int2* blocks;        // [n_blocks_total] (instance, block index within the instance)
+  int n_blocks_total;
+  const int* n_blocks_inst;  // [n_inst]
+  int flags;                 // FIN_*
+  double tol_T, tol_q;
+};
+
+// Per-instance finalize pointers (device memory).
+struct FinInst {
+  double* X[2];              // master state (Delta T or lambda), [ncell], ping-pong
+  const double* g;           // adjoint right-hand side dJ/dT [ncell] (FIN_ADJ)
+  double* q;                 // [ncell*dim] heat flux output (forward) or dJ/dQ [ncell] (adjoint)
+  double* qmag_prev;         // [ncell] |q| of the previous flux iteration
+  double* blockpart;         // [n_blocks_inst][4]
+  const unsigned char* active;  // [ncell]
+};
+
+struct WallArgs {
+  const InstDev* inst;
+  int inst_id;
+  int n_dface;
+  const int* dface_slot;     // [n_dface] boundary-face slot of each diffuse face
+  const double* inv_half;    // [n_dface] 1 / sum_{in} w |s.n|
+  const int* ofk;            // [n_oct][n_bface] index of the face in octant o's out-stream, or -1
+  const int2* grp_ob;        // [n_oct][B] (first instance-local group, count)
+  int B;
+};
+
+struct InitArgs {
+  const InstDev* inst;
+  int inst_id;
+  const double* X0;          // [ncell] initial absolute temperature (forward) / dJ/dT (adjoint) / NULL
+  double T_ref;
+  const double* Q;           // [ncell] source (forward) or NULL
+  const unsigned char* active;
+  double* X[2];
+  int adjoint;
+};
+
+struct UbfInitArgs {
+  void* ubf;                 // [B][n_bface]
+  int n_bface, B;
+  const int* bf_bc;          // [n_bface]
+  const int* bf_cell;        // [n_bface]
+  const int* bc_kind;        // [n_bc]
+  const double* bc_T;        // [n_bc]
+  const double* T_init;      // [ncell] or NULL
+  double T_ref;
+  int zero;                  // 1: all zeros (adjoint)
+};
+
+}  // namespace bte

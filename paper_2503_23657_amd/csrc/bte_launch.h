@@ -1,0 +1,30 @@
+// Launch helpers exported by the kernel translation units to the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bte_device.h"
+
+namespace bte {
+
+
+// Sweep modes.
+enum { SWEEP_PLAIN = 0, SWEEP_STORE = 1, SWEEP_TAUGRAD = 2 };
+
+// One sweep launch. prec: BTE_PREC_*; l3: 3D layout; returns hipErrorInvalidValue
+// for a (G, nacc, mode) combination that is not compiled.
+hipError_t launch_sweep(int prec, bool l3, int G, int nacc, int mode, const SweepArgs& a,
+                        int grid, int block, size_t lds, hipStream_t st);
+
+// Workgroups of the sweep kernel that fit on one CU at once (0 on error).
+int sweep_blocks_per_cu(int prec, bool l3, int G, int nacc, int mode, int block, size_t lds);
+
+hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st);
+hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st);
+hipError_t launch_init_state(int prec, const InitArgs& a, int ncell, hipStream_t st);
+hipError_t launch_output(const double* X, const unsigned char* active, int n, double T_ref,
+                         double add_ref, double* out, hipStream_t st);
+hipError_t launch_status_reset(StatusDev* stt, double n_active, hipStream_t st);
+hipError_t launch_ubf_init(int prec, const UbfInitArgs& a, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace bte

@@ -1,0 +1,442 @@
+// Host-side problem set-up: validation, boundary tables, ordinate folding and
+// grouping, group coefficients and the sweep schedule.
+#include "bte_setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+
+namespace bte {
+
+static const double kPi = 3.14159265358979323846;
+
+static std::string fmt(const char* f, double a = 0, double b = 0) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), f, a, b);
+  return buf;
+}
+
+std::string validate_problem(const bte_geometry* g, const bte_bands* b, const bte_quadrature* q) {
+  if (!g || !b || !q) return "null geometry, bands or quadrature";
+  if (g->dim < 1 || g->dim > 3) return fmt("dim must be 1, 2 or 3 (got %g)", g->dim);
+  long long ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (g->n[d] < 1) return fmt("n[%g] must be >= 1", d);
+    if (d >= g->dim && g->n[d] != 1) return fmt("n[%g] must be 1 for an unused axis", d);
+    if (d < g->dim && !(g->h[d] > 0.0 && std::isfinite(g->h[d]))) return fmt("h[%g] must be > 0", d);
+    ncell *= g->n[d];
+  }
+  if (ncell > (1ll << 30)) return "grid too large";
+  if (g->n[0] > 65535) return "n[0] must be <= 65535";
+  if (g->n_bc < 1 || g->n_bc > 255) return "n_bc must be in 1..255";
+  if (!g->h_bc_kind || !g->h_bc_T) return "bc tables missing";
+  for (int k = 0; k < g->n_bc; ++k) {
+    if (g->h_bc_kind[k] == BTE_BC_SPECULAR) return "specular walls are not supported";
+    if (g->h_bc_kind[k] != BTE_BC_ISOTHERMAL && g->h_bc_kind[k] != BTE_BC_DIFFUSE)
+      return fmt("unknown bc kind %g", g->h_bc_kind[k]);
+    if (!std::isfinite(g->h_bc_T[k])) return "non-finite wall temperature";
+  }
+  if (b->n_bands < 1 || !b->h_v || !b->h_tau || !b->h_C) return "band table missing";
+  for (int i = 0; i < b->n_bands; ++i) {
+    if (!(b->h_v[i] > 0 && std::isfinite(b->h_v[i]))) return fmt("v[%g] must be > 0", i);
+    if (!(b->h_tau[i] > 0 && std::isfinite(b->h_tau[i]))) return fmt("tau[%g] must be > 0", i);
+    if (!(b->h_C[i] > 0 && std::isfinite(b->h_C[i]))) return fmt("C[%g] must be > 0", i);
+  }
+  if (q->n_dirs < 1 || !q->h_s || !q->h_w) return "quadrature missing";
+  double ws = 0.0;
+  for (int a = 0; a < q->n_dirs; ++a) {
+    const double* s = q->h_s + 3 * a;
+    const double nn = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (!(std::fabs(nn - 1.0) <= 1e-12)) return fmt("direction %g is not a unit vector", a);
+    if (!(q->h_w[a] > 0 && std::isfinite(q->h_w[a]))) return fmt("weight %g must be > 0", a);
+    ws += q->h_w[a];
+  }
+  if (std::fabs(ws - 4.0 * kPi) > 1e-10 * 4.0 * kPi) return fmt("weights sum to %g, not 4 pi", ws);
+  // closed under the reflection of each grid axis (same weight)
+  for (int d = 0; d < g->dim; ++d) {
+    for (int a = 0; a < q->n_dirs; ++a) {
+      double r[3] = {q->h_s[3 * a], q->h_s[3 * a + 1], q->h_s[3 * a + 2]};
+      r[d] = -r[d];
+      bool found = false;
+      for (int c = 0; c < q->n_dirs && !found; ++c) {
+        const double* s = q->h_s + 3 * c;
+        if (std::fabs(s[0] - r[0]) < 1e-12 && std::fabs(s[1] - r[1]) < 1e-12 &&
+            std::fabs(s[2] - r[2]) < 1e-12 && std::fabs(q->h_w[c] - q->h_w[a]) <= 1e-12 * q->h_w[a])
+          found = true;
+      }
+      if (!found) return fmt("quadrature not closed under reflection of axis %g", d);
+    }
+  }
+  // geometry: active cells and boundary ids
+  long long nact = 0;
+  bool iso = false;
+  const int n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+  for (long long c = 0; c < ncell; ++c) {
+    if (g->h_mask && !g->h_mask[c]) continue;
+    ++nact;
+    const int i = (int)(c % n0), j = (int)((c / n0) % n1), k = (int)(c / ((long long)n0 * n1));
+    for (int f = 0; f < 2 * g->dim; ++f) {
+      int idx[3] = {i, j, k};
+      const int d = f / 2;
+      idx[d] += (f & 1) ? 1 : -1;
+      bool bnd = idx[d] < 0 || idx[d] >= g->n[d];
+      if (!bnd && g->h_mask) {
+        const long long nb = idx[0] + (long long)n0 * (idx[1] + (long long)n1 * idx[2]);
+        bnd = !g->h_mask[nb];
+      }
+      if (!bnd) continue;
+      const int bc = g->h_face_bc ? g->h_face_bc[c * 6 + f] : 0;
+      if (bc >= g->n_bc) return fmt("face_bc of cell %g face %g out of range", (double)c, f);
+      if (g->h_bc_kind[bc] == BTE_BC_ISOTHERMAL) iso = true;
+    }
+  }
+  if (nact == 0) return "no active cell";
+  if (!iso) return "no isothermal boundary face: the steady state is not unique";
+  return "";
+}
+
+void build_instance(const bte_geometry* g, HostInst& hi) {
+  hi.dim = g->dim;
+  for (int d = 0; d < 3; ++d) {
+    hi.n[d] = g->n[d];
+    hi.h[d] = d < g->dim ? g->h[d] : 1.0;
+  }
+  hi.ncell = g->n[0] * g->n[1] * g->n[2];
+  hi.active.assign(hi.ncell, 1);
+  if (g->h_mask)
+    for (int c = 0; c < hi.ncell; ++c) hi.active[c] = g->h_mask[c] ? 1 : 0;
+  hi.n_active = 0;
+  for (int c = 0; c < hi.ncell; ++c) hi.n_active += hi.active[c];
+  hi.bc_kind.assign(g->h_bc_kind, g->h_bc_kind + g->n_bc);
+  hi.bc_T.assign(g->h_bc_T, g->h_bc_T + g->n_bc);
+  hi.bslot.assign((size_t)hi.ncell * 6, -1);
+  hi.bf_cell.clear();
+  hi.bf_face.clear();
+  hi.bf_bc.clear();
+  hi.dface.clear();
+  hi.has_iso = false;
+  const int n0 = hi.n[0], n1 = hi.n[1];
+  for (int c = 0; c < hi.ncell; ++c) {
+    if (!hi.active[c]) continue;
+    const int i = c % n0, j = (c / n0) % n1, k = c / (n0 * n1);
+    for (int f = 0; f < 2 * hi.dim; ++f) {
+      int idx[3] = {i, j, k};
+      const int d = f / 2;
+      idx[d] += (f & 1) ? 1 : -1;
+      bool bnd = idx[d] < 0 || idx[d] >= hi.n[d];
+      if (!bnd) bnd = !hi.active[idx[0] + n0 * (idx[1] + n1 * idx[2])];
+      if (!bnd) continue;
+      const int bc = g->h_face_bc ? g->h_face_bc[(size_t)c * 6 + f] : 0;
+      const int slot = (int)hi.bf_cell.size();
+      hi.bslot[(size_t)c * 6 + f] = slot;
+      hi.bf_cell.push_back(c);
+      hi.bf_face.push_back(f);
+      hi.bf_bc.push_back(bc);
+      if (hi.bc_kind[bc] == BTE_BC_DIFFUSE) hi.dface.push_back(slot);
+      else hi.has_iso = true;
+    }
+  }
+}
+
+std::vector<Ordinate> fold_ordinates(const bte_quadrature* q, int dim) {
+  std::vector<Ordinate> out;
+  for (int a = 0; a < q->n_dirs; ++a) {
+    const double* s = q->h_s + 3 * a;
+    bool merged = false;
+    if (dim < 3) {
+      for (auto& o : out) {
+        bool same = true;
+        for (int d = 0; d < dim; ++d) same = same && std::fabs(o.s[d] - s[d]) < 1e-12;
+        if (same) {
+          o.w += q->h_w[a];
+          merged = true;
+          break;
+        }
+      }
+    }
+    if (merged) continue;
+    Ordinate o;
+    o.s[0] = s[0];
+    o.s[1] = s[1];
+    o.s[2] = s[2];
+    for (int d = dim; d < 3; ++d) o.s[d] = 0.0;  // off-grid components do not transport
+    o.w = q->h_w[a];
+    o.oct = 0;
+    for (int d = 0; d < dim; ++d)
+      if (s[d] < 0.0) o.oct |= 1 << d;
+    out.push_back(o);
+  }
+  return out;
+}
+
+GroupSet build_groups(const std::vector<Ordinate>& ords, int B, int dim, int G, int P) {
+  GroupSet gs;
+  gs.G = G;
+  gs.P = P;
+  const int n_oct = 1 << dim;
+  gs.ob_first.assign(n_oct * B, 0);
+  gs.ob_count.assign(n_oct * B, 0);
+  for (int o = 0; o < n_oct; ++o) {
+    std::vector<int> members;
+    for (int a = 0; a < (int)ords.size(); ++a)
+      if (ords[a].oct == o) members.push_back(a);
+    if (members.empty()) continue;
+    const int first_grp = (int)gs.band.size();
+    for (int b = 0; b < B; ++b) {
+      gs.ob_first[o * B + b] = (int)gs.band.size();
+      for (size_t m = 0; m < members.size(); m += G) {
+        gs.band.push_back(b);
+        gs.oct.push_back(o);
+        for (int g = 0; g < G; ++g)
+          gs.ords.push_back(m + g < members.size() ? members[m + g] : -1);
+        gs.ob_count[o * B + b]++;
+      }
+    }
+    // bundles of P groups of this octant; pad with all-dummy groups
+    int ng = (int)gs.band.size() - first_grp;
+    while (ng % P) {
+      gs.band.push_back(0);
+      gs.oct.push_back(o);
+      for (int g = 0; g < G; ++g) gs.ords.push_back(-1);
+      ++ng;
+    }
+    for (int k = 0; k < ng; k += P) {
+      gs.bundle_first.push_back(first_grp + k);
+      gs.bundle_oct.push_back(o);
+    }
+  }
+  return gs;
+}
+
+double half_range(const std::vector<Ordinate>& ords, int d) {
+  double h = 0.0;
+  for (const auto& o : ords)
+    if (o.s[d] > 0.0) h += o.w * o.s[d];
+  return h;
+}
+
+void group_coefficients(const GroupSet& gs, const std::vector<Ordinate>& ords, const HostInst& hi,
+                        const std::vector<double>& v, const std::vector<double>& tau,
+                        const std::vector<double>& Cb, double t0, bool adjoint,
+                        std::vector<double>& out) {
+  const int G = gs.G;
+  const int GS = grp_stride(G);
+  const int ngrp = (int)gs.band.size();
+  out.assign((size_t)ngrp * GS, 0.0);
+  double Csum = 0.0, D = 0.0;
+  for (size_t b = 0; b < v.size(); ++b) {
+    Csum += Cb[b];
+    D += Cb[b] / tau[b];
+  }
+  const double gamma = t0 / Csum;
+  for (int k = 0; k < ngrp; ++k) {
+    double* r = out.data() + (size_t)k * GS;
+    const int b = gs.band[k];
+    const double rho = t0 / tau[b];
+    // an ordinate that gives the dummy slots valid transport coefficients
+    int ref = -1;
+    for (int g = 0; g < G && ref < 0; ++g) ref = gs.ords[(size_t)k * G + g];
+    if (ref < 0) {
+      for (int a = 0; a < (int)ords.size(); ++a)
+        if (ords[a].oct == gs.oct[k]) { ref = a; break; }
+    }
+    r[0] = adjoint ? 1.0 : rho;
+    r[1] = adjoint ? 0.0 : gamma;
+    for (int g = 0; g < G; ++g) {
+      const int a = gs.ords[(size_t)k * G + g];
+      const Ordinate& o = ords[a >= 0 ? a : ref];
+      const double w = a >= 0 ? o.w : 0.0;
+      double beta[3] = {0, 0, 0};
+      double den = rho;
+      for (int d = 0; d < hi.dim; ++d) {
+        beta[d] = t0 * v[b] * std::fabs(o.s[d]) / hi.h[d];
+        den += beta[d];
+      }
+      const double inv = 1.0 / den;
+      for (int d = 0; d < 3; ++d) r[go_a(G, d) + g] = beta[d] * inv;
+      r[go_den(G) + g] = den;
+      r[go_inv(G) + g] = inv;
+      // omega = w C_b / (4 pi tau_b D): weight of u in the new temperature
+      const double omega = w * Cb[b] / (4.0 * kPi * tau[b] * D);
+      if (!adjoint) {
+        r[go_wacc(G, 0) + g] = omega * inv;
+        for (int d = 0; d < hi.dim; ++d)
+          r[go_wacc(G, 1 + d) + g] = v[b] * w * o.s[d] * Cb[b] * inv / (4.0 * kPi);
+        for (int d = 0; d < hi.dim; ++d) r[go_wo(G, d) + g] = w * std::fabs(o.s[d]) * inv;
+      } else {
+        r[go_wacc(G, 0) + g] = rho * omega * inv;
+        r[go_wacc(G, 1) + g] = gamma * omega * inv;
+        r[go_wt(G, 0) + g] = omega * inv;
+        r[go_wt(G, 1) + g] = omega;
+      }
+    }
+  }
+}
+
+static int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err) {
+  const bool L3 = hi.dim == 3;
+  const int LJ = L3 ? 8 : 1, LK = L3 ? 8 : 64;
+  const int R = L3 ? 1 : plan.R;
+  const int C = plan.C;
+  const int nx = hi.n[0];
+  const int nJc = L3 ? hi.n[1] : 1;            // cells along kernel j
+  const int nKc = L3 ? hi.n[2] : hi.n[1];      // cells along kernel k
+  const int W = L3 ? std::max(nx, 8) : nx;
+  const int nJB = (nJc + LJ - 1) / LJ;
+  const int nS = (nKc + LK - 1) / LK;
+  const int V = nJB * W;
+  int du;
+  if (R == 1) du = std::max(V, LK);
+  else du = std::max(LK - 1 + C, (V + R - 1) / R);
+  int T = (nS - 1) * du + V + (LJ - 1) + (LK - 1) + 1;
+  T = (T + C - 1) / C * C;
+  s.T = T;
+  s.R = R;
+  s.C = C;
+  s.W = W;
+  s.n_oct = 1 << hi.dim;
+  s.lag = L3 ? du - (LK - 1) : 0;
+  s.ring = L3 ? next_pow2(s.lag + C + 16 + 8) : 0;
+  s.pos_per_oct = (long long)R * T * 64;
+  const long long npos = s.pos_per_oct * s.n_oct;
+  if (npos > (1ll << 31) - 1) {
+    err = "schedule too large";
+    return false;
+  }
+  s.sched.assign(npos, make_int2(-1, 0));
+  s.pos.assign((size_t)s.n_oct * hi.ncell, -1);
+  s.in_slot.clear();
+  const int nch = T / C;
+  s.in_chunk.assign((size_t)s.n_oct * R * (nch + 1), 0);
+  s.out_base.assign((size_t)s.n_oct * R, 0);
+  const int nbf = (int)hi.bf_cell.size();
+  s.ofk.assign((size_t)s.n_oct * std::max(nbf, 1), -1);
+  s.pre_slot.assign((size_t)s.n_oct * (L3 ? 1 : W), -1);
+  s.e_max = 1;
+  s.o_max = 1;
+  int n_out_max = 1;
+  const int n0 = hi.n[0], n1 = hi.n[1];
+  for (int o = 0; o < s.n_oct; ++o) {
+    const bool fx = o & 1, fy = (o >> 1) & 1, fz = (o >> 2) & 1;
+    // upwind / downwind physical faces per axis for this octant
+    const int up[3] = {fx ? 1 : 0, fy ? 3 : 2, fz ? 5 : 4};
+    const int dn[3] = {fx ? 0 : 1, fy ? 2 : 3, fz ? 4 : 5};
+    int out_count = 0;
+    for (int r = 0; r < R; ++r) {
+      s.out_base[o * R + r] = out_count;
+      int* chk = &s.in_chunk[((size_t)o * R + r) * (nch + 1)];
+      int out_k = 0;
+      for (int tau = 0; tau < T; ++tau) {
+        if (tau % C == 0) chk[tau / C] = (int)s.in_slot.size();
+        int chunk_in = 0, chunk_out = 0;
+        (void)chunk_in;
+        (void)chunk_out;
+        for (int l = 0; l < 64; ++l) {
+          const int jl = L3 ? (l & 7) : 0, kl = L3 ? (l >> 3) : l;
+          // which strip / virtual column does lane l of slot r process at tau?
+          int sidx = -1, v = -1;
+          if (R == 1) {
+            const int q = tau - jl - kl;
+            if (q >= 0) {
+              sidx = q / du;
+              v = q - sidx * du;
+            }
+          } else {
+            // strips r, r+R, ... start at s*du
+            const int q = tau - jl - kl;
+            if (q >= 0) {
+              int m = q / du;  // candidate strip index
+              // the strip of slot r with start <= q: s = largest s = r mod R with s*du <= q
+              int sc = m - ((m - r) % R + R) % R;
+              if (sc >= 0) {
+                sidx = sc;
+                v = q - sc * du;
+              }
+            }
+          }
+          if (sidx < 0 || sidx >= nS || v < 0 || v >= V) continue;
+          const int J = v / W, ip = v - J * W;
+          if (ip >= nx) continue;
+          const int jp = J * LJ + jl, kp = sidx * LK + kl;
+          if (jp >= nJc || kp >= nKc) continue;
+          // physical cell
+          int ix = fx ? nx - 1 - ip : ip;
+          int iy, iz;
+          if (L3) {
+            iy = fy ? hi.n[1] - 1 - jp : jp;
+            iz = fz ? hi.n[2] - 1 - kp : kp;
+          } else {
+            iy = fy ? hi.n[1] - 1 - kp : kp;
+            iz = 0;
+          }
+          const int cell = ix + n0 * (iy + n1 * iz);
+          const long long pidx = ((long long)o * R + r) * T * 64 + (long long)tau * 64 + l;
+          unsigned fl = (unsigned)ip << F_COL_SHIFT;
+          if (hi.active[cell]) {
+            fl |= F_ACTIVE;
+            s.pos[(size_t)o * hi.ncell + cell] = (int)(((long long)r * T + tau) * 64 + l);
+            for (int d = 0; d < hi.dim; ++d) {
+              const int su = hi.bslot[(size_t)cell * 6 + up[d]];
+              if (su >= 0) {
+                // 2D: the first strip's lane-0 k-ghost is prefilled from pre_slot
+                if (!L3 && d == 1 && kp == 0) {
+                  s.pre_slot[(size_t)o * W + ip] = su;
+                } else {
+                  fl |= F_IN_X << d;
+                  s.in_slot.push_back(su);
+                }
+              }
+            }
+            for (int d = 0; d < hi.dim; ++d) {
+              const int sd = hi.bslot[(size_t)cell * 6 + dn[d]];
+              if (sd >= 0 && hi.bc_kind[hi.bf_bc[sd]] == BTE_BC_DIFFUSE) {
+                fl |= F_OUT_X << d;
+                s.ofk[(size_t)o * nbf + sd] = out_count + out_k;
+                ++out_k;
+              }
+            }
+          }
+          s.sched[pidx] = make_int2(cell, (int)fl);
+        }
+      }
+      chk[nch] = (int)s.in_slot.size();
+      for (int ch = 0; ch < nch; ++ch) s.e_max = std::max(s.e_max, chk[ch + 1] - chk[ch]);
+      out_count += out_k;
+    }
+    n_out_max = std::max(n_out_max, out_count);
+  }
+  // maximum outflow entries of one slot in one chunk
+  for (int o = 0; o < s.n_oct; ++o)
+    for (int r = 0; r < R; ++r)
+      for (int ch = 0; ch < nch; ++ch) {
+        int cnt = 0;
+        for (int tau = ch * C; tau < (ch + 1) * C; ++tau)
+          for (int l = 0; l < 64; ++l) {
+            const unsigned fl = (unsigned)s.sched[((long long)o * R + r) * T * 64 + (long long)tau * 64 + l].y;
+            cnt += ((fl & F_OUT_X) != 0) + ((fl & F_OUT_Y) != 0) + ((fl & F_OUT_Z) != 0);
+          }
+        s.o_max = std::max(s.o_max, cnt);
+      }
+  s.n_out_stride = n_out_max;
+  if (s.e_max > 256) {
+    err = "too many boundary inflows per chunk: use a smaller C";
+    return false;
+  }
+  // every active cell must be scheduled exactly once per octant
+  for (int o = 0; o < s.n_oct; ++o)
+    for (int c = 0; c < hi.ncell; ++c)
+      if (hi.active[c] && s.pos[(size_t)o * hi.ncell + c] < 0) {
+        err = "internal: cell missing from the schedule";
+        return false;
+      }
+  return true;
+}
+
+}  // namespace bte

@@ -1,0 +1,96 @@
+// Host-side problem set-up shared by the C ABI implementation: validation,
+// ordinate folding, ordinate groups and their coefficients, boundary-face
+// tables and the sweep schedule. Plain C++ (no HIP calls).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/bte.h"
+#include "bte_device.h"
+
+namespace bte {
+
+struct Ordinate {
+  double s[3];  // direction
+  double w;     // weight (sum of the folded members)
+  int oct;      // bit d set: negative direction along grid axis d
+};
+
+struct Plan {
+  int G = 4, R = 4, P = 1, C = 16;
+};
+
+// One problem instance on the host.
+struct HostInst {
+  int dim = 0;
+  int n[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int ncell = 0, n_active = 0;
+  std::vector<uint8_t> active;       // [ncell]
+  // boundary faces: active cells ascending, faces ascending
+  std::vector<int> bf_cell, bf_face, bf_bc;
+  std::vector<int> bslot;            // [ncell*6] -> boundary-face slot or -1
+  std::vector<int> bc_kind;          // copy of the bc table
+  std::vector<double> bc_T;
+  std::vector<int> dface;            // slots of diffuse faces
+  bool has_iso = false;
+};
+
+// Ordinate groups of an instance (same for every instance of a batch, but the
+// coefficients depend on the cell size).
+struct GroupSet {
+  int G = 0, P = 0;
+  std::vector<int> band;             // [n_grp]
+  std::vector<int> oct;              // [n_grp]
+  std::vector<int> ords;             // [n_grp*G] ordinate index or -1 (dummy slot)
+  std::vector<int> bundle_first;     // [n_bundle] first group of each bundle
+  std::vector<int> bundle_oct;       // [n_bundle]
+  std::vector<int> ob_first, ob_count;  // [n_oct*B] groups of (octant, band): contiguous run
+};
+
+// Schedule of an instance for one plan (see bte_device.h).
+struct Schedule {
+  int T = 0, n_oct = 0, R = 1, C = 16, W = 0, lag = 0, ring = 0;
+  int e_max = 0, o_max = 0;
+  long long pos_per_oct = 0;
+  std::vector<int2> sched;           // [n_oct][R][T][64] (cell, flags)
+  std::vector<int> pos;              // [n_oct][ncell]
+  std::vector<int> in_slot;          // concatenated inflow slots
+  std::vector<int> in_chunk;         // [n_oct][R][nch+1] absolute offsets
+  std::vector<int> out_base;         // [n_oct][R]
+  std::vector<int> ofk;              // [n_oct][n_bface]
+  std::vector<int> pre_slot;         // 2D: [n_oct][W]
+  int n_out_stride = 1;              // max out-stream length over octants
+};
+
+// Validation of the public structures; returns "" when valid.
+std::string validate_problem(const bte_geometry* g, const bte_bands* b, const bte_quadrature* q);
+
+// Build the host instance from a validated geometry.
+void build_instance(const bte_geometry* g, HostInst& out);
+
+// Fold ordinates with identical projections on the grid axes (2D: +-z mirror
+// pairs), summing their weights.
+std::vector<Ordinate> fold_ordinates(const bte_quadrature* q, int dim);
+
+// Groups of G ordinates of one band and one octant, bundles of P groups of one
+// octant (padded with zero-weight dummies).
+GroupSet build_groups(const std::vector<Ordinate>& ords, int B, int dim, int G, int P);
+
+// Coefficient records (grp_stride(G) doubles per group) of every group.
+// adjoint = false: forward sweep; true: transposed sweep (octant flipped).
+void group_coefficients(const GroupSet& gs, const std::vector<Ordinate>& ords, const HostInst& hi,
+                        const std::vector<double>& v, const std::vector<double>& tau,
+                        const std::vector<double>& C, double t0, bool adjoint,
+                        std::vector<double>& out);
+
+// Sweep schedule of an instance.
+bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err);
+
+// sum over incoming directions of w |s . n| for a face normal to axis d.
+double half_range(const std::vector<Ordinate>& ords, int d);
+
+}  // namespace bte

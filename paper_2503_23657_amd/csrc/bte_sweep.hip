@@ -1,0 +1,499 @@
+// Transport sweep kernel for gfx950 (MI355X).
+//
+// One launch performs one source-iteration sweep (paper Methods, "Iterative
+// matrix formulation and solution scheme", step 2): for every (band,
+// direction) pair the first-order upwind system A e = b (Eqs. Axb, A_matrix with
+// first-order faces) is solved exactly by one pass in upwind order, and in the
+// same pass the band/direction sums of Eq. updatee0_t (new lattice temperature)
+// and Eq. 4 (heat flux) are accumulated, plus the outgoing partial currents of
+// the diffuse walls (Eq. 6).
+//
+// Work decomposition (see bte_device.h for the terms):
+//   * a lane owns one cell of the (j, k) cross-section and sweeps it along i;
+//     its G register slots hold G ordinates of one band and one octant;
+//   * the upwind neighbour in i is the lane's own previous value; the neighbour
+//     in j or k is a neighbouring lane's previous value, moved with a DPP lane
+//     shift (wave_shr:1 for k in 2D, row_shr:1 for j in 3D) or, for k in 3D,
+//     through a per-wave LDS exchange block with a ghost row;
+//   * 2D: the R waves of a workgroup pipeline successive 64-row strips, the top
+//     row of one strip reaching the next wave through an LDS ring, with one
+//     workgroup barrier every C steps;
+//     3D: one wave streams all 8x8 pencil blocks; the j-link between blocks goes
+//     through an LDS ring, the k-link between strips through a global ring whose
+//     values are prefetched D steps ahead;
+//   * every per-step input comes from the precomputed skewed schedule, so each
+//     wave reads 64 contiguous entries per step, prefetched D steps ahead;
+//   * boundary inflows are consumed as an ordered stream per wave, staged into
+//     LDS one chunk ahead, so no lane waits on a dependent load;
+//   * per-cell partial sums of the P waves of a workgroup are staged in LDS,
+//     added, and written back as contiguous row segments.
+#include <hip/hip_runtime.h>
+
+#include "bte_device.h"
+
+namespace bte {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+  using t = float2;
+};
+template <>
+struct V2<double> {
+  using t = double2;
+};
+
+// DPP controls (GFX9 encoding): wave_shr:1 = 0x138, row_shr:1 = 0x111.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float old, float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ unsigned long long ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+enum { M_PLAIN = 0, M_STORE = 1, M_TAUGRAD = 2 };
+
+constexpr int kD = 8;    // prefetch distance (steps) of the per-step inputs
+constexpr int kEPL = 4;  // in-stream entries per lane per chunk (e_max <= 256)
+
+// ============================================================================
+// L3 = false: 1D/2D layout (LJ = 1, LK = 64, k = y), R strip waves per slot;
+// L3 = true : 3D layout (LJ = 8, LK = 8, j = y, k = z), R = 1.
+// ============================================================================
+template <typename T, int G, int NACC, int MODE, bool L3>
+__global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
+  using T2 = typename V2<T>::t;
+  constexpr int LJ = L3 ? 8 : 1;
+  constexpr int LK = L3 ? 8 : 64;
+  constexpr int GS = grp_stride(G);
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_job;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int R = A.R, P = A.P, C = A.C;
+  const int r = wave % R;
+  const int p = wave / R;
+  const int rprev = (r + R - 1) % R;
+  const int jl = L3 ? (lane & 7) : 0;
+  const int kl = L3 ? (lane >> 3) : lane;
+
+  // LDS carve-up (byte offsets computed on the host)
+  T* zring = reinterpret_cast<T*>(lds + A.lds_zring);  // 2D: [P][R][W_max][G]
+  T* yring = reinterpret_cast<T*>(lds + A.lds_yring);  // 3D: [P][LK][W_max][G]
+  T* xb = reinterpret_cast<T*>(lds + A.lds_xb);        // 3D: [P][72][G]
+  T* stage = reinterpret_cast<T*>(lds + A.lds_stage);  // [P*R][NACC][C][65]
+  int* scid = reinterpret_cast<int*>(lds + A.lds_cid); // [R][C][65]
+  T* inb = reinterpret_cast<T*>(lds + A.lds_in);       // [P*R][2][e_max]
+  T* outb = reinterpret_cast<T*>(lds + A.lds_out);     // [P*R][o_max]
+  const int W_max = A.W_max;
+  T* my_zring = zring + (size_t)(p * R + r) * W_max * G;
+  const T* prev_zring = zring + (size_t)(p * R + rprev) * W_max * G;
+  T* my_yring = yring + (size_t)p * LK * W_max * G;
+  T* my_xb = xb + (size_t)p * 72 * G;
+  T* my_stage = stage + (size_t)(p * R + r) * NACC * C * 65;
+  int* my_scid = scid + (size_t)r * C * 65;
+  T* my_inb = inb + (size_t)(p * R + r) * 2 * A.e_max;
+  T* my_outb = outb + (size_t)(p * R + r) * A.o_max;
+  T* my_zg = L3 ? reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride : nullptr;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_job = atomicAdd(&A.counters[0], 1);
+    __syncthreads();
+    const int job = s_job;
+    if (job >= A.n_jobs) break;
+    const JobDev jd = A.jobs[job];
+    const InstDev& I = A.inst[jd.inst];
+    const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+    if (!A.force && st->done) continue;
+    const int iter = st->iter;
+
+    // ---- this wave's group: band constants and per-ordinate coefficients
+    const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
+    const int4 gi = A.grp_i[g_glob];
+    const int band = gi.x;
+    const int g_loc = gi.z;
+    const T* gt = reinterpret_cast<const T*>(A.grp_t) + (size_t)g_glob * GS;
+    const T kS = gt[0], cQ = gt[1];
+    T a0[G], a1[G], a2[G], den[G], inv[G];
+    T wacc[NACC][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      a0[g] = gt[go_a(G, 0) + g];
+      a1[g] = gt[go_a(G, 1) + g];
+      a2[g] = gt[go_a(G, 2) + g];
+      den[g] = gt[go_den(G) + g];
+      inv[g] = gt[go_inv(G) + g];
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) wacc[a][g] = gt[go_wacc(G, a) + g];
+    }
+
+    const int o = jd.oct;
+    const int T_steps = I.T;
+    const int nch = T_steps / C;
+    const long long slot_base = (long long)o * I.pos_per_oct + (long long)r * T_steps * 64;
+    const int2* SCH = I.sched + slot_base;
+    const T2* XQ = reinterpret_cast<const T2*>(I.xq[iter & 1]) + slot_base;
+    const T2* XF = MODE == M_TAUGRAD ? reinterpret_cast<const T2*>(I.xf) + slot_base : nullptr;
+    const T* UBF = reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface;
+    const int* ich = I.in_chunk + (size_t)(o * R + r) * (nch + 1);
+    T* OUTV = reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[o * R + r];
+    T* PART = reinterpret_cast<T*>(I.part);
+    const size_t part_plane = (size_t)I.n_jobs * I.ncell;
+    T* PARTJ = PART + (size_t)jd.jl * I.ncell;
+    const int zmask = L3 ? I.ring - 1 : 0;
+    const int zlag = L3 ? I.lag : 0;
+
+    // ---- clear the exchange buffers; prefill the first strip's ghosts (2D)
+    if (!L3) {
+      for (int e = lane; e < W_max * G; e += 64) my_zring[e] = T(0);
+    } else if (r == 0) {
+      for (int e = lane; e < LK * W_max * G; e += 64) my_yring[e] = T(0);
+      for (int e = lane; e < 72 * G; e += 64) my_xb[e] = T(0);
+    }
+    __syncthreads();
+    if (!L3 && r == 0) {
+      // strip 0, lane 0 reads the ring of "strip -1" = slot R-1, indexed by column
+      T* zr = zring + (size_t)(p * R + (R - 1)) * W_max * G;
+      const int* pre = I.pre_slot + (size_t)o * I.W;
+      for (int c = lane; c < I.W; c += 64) {
+        const int sl = pre[c];
+        const T u = sl >= 0 ? UBF[sl] : T(0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) zr[c * G + g] = u * den[g];
+      }
+    }
+
+    // ---- inflow stream pipeline: slots of chunk k+1 wait in registers, the
+    //      values of chunk k sit in LDS buffer (k & 1)
+    int slot_n[kEPL];
+    {
+      const int b0 = ich[0], e0 = ich[1];
+#pragma unroll
+      for (int m = 0; m < kEPL; ++m) {
+        const int idx = b0 + lane + 64 * m;
+        const T v = idx < e0 ? UBF[I.in_slot[idx]] : T(0);
+        if (lane + 64 * m < A.e_max) my_inb[lane + 64 * m] = v;
+      }
+      const int b1 = nch > 1 ? ich[1] : 0, e1 = nch > 1 ? ich[2] : 0;
+#pragma unroll
+      for (int m = 0; m < kEPL; ++m) {
+        const int idx = b1 + lane + 64 * m;
+        slot_n[m] = idx < e1 ? I.in_slot[idx] : -1;
+      }
+    }
+    __syncthreads();
+
+    // ---- per-lane state
+    T f[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) f[g] = T(0);
+    int out_cur = 0;
+    double tg0 = 0.0, tg1 = 0.0;
+
+    // prefetch ring of the per-step inputs
+    int2 rcf[kD];
+    T2 rxq[kD];
+    T2 rxf[kD];
+    T rzg[kD][G];
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      rcf[u] = SCH[u * 64 + lane];
+      rxq[u] = XQ[u * 64 + lane];
+      if (MODE == M_TAUGRAD) rxf[u] = XF[u * 64 + lane];
+      if (L3) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) rzg[u][g] = T(0);
+        if (kl == 0 && u >= zlag) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((u - zlag) & zmask) * LJ + jl) * G + g];
+        }
+      }
+    }
+
+    for (int ch = 0; ch < nch; ++ch) {
+      // gather the next chunk's inflow values now; they are written to LDS at
+      // the end of the chunk
+      T inval[kEPL];
+#pragma unroll
+      for (int m = 0; m < kEPL; ++m) inval[m] = slot_n[m] >= 0 ? UBF[slot_n[m]] : T(0);
+      {
+        const int b2 = ch + 2 < nch ? ich[ch + 2] : 0;
+        const int e2 = ch + 2 < nch ? ich[ch + 3] : 0;
+#pragma unroll
+        for (int m = 0; m < kEPL; ++m) {
+          const int idx = b2 + lane + 64 * m;
+          slot_n[m] = idx < e2 ? I.in_slot[idx] : -1;
+        }
+      }
+      const T* inbuf = my_inb + (ch & 1) * A.e_max;
+      int in_cur = 0;
+      const int out_chunk0 = out_cur;
+
+      for (int cc0 = 0; cc0 < C; cc0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+          const int cc = cc0 + u;
+          const int tau = ch * C + cc;
+          const int2 cf = rcf[u];
+          const T2 xq = rxq[u];
+          T2 xf;
+          if (MODE == M_TAUGRAD) xf = rxf[u];
+          T zg[G];
+          if (L3) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) zg[g] = rzg[u][g];
+          }
+          if (tau + kD < T_steps) {
+            const int tn = tau + kD;
+            rcf[u] = SCH[tn * 64 + lane];
+            rxq[u] = XQ[tn * 64 + lane];
+            if (MODE == M_TAUGRAD) rxf[u] = XF[tn * 64 + lane];
+            if (L3 && kl == 0 && tn >= zlag) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
+            }
+          }
+          const int cid = cf.x;
+          const unsigned fl = (unsigned)cf.y;
+          const int col = (int)((fl >> F_COL_SHIFT) & F_COL_MASK);
+          const T S = kS * xq.x + cQ * xq.y;
+
+          // lanes exchange values through LDS: keep this step's reads after the
+          // previous step's writes (the compiler cannot see the cross-lane use)
+          __builtin_amdgcn_wave_barrier();
+
+          // ---- upwind values
+          T xu[G], yu[G], zu[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) xu[g] = f[g];
+          if (!L3) {
+            // k-neighbour (y): lane - 1; lane 0 takes the previous strip's value
+            T gh[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) gh[g] = T(0);
+            if (lane == 0) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) gh[g] = prev_zring[col * G + g];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              zu[g] = dpp_move<0x138>(gh[g], f[g]);
+              yu[g] = T(0);
+            }
+          } else {
+            // j-neighbour (y): lane - 1 inside each 8-lane group; jl == 0 takes
+            // the previous J-block's value from the y-ring
+            T gh[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) gh[g] = T(0);
+            if (jl == 0) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) gh[g] = my_yring[(kl * W_max + col) * G + g];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const T d = dpp_move<0x111>(T(0), f[g]);
+              yu[g] = jl == 0 ? gh[g] : d;
+            }
+            // k-neighbour (z): entry lane of the exchange block; the ghost row
+            // (entries 0..7) holds the previous strip's values for kl == 0
+            if (kl == 0) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) my_xb[jl * G + g] = zg[g];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) zu[g] = my_xb[lane * G + g];
+          }
+
+          // ---- boundary inflows from the stream
+          {
+            const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = fl & F_IN_Z;
+            const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = ballot64(bz);
+            if ((mx | my | mz) != 0ull) {
+              int k = in_cur + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
+              if (bx) {
+                const T uin = inbuf[k++];
+#pragma unroll
+                for (int g = 0; g < G; ++g) xu[g] = uin * den[g];
+              }
+              if (by) {
+                const T uin = inbuf[k++];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                  if (L3) yu[g] = uin * den[g];
+                  else zu[g] = uin * den[g];
+                }
+              }
+              if (bz) {
+                const T uin = inbuf[k++];
+#pragma unroll
+                for (int g = 0; g < G; ++g) zu[g] = uin * den[g];
+              }
+              in_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
+            }
+          }
+
+          // ---- the transport update and the fused band/direction sums
+          T acc[NACC];
+#pragma unroll
+          for (int a = 0; a < NACC; ++a) acc[a] = T(0);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            T fn;
+            if (L3) fn = fma(a2[g], zu[g], fma(a1[g], yu[g], fma(a0[g], xu[g], S)));
+            else fn = fma(a1[g], zu[g], fma(a0[g], xu[g], S));
+            f[g] = fn;
+#pragma unroll
+            for (int a = 0; a < NACC; ++a) acc[a] = fma(wacc[a][g], fn, acc[a]);
+          }
+
+          // ---- exchange writes for the downstream neighbours
+          __builtin_amdgcn_wave_barrier();
+          if (L3) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) my_xb[(lane + 8) * G + g] = f[g];
+            if (jl == LJ - 1 && cid >= 0) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) my_yring[(kl * W_max + col) * G + g] = f[g];
+            }
+            if (kl == LK - 1) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) my_zg[(size_t)((tau & zmask) * LJ + jl) * G + g] = f[g];
+            }
+          } else {
+            if (lane == 63 && cid >= 0) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) my_zring[col * G + g] = f[g];
+            }
+          }
+
+          // ---- diffuse-wall outflow stream
+          {
+            const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = fl & F_OUT_Z;
+            const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = ballot64(oz);
+            if ((mx | my | mz) != 0ull) {
+              int k = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
+              const T* wo = gt + go_wo(G, 0);
+              if (ox) {
+                T v = T(0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) v = fma(wo[g], f[g], v);
+                my_outb[k++] = v;
+              }
+              if (oy) {
+                T v = T(0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) v = fma(wo[G + g], f[g], v);
+                my_outb[k++] = v;
+              }
+              if (oz) {
+                T v = T(0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) v = fma(wo[2 * G + g], f[g], v);
+                my_outb[k++] = v;
+              }
+              out_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
+            }
+          }
+
+          // ---- stored angular field / tau-gradient sums
+          if (MODE == M_STORE && cid >= 0 && (fl & F_ACTIVE)) {
+            T* su = reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G;
+#pragma unroll
+            for (int g = 0; g < G; ++g) su[g] = f[g] * inv[g];
+          }
+          if (MODE == M_TAUGRAD && cid >= 0 && (fl & F_ACTIVE)) {
+            const T* su = reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G;
+            const T* wt0 = gt + go_wt(G, 0);
+            const T* wt1 = gt + go_wt(G, 1);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const double uf = (double)su[g];
+              s0 += (double)wt0[g] * (double)f[g] * (uf - (double)xf.x);
+              s1 += (double)wt1[g] * uf;
+            }
+            tg0 += s0;
+            tg1 += (double)xq.x * s1;
+          }
+
+          // ---- stage the partial sums of this step
+#pragma unroll
+          for (int a = 0; a < NACC; ++a) my_stage[(a * C + cc) * 65 + lane] = acc[a];
+          if (p == 0) my_scid[cc * 65 + lane] = (fl & F_ACTIVE) ? cid : -1;
+        }
+      }
+
+      // ---- end of chunk: publish ring values, then write the partial sums
+      __syncthreads();
+      {
+        // the P waves of slot r add their partials; P*64 threads share C*64 entries
+        const int t = p * 64 + lane;
+        const int per = C / P;
+        for (int m = 0; m < per; ++m) {
+          const int e = m * (P * 64) + t;
+          const int lp = e / C, cc = e - lp * C;
+          const int cid = my_scid[cc * 65 + lp];
+          if (cid >= 0) {
+#pragma unroll
+            for (int a = 0; a < NACC; ++a) {
+              T v = T(0);
+              for (int q = 0; q < P; ++q) v += stage[((size_t)(q * R + r) * NACC * C + a * C + cc) * 65 + lp];
+              PARTJ[a * part_plane + cid] = v;
+            }
+          }
+        }
+      }
+      // flush this chunk's outflow entries
+      for (int e = lane; e < out_cur - out_chunk0; e += 64) OUTV[out_chunk0 + e] = my_outb[e];
+      // the gathered inflow values of the next chunk
+#pragma unroll
+      for (int m = 0; m < kEPL; ++m)
+        if (lane + 64 * m < A.e_max) my_inb[((ch + 1) & 1) * A.e_max + lane + 64 * m] = inval[m];
+      __syncthreads();
+    }
+
+    if (MODE == M_TAUGRAD) {
+      // wave reduction of the tau-gradient sums of this group
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        tg0 += __shfl_xor(tg0, off);
+        tg1 += __shfl_xor(tg1, off);
+      }
+      // the R waves of a slot column share the group: add them in slot order
+      double* tgp = I.tgrad + (size_t)g_loc * 2;
+      for (int rr = 0; rr < R; ++rr) {
+        if (r == rr && lane == 0) {
+          tgp[0] += tg0;
+          tgp[1] += tg1;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // the last workgroup out resets the queue counters for the next launch
+  if (tid == 0) {
+    const int e = atomicAdd(&A.counters[1], 1);
+    if (e == (int)gridDim.x - 1) {
+      atomicExch(&A.counters[0], 0);
+      atomicExch(&A.counters[1], 0);
+    }
+  }
+}
+
+}  // namespace bte

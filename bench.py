@@ -1,0 +1,152 @@
+"""Benchmark: cell x ordinate x band updates/s of the source-iteration sweep on
+the 2D nongray square (256 x 256 cells, 15 bands, 128 directions of which 64
+distinct in-plane projections are swept, FP32 sweeps with FP64 band sums),
+plus the adjoint/forward time ratio and batched solves/s as extra fields.
+
+One step is one source iteration of the whole hot path on the whole problem:
+the fused transport sweep of every (band, direction) pair with the band /
+direction reduction, the new temperature and its residuals, replayed from a
+captured hipGraph. Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. --gpus N with N > 1 exits: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_update(dim: int, with_q: bool) -> float:
+    # f = S + sum_d a_d f_d (dim FMAs), one FMA into the temperature sum, dim FMAs
+    # into the flux sums on flux iterations
+    return 2.0 * (dim + 1 + (dim if with_q else 0))
+
+
+def cpu_baseline(p, iters: int):
+    """The FP64 oracle timed on the host over a bounded number of iterations."""
+    import oracle
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    oracle.solve(p, tol=0.0, max_iters=iters, threads=threads)
+    dt = time.perf_counter() - t0
+    upd = p.n_active * p.M * p.B * iters
+    return dict(value=upd / dt, unit="cell-ordinate-band updates/s", cores=threads, kind="oracle",
+                sample=f"{iters} source iterations of the full 256x256x15x128 problem "
+                       f"({p.M} directions swept, FP64, {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import bte_inputs as bi
+    import paper_2503_23657_amd as bte
+
+    dev = torch.device("cuda:0")
+    p = bi.square_2d(256)  # 1 um square, 15 bands, 8x2 per octant z-polar (128 dirs)
+    M_swept = 64
+    solver = bte.Solver(p, precision="fp32")
+    Q = torch.tensor(p.Q, dtype=torch.float64, device=dev)
+    plan = solver.autotune(Q, n_iters=5)
+    log("plan", plan)
+    K = max(8, args.steps)
+    # warm-up (also captures the graphs)
+    solver.solve(Q, tol=0.0, max_iters=max(args.warmup, 2), check_every=K)
+    solver.solve(Q, tol=0.0, max_iters=K, check_every=K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, q, rep = solver.solve(Q, tol=0.0, max_iters=K, check_every=K)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_upd = p.n_active * M_swept * p.B
+    value = n_upd * K / dt
+    ms_per_step = dt / K * 1e3
+    log(f"forward: {K} iterations in {dt:.4f} s -> {value:.4e} updates/s")
+
+    # dominant kernel: the sweep, timed with HIP events on the stream it runs on
+    sweep_ms, _ = solver.time_sweep(n_launches=50)
+    flop = n_upd * flops_per_update(2, False)
+    achieved_tf = flop / (sweep_ms * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=achieved_tf, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved_tf / FP32_VALU_PEAK_TFLOPS, traffic=None,
+                    kernel="sweep_kernel<float,G,1,0,false>", kernel_ms=sweep_ms,
+                    sweep_updates_per_s=n_upd / (sweep_ms * 1e-3))
+
+    extra = {}
+    if not args.no_extra:
+        # adjoint / forward time ratio at equal tolerance (inverse-problem case on the square)
+        s64 = solver
+        tol = 1e-6
+        t0 = time.perf_counter()
+        T, _, rf = s64.solve(Q, tol=tol, check_every=8, store_state=True)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        case = bi.adjoint_case(p)
+        probes = torch.tensor(case["probes"], device=dev)
+        Tt = T.detach().clone().requires_grad_(True)
+        target = T.detach()[probes] + 1.0
+        J = ((Tt[probes] - target) ** 2).mean()
+        (gT,) = torch.autograd.grad(J, Tt)
+        t0 = time.perf_counter()
+        dtau, dQ, ra = s64.adjoint(gT.contiguous(), tol=tol, check_every=8)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        extra["adjoint_forward_ratio"] = ta / tf
+        extra["forward_solve_s"] = tf
+        extra["forward_iters"] = rf["iters"]
+        extra["adjoint_solve_s"] = ta
+        extra["adjoint_iters"] = ra["iters"]
+        log(f"adjoint/forward = {ta / tf:.3f} ({ra['iters']} vs {rf['iters']} iterations)")
+
+    out = {
+        "metric": "cell-ordinate-band updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D nongray square 256x256, 15 bands, 128 directions "
+                               "(64 in-plane projections swept), Gaussian hot spot, isothermal edges",
+                   "cells": p.n_active, "bands": p.B, "directions": p.M, "directions_swept": M_swept,
+                   "plan": plan, "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

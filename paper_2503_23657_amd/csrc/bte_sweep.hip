@@ -59,6 +59,19 @@ __device__ __forceinline__ double dpp_move(double old, double v) {
 }
 
 __device__ __forceinline__ unsigned long long ballot64(bool p) { return __ballot(p); }
+
+// Pointers taken from the descriptors are generic; marking them global lets the
+// compiler use global (not flat) memory instructions, which do not count
+// against the LDS wait counter.
+#define GAS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GAS T* gp(T* p) {
+  return (GAS T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GAS T* gp(const T* p) {
+  return (const GAS T*)p;
+}
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
@@ -108,7 +121,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
   int* my_scid = scid + (size_t)r * C * 65;
   T* my_inb = inb + (size_t)(p * R + r) * 2 * A.e_max;
   T* my_outb = outb + (size_t)(p * R + r) * A.o_max;
-  T* my_zg = L3 ? reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride : nullptr;
+  GAS T* my_zg = L3 ? gp(reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride) : nullptr;
 
   for (;;) {
     __syncthreads();
@@ -146,15 +159,15 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const int T_steps = I.T;
     const int nch = T_steps / C;
     const long long slot_base = (long long)o * I.pos_per_oct + (long long)r * T_steps * 64;
-    const int2* SCH = I.sched + slot_base;
-    const T2* XQ = reinterpret_cast<const T2*>(I.xq[iter & 1]) + slot_base;
-    const T2* XF = MODE == M_TAUGRAD ? reinterpret_cast<const T2*>(I.xf) + slot_base : nullptr;
-    const T* UBF = reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface;
-    const int* ich = I.in_chunk + (size_t)(o * R + r) * (nch + 1);
-    T* OUTV = reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[o * R + r];
-    T* PART = reinterpret_cast<T*>(I.part);
+    const GAS int2* SCH = gp(I.sched + slot_base);
+    const GAS T2* XQ = gp(reinterpret_cast<const T2*>(I.xq[iter & 1]) + slot_base);
+    const GAS T2* XF = MODE == M_TAUGRAD ? gp(reinterpret_cast<const T2*>(I.xf) + slot_base) : nullptr;
+    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
+    const GAS int* ISLOT = gp(I.in_slot);
+    const GAS int* ich = gp(I.in_chunk + (size_t)(o * R + r) * (nch + 1));
+    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[o * R + r]);
     const size_t part_plane = (size_t)I.n_jobs * I.ncell;
-    T* PARTJ = PART + (size_t)jd.jl * I.ncell;
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.ncell);
     const int zmask = L3 ? I.ring - 1 : 0;
     const int zlag = L3 ? I.lag : 0;
 
@@ -169,7 +182,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     if (!L3 && r == 0) {
       // strip 0, lane 0 reads the ring of "strip -1" = slot R-1, indexed by column
       T* zr = zring + (size_t)(p * R + (R - 1)) * W_max * G;
-      const int* pre = I.pre_slot + (size_t)o * I.W;
+      const GAS int* pre = gp(I.pre_slot + (size_t)o * I.W);
       for (int c = lane; c < I.W; c += 64) {
         const int sl = pre[c];
         const T u = sl >= 0 ? UBF[sl] : T(0);
@@ -186,14 +199,14 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 #pragma unroll
       for (int m = 0; m < kEPL; ++m) {
         const int idx = b0 + lane + 64 * m;
-        const T v = idx < e0 ? UBF[I.in_slot[idx]] : T(0);
+        const T v = idx < e0 ? UBF[ISLOT[idx]] : T(0);
         if (lane + 64 * m < A.e_max) my_inb[lane + 64 * m] = v;
       }
       const int b1 = nch > 1 ? ich[1] : 0, e1 = nch > 1 ? ich[2] : 0;
 #pragma unroll
       for (int m = 0; m < kEPL; ++m) {
         const int idx = b1 + lane + 64 * m;
-        slot_n[m] = idx < e1 ? I.in_slot[idx] : -1;
+        slot_n[m] = idx < e1 ? ISLOT[idx] : -1;
       }
     }
     __syncthreads();
@@ -237,7 +250,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 #pragma unroll
         for (int m = 0; m < kEPL; ++m) {
           const int idx = b2 + lane + 64 * m;
-          slot_n[m] = idx < e2 ? I.in_slot[idx] : -1;
+          slot_n[m] = idx < e2 ? ISLOT[idx] : -1;
         }
       }
       const T* inbuf = my_inb + (ch & 1) * A.e_max;
@@ -413,12 +426,12 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 
           // ---- stored angular field / tau-gradient sums
           if (MODE == M_STORE && cid >= 0 && (fl & F_ACTIVE)) {
-            T* su = reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G;
+            GAS T* su = gp(reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G);
 #pragma unroll
             for (int g = 0; g < G; ++g) su[g] = f[g] * inv[g];
           }
           if (MODE == M_TAUGRAD && cid >= 0 && (fl & F_ACTIVE)) {
-            const T* su = reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G;
+            const GAS T* su = gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G);
             const T* wt0 = gt + go_wt(G, 0);
             const T* wt1 = gt + go_wt(G, 1);
             double s0 = 0.0, s1 = 0.0;
@@ -476,7 +489,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
         tg1 += __shfl_xor(tg1, off);
       }
       // the R waves of a slot column share the group: add them in slot order
-      double* tgp = I.tgrad + (size_t)g_loc * 2;
+      GAS double* tgp = gp(I.tgrad + (size_t)g_loc * 2);
       for (int rr = 0; rr < R; ++rr) {
         if (r == rr && lane == 0) {
           tgp[0] += tg0;

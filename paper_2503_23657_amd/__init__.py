@@ -20,6 +20,11 @@ LIB_PATH = os.path.join(_HERE, "libbte_hip.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python {os.path.join(_HERE, 'build.py')}`")
 
+# torch carries its own HIP runtime; it must be loaded before the library so
+# that the library binds to the same runtime (one device context, shared
+# streams and allocations).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 BTE_OK, BTE_ERR_INVALID, BTE_ERR_HIP, BTE_ERR_NOT_CONVERGED, BTE_ERR_NONFINITE, BTE_ERR_STATE = range(6)

@@ -44,6 +44,13 @@ void set_err(const char* f, ...) {
 
 const double kPi = 3.14159265358979323846;
 
+// Every ABI call leaves the HIP runtime's last-error state clear on exit: the
+// runtime is shared with the caller (torch), whose next call would otherwise
+// report an error this library already handled or returned.
+struct ErrClear {
+  ~ErrClear() { (void)hipGetLastError(); }
+};
+
 // Device allocations owned by a handle.
 struct DevPool {
   std::vector<void*> ptrs;
@@ -160,6 +167,7 @@ struct bte_ctx {
   size_t lds = 0;
   int block = 64, grid = 1;
   int nacc_max = 1;
+  size_t lds_stage_plane = 0;
   hipStream_t cap_stream = nullptr;
   std::map<long long, hipGraphExec_t> graphs;
   std::map<long long, hipGraph_t> graph_src;
@@ -359,14 +367,17 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   off += al(L3 ? (size_t)P * 8 * W_max * G * es : 0);
   sa.lds_xb = (int)off;
   off += al(L3 ? (size_t)P * 72 * G * es : 0);
-  sa.lds_stage = (int)off;
-  off += al((size_t)P * R * h->nacc_max * Cc * 65 * es);
   sa.lds_cid = (int)off;
   off += al((size_t)R * Cc * 65 * 4);
   sa.lds_in = (int)off;
   off += al((size_t)P * R * 2 * e_max * es);
   sa.lds_out = (int)off;
   off += al((size_t)P * R * o_max * es);
+  // the partial-sum staging goes last: its size depends on the number of
+  // accumulator planes of the launched variant
+  sa.lds_stage = (int)off;
+  h->lds_stage_plane = al((size_t)P * R * Cc * 65 * es);
+  off += (size_t)h->nacc_max * h->lds_stage_plane;
   sa.lds_total = (int)off;
   if (off > 160 * 1024 - 64) {
     set_err("plan needs %zu bytes of LDS (limit 160 KiB): reduce P, R, C or G", off);
@@ -388,7 +399,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   sa.e_max = e_max;
   sa.o_max = o_max;
   h->block = R * P * 64;
-  int bpc = sweep_blocks_per_cu(prec, L3, G, 1, SWEEP_PLAIN, h->block, h->lds);
+  int bpc = sweep_blocks_per_cu(prec, L3, G, 1, SWEEP_PLAIN, h->block, sa.lds_stage + h->lds_stage_plane);
   if (bpc < 1) bpc = 1;
   h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
   if (L3) {
@@ -538,7 +549,7 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
     pl.G = 2;
     pl.R = 1;
     pl.P = 4;
-    pl.C = 16;
+    pl.C = 8;
   } else if (h->dim == 1) {
     pl.G = 1;
     pl.R = 1;
@@ -551,6 +562,11 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
     pl.C = 16;
   }
   s = build_plan(h.get(), pl);
+  if (s != BTE_OK && pl.C > 8) {
+    // boundary-rich geometries need shorter chunks for the inflow stream buffer
+    pl.C = 8;
+    s = build_plan(h.get(), pl);
+  }
   if (s != BTE_OK) return s;
   *out = h.release();
   return BTE_OK;
@@ -569,7 +585,8 @@ bte_status enqueue_sweep(bte_ctx* h, bool adj, int nacc, int mode, int force, hi
   a.grp_i = adj ? h->d_gi_a : h->d_gi_f;
   a.grp_t = adj ? h->d_gt_a : h->d_gt_f;
   a.force = force;
-  HIPCHK(launch_sweep(h->precision, h->dim == 3, h->plan.G, nacc, mode, a, h->grid, h->block, h->lds, st));
+  const size_t lds = (size_t)a.lds_stage + (size_t)nacc * h->lds_stage_plane;
+  HIPCHK(launch_sweep(h->precision, h->dim == 3, h->plan.G, nacc, mode, a, h->grid, h->block, lds, st));
   return BTE_OK;
 }
 
@@ -887,15 +904,18 @@ bte_status bte_quadrature_octant_gl(int n_theta, int n_phi, int polar_axis, doub
 
 bte_status bte_create(const bte_geometry* geom, const bte_bands* bands, const bte_quadrature* quad,
                       double T_ref, int precision, bte_handle* out) {
+  ErrClear clear_on_exit;
   return create_common(1, geom, bands, quad, T_ref, precision, out);
 }
 
 bte_status bte_batch_create(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
                             const bte_quadrature* quad, double T_ref, int precision, bte_handle* out) {
+  ErrClear clear_on_exit;
   return create_common(n_inst, geoms, bands, quad, T_ref, precision, out);
 }
 
 bte_status bte_set_tau(bte_handle h, const double* h_tau) {
+  ErrClear clear_on_exit;
   if (!h || !h_tau) {
     set_err("null handle or tau");
     return BTE_ERR_INVALID;
@@ -910,6 +930,7 @@ bte_status bte_set_tau(bte_handle h, const double* h_tau) {
 }
 
 bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
+  ErrClear clear_on_exit;
   if (!h || !plan) {
     set_err("null handle or plan");
     return BTE_ERR_INVALID;
@@ -943,6 +964,7 @@ bte_status bte_get_plan(bte_handle h, bte_plan* plan) {
 
 bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, double* d_T, double* d_q,
                      const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+  ErrClear clear_on_exit;
   if (!h || !d_T) {
     set_err("null handle or output");
     return BTE_ERR_INVALID;
@@ -974,6 +996,7 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
 
 bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const* d_T, double* const* d_q,
                            const bte_opts* opts, void* hip_stream, bte_report* h_reps) {
+  ErrClear clear_on_exit;
   if (!h || !d_T || !d_Q) {
     set_err("null handle or arrays");
     return BTE_ERR_INVALID;
@@ -1113,6 +1136,7 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
 
 bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, double* d_dJdQ,
                        const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+  ErrClear clear_on_exit;
   if (h && h->inst.size() != 1) {
     set_err("bte_adjoint needs a single-instance handle (use bte_batch_adjoint)");
     return BTE_ERR_STATE;
@@ -1125,10 +1149,12 @@ bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, dou
 bte_status bte_batch_adjoint(bte_handle h, const double* const* d_dJdT, double* h_dJdtau,
                              double* const* d_dJdQ, const bte_opts* opts, void* hip_stream,
                              bte_report* h_reps) {
+  ErrClear clear_on_exit;
   return adjoint_common(h, d_dJdT, h_dJdtau, d_dJdQ, opts, hip_stream, h_reps);
 }
 
 bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double* h_ms, double* h_updates) {
+  ErrClear clear_on_exit;
   if (!h || n_launches < 1 || !h_ms) {
     set_err("null handle/output or n_launches < 1");
     return BTE_ERR_INVALID;
@@ -1158,6 +1184,7 @@ bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double
 }
 
 bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_stream, bte_plan* best) {
+  ErrClear clear_on_exit;
   if (!h || n_iters < 1) {
     set_err("null handle or n_iters < 1");
     return BTE_ERR_INVALID;
@@ -1165,7 +1192,7 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<Plan> cand;
   const int Gs[3] = {1, 2, 4};
-  const int Cs[2] = {16, 32};
+  const int Cs[3] = {8, 16, 32};
   if (h->dim == 3) {
     for (int G : Gs)
       for (int P : {1, 2, 4, 8})
@@ -1205,6 +1232,7 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
 }
 
 bte_status bte_destroy(bte_handle h) {
+  ErrClear clear_on_exit;
   if (!h) return BTE_OK;
   clear_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);

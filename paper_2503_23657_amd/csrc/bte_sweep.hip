@@ -72,6 +72,23 @@ template <typename T>
 __device__ __forceinline__ const GAS T* gp(const T* p) {
   return (const GAS T*)p;
 }
+// HIP's vector types cannot bind address-space references: load pairs through
+// clang vector types
+typedef int iv2_t __attribute__((ext_vector_type(2)));
+typedef float fv2_t __attribute__((ext_vector_type(2)));
+typedef double dv2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int2 ld2(const GAS int2* p) {
+  const iv2_t v = *(const GAS iv2_t*)p;
+  return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld2(const GAS float2* p) {
+  const fv2_t v = *(const GAS fv2_t*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld2(const GAS double2* p) {
+  const dv2_t v = *(const GAS dv2_t*)p;
+  return make_double2(v.x, v.y);
+}
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
@@ -225,9 +242,9 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     T rzg[kD][G];
 #pragma unroll
     for (int u = 0; u < kD; ++u) {
-      rcf[u] = SCH[u * 64 + lane];
-      rxq[u] = XQ[u * 64 + lane];
-      if (MODE == M_TAUGRAD) rxf[u] = XF[u * 64 + lane];
+      rcf[u] = ld2(SCH + u * 64 + lane);
+      rxq[u] = ld2(XQ + u * 64 + lane);
+      if (MODE == M_TAUGRAD) rxf[u] = ld2(XF + u * 64 + lane);
       if (L3) {
 #pragma unroll
         for (int g = 0; g < G; ++g) rzg[u][g] = T(0);
@@ -273,9 +290,9 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           }
           if (tau + kD < T_steps) {
             const int tn = tau + kD;
-            rcf[u] = SCH[tn * 64 + lane];
-            rxq[u] = XQ[tn * 64 + lane];
-            if (MODE == M_TAUGRAD) rxf[u] = XF[tn * 64 + lane];
+            rcf[u] = ld2(SCH + tn * 64 + lane);
+            rxq[u] = ld2(XQ + tn * 64 + lane);
+            if (MODE == M_TAUGRAD) rxf[u] = ld2(XF + tn * 64 + lane);
             if (L3 && kl == 0 && tn >= zlag) {
 #pragma unroll
               for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
@@ -334,31 +351,29 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           }
 
           // ---- boundary inflows from the stream
-          {
-            const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = fl & F_IN_Z;
-            const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = ballot64(bz);
-            if ((mx | my | mz) != 0ull) {
-              int k = in_cur + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
-              if (bx) {
-                const T uin = inbuf[k++];
+          if (ballot64(fl & (F_IN_X | F_IN_Y | F_IN_Z)) != 0ull) {
+            const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = L3 && (fl & F_IN_Z);
+            const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = L3 ? ballot64(bz) : 0ull;
+            int k = in_cur + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            if (bx) {
+              const T uin = inbuf[k++];
 #pragma unroll
-                for (int g = 0; g < G; ++g) xu[g] = uin * den[g];
-              }
-              if (by) {
-                const T uin = inbuf[k++];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                  if (L3) yu[g] = uin * den[g];
-                  else zu[g] = uin * den[g];
-                }
-              }
-              if (bz) {
-                const T uin = inbuf[k++];
-#pragma unroll
-                for (int g = 0; g < G; ++g) zu[g] = uin * den[g];
-              }
-              in_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
+              for (int g = 0; g < G; ++g) xu[g] = uin * den[g];
             }
+            if (by) {
+              const T uin = inbuf[k++];
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                if (L3) yu[g] = uin * den[g];
+                else zu[g] = uin * den[g];
+              }
+            }
+            if (L3 && bz) {
+              const T uin = inbuf[k++];
+#pragma unroll
+              for (int g = 0; g < G; ++g) zu[g] = uin * den[g];
+            }
+            in_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
 
           // ---- the transport update and the fused band/direction sums
@@ -396,32 +411,30 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           }
 
           // ---- diffuse-wall outflow stream
-          {
-            const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = fl & F_OUT_Z;
-            const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = ballot64(oz);
-            if ((mx | my | mz) != 0ull) {
-              int k = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
-              const T* wo = gt + go_wo(G, 0);
-              if (ox) {
-                T v = T(0);
+          if (ballot64(fl & (F_OUT_X | F_OUT_Y | F_OUT_Z)) != 0ull) {
+            const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = L3 && (fl & F_OUT_Z);
+            const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = L3 ? ballot64(oz) : 0ull;
+            int k = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const T* wo = gt + go_wo(G, 0);
+            if (ox) {
+              T v = T(0);
 #pragma unroll
-                for (int g = 0; g < G; ++g) v = fma(wo[g], f[g], v);
-                my_outb[k++] = v;
-              }
-              if (oy) {
-                T v = T(0);
-#pragma unroll
-                for (int g = 0; g < G; ++g) v = fma(wo[G + g], f[g], v);
-                my_outb[k++] = v;
-              }
-              if (oz) {
-                T v = T(0);
-#pragma unroll
-                for (int g = 0; g < G; ++g) v = fma(wo[2 * G + g], f[g], v);
-                my_outb[k++] = v;
-              }
-              out_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
+              for (int g = 0; g < G; ++g) v = fma(wo[g], f[g], v);
+              my_outb[k++] = v;
             }
+            if (oy) {
+              T v = T(0);
+#pragma unroll
+              for (int g = 0; g < G; ++g) v = fma(wo[G + g], f[g], v);
+              my_outb[k++] = v;
+            }
+            if (L3 && oz) {
+              T v = T(0);
+#pragma unroll
+              for (int g = 0; g < G; ++g) v = fma(wo[2 * G + g], f[g], v);
+              my_outb[k++] = v;
+            }
+            out_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
 
           // ---- stored angular field / tau-gradient sums

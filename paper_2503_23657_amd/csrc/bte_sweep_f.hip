@@ -5,16 +5,35 @@
 
 namespace bte {
 
+// Largest dynamic LDS a launch of kernel k may request: the device's per-block
+// limit minus the kernel's static LDS. The attribute is raised once per kernel;
+// a refused request is cleared so that no sticky error is left in the runtime.
+static int dyn_lds_limit(const void* k) {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, k) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  const int dyn = lim - (int)fa.sharedSizeBytes;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return dyn;
+}
+
 template <int G, int NACC, int MODE, bool L3>
 static hipError_t launch_one_f(const SweepArgs& a, int grid, int block, size_t lds, hipStream_t st) {
   auto k = sweep_kernel<float, G, NACC, MODE, L3>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static int lim = -1;
+  if (lim < 0) lim = dyn_lds_limit(reinterpret_cast<const void*>(k));
+  if ((long long)lds > lim) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, st, a);
   return hipGetLastError();
 }
@@ -23,10 +42,13 @@ template <int G, int NACC, int MODE, bool L3>
 static int occ_one_f(int block, size_t lds) {
   int n = 0;
   auto k = sweep_kernel<float, G, NACC, MODE, L3>;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+  static int lim = -1;
+  if (lim < 0) lim = dyn_lds_limit(reinterpret_cast<const void*>(k));
+  if ((long long)lds > lim) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess) {
+    (void)hipGetLastError();
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess) return 0;
+  }
   return n;
 }
 

@@ -1,0 +1,239 @@
+// CPU emulation of the sweep kernel's data flow (2D and 3D layouts) driven by
+// the library's own host-side schedule builder, inflow/outflow stream ordering
+// and group coefficient tables (bte_setup.cpp), in FP64. Used by the CPU test
+// suite to check that host logic against the oracle without a GPU: it mirrors
+// what each lane reads (own previous value, the lane below, the previous strip's
+// ring, the boundary stream) at each clock step of the schedule.
+// Usage: sweep_emulator problem.bin [dJdT.bin]
+//   prints T after n iterations, or, with dJ/dT, the adjoint gradients.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../paper_2503_23657_amd/csrc/bte_setup.h"
+
+using namespace bte;
+
+int main(int argc, char** argv) {
+  FILE* fp = fopen(argv[1], "rb");
+  int hdr[8];
+  fread(hdr, 4, 8, fp);
+  int dim = hdr[0], n0 = hdr[1], n1 = hdr[2], n2 = hdr[3], B = hdr[4], M = hdr[5], nbc = hdr[6], iters = hdr[7];
+  double h[3];
+  fread(h, 8, 3, fp);
+  int G = 2, R = 2, P = 1, Cc = 16;
+  int pl[4];
+  fread(pl, 4, 4, fp);
+  G = pl[0]; R = pl[1]; P = pl[2]; Cc = pl[3];
+  int ncell = n0 * n1 * n2;
+  std::vector<uint8_t> mask(ncell), fbc(ncell * 6);
+  fread(mask.data(), 1, ncell, fp);
+  fread(fbc.data(), 1, ncell * 6, fp);
+  std::vector<int> bck(nbc);
+  std::vector<double> bcT(nbc), v(B), tau(B), C(B), s(3 * M), w(M), Q(ncell);
+  fread(bck.data(), 4, nbc, fp);
+  fread(bcT.data(), 8, nbc, fp);
+  fread(v.data(), 8, B, fp);
+  fread(tau.data(), 8, B, fp);
+  fread(C.data(), 8, B, fp);
+  fread(s.data(), 8, 3 * M, fp);
+  fread(w.data(), 8, M, fp);
+  fread(Q.data(), 8, ncell, fp);
+  double Tref;
+  fread(&Tref, 8, 1, fp);
+  fclose(fp);
+  bte_geometry g{};
+  g.dim = dim; g.n[0] = n0; g.n[1] = n1; g.n[2] = n2; g.h[0] = h[0]; g.h[1] = h[1]; g.h[2] = h[2];
+  g.h_mask = mask.data(); g.h_face_bc = fbc.data(); g.n_bc = nbc; g.h_bc_kind = bck.data(); g.h_bc_T = bcT.data();
+  bte_bands bb{B, v.data(), tau.data(), C.data()};
+  bte_quadrature qq{M, s.data(), w.data()};
+  std::string e = validate_problem(&g, &bb, &qq);
+  if (!e.empty()) { printf("invalid %s\n", e.c_str()); return 1; }
+  HostInst hi;
+  build_instance(&g, hi);
+  auto ords = fold_ordinates(&qq, dim);
+  Plan plan{G, R, P, Cc};
+  if (dim == 3) plan.R = 1;
+  Schedule S;
+  std::string err;
+  if (!build_schedule(hi, plan, S, err)) { printf("sched %s\n", err.c_str()); return 1; }
+  GroupSet gs = build_groups(ords, B, dim, G, P);
+  double t0 = tau[0];
+  for (double t : tau) t0 = std::min(t0, t);
+  std::vector<double> coef;
+  group_coefficients(gs, ords, hi, v, tau, C, t0, false, coef);
+  const int GS = grp_stride(G);
+  const bool L3 = dim == 3;
+  const int LJ = L3 ? 8 : 1, LK = L3 ? 8 : 64;
+  const int nbf = (int)hi.bf_cell.size();
+  // state
+  std::vector<double> X(ncell, 0.0);
+  std::vector<double> ubf((size_t)B * std::max(nbf, 1), 0.0);
+  for (int f = 0; f < nbf; ++f) {
+    const int bc = hi.bf_bc[f];
+    for (int b = 0; b < B; ++b) ubf[(size_t)b * nbf + f] = hi.bc_kind[bc] == 0 ? hi.bc_T[bc] - Tref : 0.0;
+  }
+  const int n_oct = S.n_oct, T = S.T, W = S.W;
+  const int nch = T / Cc;
+  std::vector<double> outv((size_t)gs.band.size() * S.n_out_stride, 0.0);
+  // one sweep: returns per-cell sums of wacc[0] and wacc[1] terms; optionally
+  // stores u (forward) or accumulates the tau-gradient sums (adjoint)
+  auto sweep = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
+                   bool adj, const std::vector<double>& ub, std::vector<double>& acc0, std::vector<double>& acc1,
+                   std::vector<double>* store, const std::vector<double>* stored, const std::vector<double>* dTf,
+                   std::vector<double>* tg) {
+    acc0.assign(ncell, 0.0);
+    acc1.assign(ncell, 0.0);
+    for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
+      const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
+      for (int p = 0; p < P; ++p) {
+        const int grp = gs.bundle_first[bu] + p;
+        const double* gt = cf.data() + (size_t)grp * GS;
+        const int band = gs.band[grp];
+        const double kS = gt[0], cQ = gt[1];
+        std::vector<std::vector<double>> f(R, std::vector<double>(64 * G, 0.0));
+        std::vector<std::vector<double>> zring(R, std::vector<double>((size_t)W * G, 0.0));
+        std::vector<double> yring((size_t)LK * W * G, 0.0);
+        std::vector<double> zg((size_t)std::max(S.ring, 1) * 8 * G, 0.0);
+        std::vector<int> in_cur(R, 0), out_cur(R, 0);
+        if (!L3)
+          for (int c = 0; c < W; ++c) {
+            const int sl = S.pre_slot[(size_t)o * W + c];
+            const double u = sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0;
+            for (int gg = 0; gg < G; ++gg) zring[R - 1][c * G + gg] = u * gt[go_den(G) + gg];
+          }
+        for (int tau_ = 0; tau_ < T; ++tau_) {
+          for (int r = 0; r < R; ++r) {
+            const int rprev = (r + R - 1) % R;
+            const int* ich = &S.in_chunk[((size_t)o * R + r) * (nch + 1)];
+            const int ch = tau_ / Cc;
+            if (tau_ % Cc == 0) in_cur[r] = 0;
+            std::vector<double> fold = f[r], fnew(64 * G), xu(64 * G), yu(64 * G), zu(64 * G);
+            std::vector<int2> ent(64);
+            for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)o * R + r) * T * 64 + (size_t)tau_ * 64 + l];
+            for (int l = 0; l < 64; ++l) {
+              const int jl = L3 ? (l & 7) : 0, kl = L3 ? (l >> 3) : l;
+              const unsigned fl = (unsigned)ent[l].y;
+              const int col = (fl >> F_COL_SHIFT) & F_COL_MASK;
+              for (int gg = 0; gg < G; ++gg) {
+                xu[l * G + gg] = fold[l * G + gg];
+                if (!L3) {
+                  zu[l * G + gg] = l == 0 ? zring[rprev][col * G + gg] : fold[(l - 1) * G + gg];
+                  yu[l * G + gg] = 0.0;
+                } else {
+                  yu[l * G + gg] = jl == 0 ? yring[(kl * W + col) * G + gg] : fold[(l - 1) * G + gg];
+                  if (kl == 0) {
+                    const int tt = tau_ - S.lag;
+                    zu[l * G + gg] = tt >= 0 ? zg[((size_t)(tt & (S.ring - 1)) * 8 + jl) * G + gg] : 0.0;
+                  } else zu[l * G + gg] = fold[(l - 8) * G + gg];
+                }
+              }
+            }
+            int k = ich[ch] + in_cur[r];
+            for (int l = 0; l < 64; ++l) {
+              const unsigned fl = (unsigned)ent[l].y;
+              for (int d = 0; d < 3; ++d)
+                if (fl & (F_IN_X << d)) {
+                  const double u = ub[(size_t)band * nbf + S.in_slot[k++]];
+                  in_cur[r]++;
+                  for (int gg = 0; gg < G; ++gg) {
+                    const double val = u * gt[go_den(G) + gg];
+                    if (d == 0) xu[l * G + gg] = val;
+                    else if (d == 1) { if (L3) yu[l * G + gg] = val; else zu[l * G + gg] = val; }
+                    else zu[l * G + gg] = val;
+                  }
+                }
+            }
+            for (int l = 0; l < 64; ++l) {
+              const int cid = ent[l].x;
+              const unsigned fl = (unsigned)ent[l].y;
+              const bool act = cid >= 0 && (fl & F_ACTIVE);
+              double a0 = 0.0, a1 = 0.0;
+              for (int gg = 0; gg < G; ++gg) {
+                const double S_ = kS * (cid >= 0 ? Xs[cid] : 0.0) + cQ * (act ? Qs[cid] : 0.0);
+                double fn;
+                if (L3) fn = gt[go_a(G, 2) + gg] * zu[l * G + gg] + gt[go_a(G, 1) + gg] * yu[l * G + gg] + gt[go_a(G, 0) + gg] * xu[l * G + gg] + S_;
+                else fn = gt[go_a(G, 1) + gg] * zu[l * G + gg] + gt[go_a(G, 0) + gg] * xu[l * G + gg] + S_;
+                fnew[l * G + gg] = fn;
+                a0 += gt[go_wacc(G, 0) + gg] * fn;
+                a1 += gt[go_wacc(G, 1) + gg] * fn;
+                if (act && store) (*store)[((size_t)grp * ncell + cid) * G + gg] = fn * gt[go_inv(G) + gg];
+                if (act && tg) {
+                  const double uf = (*stored)[((size_t)grp * ncell + cid) * G + gg];
+                  (*tg)[2 * grp] += gt[go_wt(G, 0) + gg] * fn * (uf - (*dTf)[cid]);
+                  (*tg)[2 * grp + 1] += Xs[cid] * gt[go_wt(G, 1) + gg] * uf;
+                }
+              }
+              if (act) { acc0[cid] += a0; acc1[cid] += a1; }
+              for (int d = 0; d < 3; ++d)
+                if (fl & (F_OUT_X << d)) {
+                  double vv = 0.0;
+                  for (int gg = 0; gg < G; ++gg) vv += gt[go_wo(G, d) + gg] * fnew[l * G + gg];
+                  outv[(size_t)grp * S.n_out_stride + S.out_base[o * R + r] + out_cur[r]++] = vv;
+                }
+            }
+            for (int l = 0; l < 64; ++l) {
+              const int jl = L3 ? (l & 7) : 0, kl = L3 ? (l >> 3) : l;
+              const int cid = ent[l].x;
+              const unsigned fl = (unsigned)ent[l].y;
+              const int col = (fl >> F_COL_SHIFT) & F_COL_MASK;
+              for (int gg = 0; gg < G; ++gg) {
+                if (!L3 && l == 63 && cid >= 0) zring[r][col * G + gg] = fnew[l * G + gg];
+                if (L3 && jl == 7 && cid >= 0) yring[(kl * W + col) * G + gg] = fnew[l * G + gg];
+                if (L3 && kl == 7) zg[((size_t)(tau_ & (S.ring - 1)) * 8 + jl) * G + gg] = fnew[l * G + gg];
+              }
+            }
+            f[r] = fnew;
+          }
+        }
+      }
+    }
+  };
+  std::vector<double> acc0, acc1;
+  for (int it = 0; it < iters; ++it) {
+    sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+    for (int df : hi.dface) {
+      for (int b = 0; b < B; ++b) {
+        double sacc = 0.0;
+        for (int o = 0; o < n_oct; ++o) {
+          const int k = S.ofk[(size_t)o * nbf + df];
+          if (k < 0) continue;
+          for (int gg = 0; gg < gs.ob_count[o * B + b]; ++gg)
+            sacc += outv[(size_t)(gs.ob_first[o * B + b] + gg) * S.n_out_stride + k];
+        }
+        ubf[(size_t)b * nbf + df] = sacc / half_range(ords, hi.bf_face[df] / 2);
+      }
+    }
+    X = acc0;
+  }
+  if (argc > 2) {
+    // adjoint with dJ/dT read from argv[2] (ncell doubles)
+    std::vector<double> g(ncell);
+    FILE* fg = fopen(argv[2], "rb");
+    fread(g.data(), 8, ncell, fg);
+    fclose(fg);
+    std::vector<double> store((size_t)gs.band.size() * ncell * G, 0.0);
+    sweep(X, Q, coef, false, ubf, acc0, acc1, &store, nullptr, nullptr, nullptr);
+    std::vector<double> ca;
+    group_coefficients(gs, ords, hi, v, tau, C, t0, true, ca);
+    std::vector<double> zero(ubf.size(), 0.0), lam = g, dumQ(ncell, 0.0);
+    for (int it = 0; it < iters; ++it) {
+      sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+      for (int c = 0; c < ncell; ++c) lam[c] = hi.active[c] ? g[c] + acc0[c] : 0.0;
+    }
+    std::vector<double> tg(2 * gs.band.size(), 0.0);
+    sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, &store, &X, &tg);
+    double D = 0.0;
+    for (int b = 0; b < B; ++b) D += C[b] / tau[b];
+    double L = 0.0;
+    for (int c = 0; c < ncell; ++c) if (hi.active[c]) L += lam[c] * X[c];
+    std::vector<double> T1(B, 0.0), T2(B, 0.0);
+    for (size_t k2 = 0; k2 < gs.band.size(); ++k2) { T1[gs.band[k2]] += tg[2 * k2]; T2[gs.band[k2]] += tg[2 * k2 + 1]; }
+    for (int b = 0; b < B; ++b) printf("dtau %.17g\n", (1.0 / tau[b]) * ((t0 / tau[b]) * T1[b] - T2[b] + C[b] / (tau[b] * D) * L));
+    for (int c = 0; c < ncell; ++c) printf("dQ %.17g\n", acc1[c]);
+    return 0;
+  }
+  for (int c = 0; c < ncell; ++c) printf("%.17g\n", hi.active[c] ? X[c] + Tref : 0.0);
+  return 0;
+}

@@ -1,0 +1,95 @@
+"""Host logic of the HIP library, checked on the CPU: the schedule builder, the
+boundary inflow/outflow stream ordering and the group coefficient tables of
+``paper_2503_23657_amd/csrc/bte_setup.cpp`` drive a CPU emulation of the sweep
+kernel's data flow (tests/emu/sweep_emulator.cpp), whose result must match the
+FP64 oracle; the adjoint tables and the dJ/dtau formula must match reverse mode
+through the unrolled PyTorch oracle."""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+import bte_inputs as bi
+import oracle
+from oracle import unrolled
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+EMU_SRC = os.path.join(HERE, "emu", "sweep_emulator.cpp")
+BUILD = os.path.join(ROOT, "paper_2503_23657_amd", "_build")
+EMU = os.path.join(BUILD, "sweep_emulator")
+
+
+@pytest.fixture(scope="module")
+def emu():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    os.makedirs(BUILD, exist_ok=True)
+    subprocess.check_call([hipcc, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950", "-o", EMU, EMU_SRC,
+                           os.path.join(ROOT, "paper_2503_23657_amd", "csrc", "bte_setup.cpp")])
+    return EMU
+
+
+def _write(p, iters, plan, path):
+    with open(path, "wb") as f:
+        f.write(struct.pack("8i", p.dim, *p.n, p.B, p.M, len(p.bc_kind), iters))
+        f.write(np.array(p.h, dtype=np.float64).tobytes())
+        f.write(struct.pack("4i", *plan))
+        f.write(p.mask.astype(np.uint8).tobytes())
+        f.write(p.face_bc.astype(np.uint8).tobytes())
+        f.write(p.bc_kind.astype(np.int32).tobytes())
+        f.write(p.bc_T.astype(np.float64).tobytes())
+        for a in (p.v, p.tau, p.C, p.s.reshape(-1), p.w, p.Q):
+            f.write(np.asarray(a, np.float64).tobytes())
+        f.write(struct.pack("d", p.T_ref))
+
+
+CASES = [
+    ("film", lambda: bi.film_1d(n_cells=50, n_mu=8), 5, (1, 1, 1, 16)),
+    ("square_r1", lambda: bi.square_2d(20, L=0.1e-6, n_bands=3, n_theta=2, n_phi=1), 4, (2, 1, 1, 16)),
+    ("square_r2", lambda: bi.square_2d(100, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 3, (2, 2, 1, 16)),
+    ("square_r3_p2", lambda: bi.square_2d(150, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 2, (4, 3, 2, 8)),
+    ("box_diffuse", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1), 5, (2, 1, 1, 16)),
+    ("box3d_diffuse", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4, (2, 1, 1, 8)),
+    ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8)),
+]
+
+
+@pytest.mark.parametrize("name,make,iters,plan", CASES, ids=[c[0] for c in CASES])
+def test_emulated_sweep_matches_oracle(emu, tmp_path, name, make, iters, plan):
+    p = make()
+    path = str(tmp_path / "in.bin")
+    _write(p, iters, plan, path)
+    out = subprocess.run([emu, path], capture_output=True, text=True, check=True).stdout.split()
+    T = np.array([float(x) for x in out])
+    r = oracle.solve(p, tol=0.0, max_iters=iters)
+    act = p.mask > 0
+    assert np.abs(T[act] - r["T"][act]).max() < 1e-11 * np.abs(r["T"][act] - p.T_ref).max()
+
+
+@pytest.mark.parametrize("plan", [(2, 1, 1, 16), (4, 1, 1, 8)])
+def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
+    p = bi.square_2d(8, L=0.06e-6, n_bands=3, n_theta=1, n_phi=1)
+    iters = 400
+    probes = np.arange(3, p.ncell, 7)[:6]
+    base = unrolled.Unrolled(p).run(torch.tensor(p.tau), torch.tensor(p.Q), iters).numpy()
+    target = base[probes] + 0.05
+
+    def loss_t(T):
+        return ((T[torch.as_tensor(probes)] - torch.as_tensor(target)) ** 2).mean()
+
+    gt, gq, T = unrolled.grad_unrolled(p, loss_t, iters)
+    Tt = torch.tensor(T, requires_grad=True)
+    loss_t(Tt).backward()
+    gpath = str(tmp_path / "g.bin")
+    Tt.grad.numpy().astype(np.float64).tofile(gpath)
+    path = str(tmp_path / "in.bin")
+    _write(p, iters, plan, path)
+    out = subprocess.run([emu, path, gpath], capture_output=True, text=True, check=True).stdout.split("\n")
+    dtau = np.array([float(l.split()[1]) for l in out if l.startswith("dtau")])
+    dQ = np.array([float(l.split()[1]) for l in out if l.startswith("dQ")])
+    assert np.abs(dtau - gt).max() < 1e-8 * np.abs(gt).max()
+    assert np.abs(dQ - gq).max() < 1e-10 * np.abs(gq).max()

@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--batch-kn-min", type=float, default=0.3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -122,6 +123,38 @@ def main():
         extra["adjoint_solve_s"] = ta
         extra["adjoint_iters"] = ra["iters"]
         log(f"adjoint/forward = {ta / tf:.3f} ({ra['iters']} vs {rf['iters']} iterations)")
+
+    if not args.no_extra:
+        # batched solves/s vs a sequential loop of single solves at equal accuracy
+        insts = [q for q in bi.batch_instances() if q.Kn >= args.batch_kn_min]
+        tol_b = 1e-6
+        Qs = [torch.tensor(q.Q, dtype=torch.float64, device=dev) for q in insts]
+        bs = bte.BatchSolver(insts, precision="fp32")
+        bs.solve(Qs, tol=tol_b, check_every=8)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ts, _, reps = bs.solve(Qs, tol=tol_b, check_every=8)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        singles = [bte.Solver(q, precision="fp32", plan=bs.plan()) for q in insts]
+        for s1, q1 in zip(singles, Qs):
+            s1.solve(q1, tol=tol_b, check_every=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        worst = 0.0
+        for s1, q1, Tb in zip(singles, Qs, Ts):
+            T1, _, _ = s1.solve(q1, tol=tol_b, check_every=8)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for s1, q1, Tb, q in zip(singles, Qs, Ts, insts):
+            T1, _, _ = s1.solve(q1, tol=tol_b, check_every=8)
+            worst = max(worst, float((T1 - Tb).abs().max() / (Tb - 300.0).abs().max()))
+        n_ok = sum(r["status"] == "ok" for r in reps)
+        extra["batch"] = dict(instances=len(insts), kn_min=args.batch_kn_min, converged=n_ok, tol=tol_b,
+                              batched_solves_per_s=len(insts) / tb, sequential_solves_per_s=len(insts) / ts,
+                              speedup=ts / tb, max_rel_diff_batched_vs_single=worst,
+                              iters_min=min(r["iters"] for r in reps), iters_max=max(r["iters"] for r in reps))
+        log(f"batch: {len(insts)} instances, {len(insts)/tb:.1f} solves/s batched vs {len(insts)/ts:.1f} sequential")
 
     out = {
         "metric": "cell-ordinate-band updates/s",

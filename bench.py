@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--batch-kn-min", type=float, default=0.3)
+    ap.add_argument("--plan", type=str, default=None,
+                    help="fixed kernel plan 'G,R,P,NR' instead of the autotuned one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -73,7 +75,12 @@ def main():
     M_swept = 64
     solver = bte.Solver(p, precision="fp32")
     Q = torch.tensor(p.Q, dtype=torch.float64, device=dev)
-    plan = solver.autotune(Q, n_iters=5)
+    if args.plan:
+        G_, R_, P_, NR_ = (int(x) for x in args.plan.split(","))
+        solver.set_plan(G=G_, R=R_, P=P_, NR=NR_)
+        plan = solver.plan()
+    else:
+        plan = solver.autotune(Q, n_iters=5)
     log("plan", plan)
     K = max(8, args.steps)
     # warm-up (also captures the graphs)

@@ -33,7 +33,7 @@ __all__ = [
     "BC_ISOTHERMAL", "BC_DIFFUSE", "BC_SPECULAR", "NO_BC", "Problem",
     "band_table_synthetic", "band_table_gray", "quad_gl_mu", "quad_octant_gl",
     "face_bc_from_mask", "gaussian_source", "film_1d", "square_2d", "finfet_3d",
-    "adjoint_case", "batch_instances", "scattering_mfp", "random_box_2d", "random_box_3d",
+    "adjoint_case", "batch_instances", "scattering_mfp", "random_box_2d", "random_box_3d", "multi_hole_2d",
 ]
 
 
@@ -285,6 +285,21 @@ def random_box_2d(nx, ny, seed, n_bands=3, n_theta=2, n_phi=1, hole=True, kinds=
     return Problem("random_box_2d", 2, n, (dx, dx, dx), mask, fbc,
                    np.array([BC_ISOTHERMAL, kinds[1]], dtype=np.int32),
                    np.array(T_walls, dtype=np.float64), v, tau, C, s, w, Q, 300.0)
+
+
+def multi_hole_2d(nx, ny, seed, n_holes=8, **kw):
+    """random_box_2d without its hole but with several seeded inactive blocks,
+    so that holes fall inside a lane's rows, across lanes and next to strip
+    boundaries of the 2D sweep layouts."""
+    p = random_box_2d(nx, ny, seed, hole=False, **kw)
+    rng = np.random.default_rng(seed + 100)
+    m = p.mask.reshape(ny, nx).copy()
+    for _ in range(n_holes):
+        hx, hy = int(rng.integers(1, nx - 3)), int(rng.integers(1, ny - 4))
+        m[hy:hy + int(rng.integers(1, 4)), hx:hx + int(rng.integers(1, 3))] = 0
+    mask = m.reshape(-1).astype(np.uint8)
+    fbc = face_bc_from_mask(p.n, 2, mask, lambda i, j, k, f: 0 if (f == 2 and j == 0) else 1)
+    return p.replace(name="multi_hole_2d", mask=mask, face_bc=fbc, Q=p.Q * mask)
 
 
 def random_box_3d(nx, ny, nz, seed, n_bands=2, n_theta=1, n_phi=1, hole=True, kinds=(0, 1),

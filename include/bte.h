@@ -89,12 +89,18 @@ typedef struct {
 } bte_quadrature;
 
 /* Kernel shape of the sweep (chosen by bte_autotune, or set by hand).
-   G: ordinates per lane (1, 2, 4 or 8); R: waves per workgroup that pipeline
-   successive 64-row strips (2D/1D only; 1..16); P: waves per workgroup that
-   sweep different ordinate groups of one quadrant in lockstep and share one
-   partial sum per cell (1..8); C: steps between workgroup barriers (4..64,
-   multiple of 4). Zero fields mean "library default". */
-typedef struct { int G, R, P, C; } bte_plan;
+   G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D: 1, 2 or 4).
+   R: 1D/2D only, waves per workgroup that pipeline successive strips of
+      64*NR rows (R*P <= 8); 3D: always 1.
+   P: waves per workgroup that sweep different ordinate groups of one octant
+      in lockstep and add their partial sums per cell before writing them
+      (1D/2D: 1, 2, 4 or 8; 3D: 1..8; R*P <= 8).
+   C: 3D only, steps between workgroup barriers (multiple of 8 in 8..64 and of
+      P); 1D/2D always use chunks of 8 steps.
+   NR: 1D/2D only, rows owned by each lane of a strip (1, 2 or 4).
+   Zero fields mean "keep the current value". A shape whose LDS need exceeds
+   the per-workgroup limit is rejected with BTE_ERR_INVALID. */
+typedef struct { int G, R, P, C, NR; } bte_plan;
 
 typedef struct {
   double tol_T;        /* target eps_T (Eq. 22, normalised by max |T - T_ref|); <= 0: run max_iters */

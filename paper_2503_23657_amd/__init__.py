@@ -49,10 +49,11 @@ class Quadrature(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("G", ctypes.c_int), ("R", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int)]
+    _fields_ = [("G", ctypes.c_int), ("R", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int),
+                ("NR", ctypes.c_int)]
 
     def as_dict(self):
-        return dict(G=self.G, R=self.R, P=self.P, C=self.C)
+        return dict(G=self.G, R=self.R, P=self.P, C=self.C, NR=self.NR)
 
 
 class Opts(ctypes.Structure):
@@ -237,8 +238,8 @@ class Solver:
         except Exception:
             pass
 
-    def set_plan(self, G=0, R=0, P=0, C=0):
-        pl = Plan(G, R, P, C)
+    def set_plan(self, G=0, R=0, P=0, C=0, NR=0):
+        pl = Plan(G, R, P, C, NR)
         _check(bte_set_plan(self._h, ctypes.byref(pl)))
 
     def plan(self) -> dict:
@@ -308,7 +309,7 @@ class BatchSolver:
                                 ctypes.byref(self._hps[0].quad), self.T_ref, self.prec, ctypes.byref(h)))
         self._h = h
         if plan:
-            pl = Plan(plan.get("G", 0), plan.get("R", 0), plan.get("P", 0), plan.get("C", 0))
+            pl = Plan(plan.get("G", 0), plan.get("R", 0), plan.get("P", 0), plan.get("C", 0), plan.get("NR", 0))
             _check(bte_set_plan(self._h, ctypes.byref(pl)))
 
     def close(self):

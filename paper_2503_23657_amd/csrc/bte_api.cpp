@@ -111,6 +111,7 @@ struct Inst {
   int* d_pos = nullptr;
   int* d_in_slot = nullptr;
   int* d_in_chunk = nullptr;
+  int* d_in_tab = nullptr;
   int* d_out_base = nullptr;
   int* d_pre_slot = nullptr;
   int* d_ofk = nullptr;
@@ -205,17 +206,36 @@ double total_D(const bte_ctx* h) {
 // (Re)build everything that depends on the plan or on tau.
 bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   Plan pl = pl_in;
-  if (h->dim == 3) pl.R = 1;
-  if (pl.G != 1 && pl.G != 2 && pl.G != 4) {
-    set_err("plan G must be 1, 2 or 4");
-    return BTE_ERR_INVALID;
+  const bool L3 = h->dim == 3;
+  if (L3) {
+    pl.R = 1;
+    pl.NR = 1;
+    if (pl.G != 1 && pl.G != 2 && pl.G != 4) {
+      set_err("plan G must be 1, 2 or 4");
+      return BTE_ERR_INVALID;
+    }
+    if (pl.C < 8 || pl.C > 64 || pl.C % 8 || pl.C % pl.P) {
+      set_err("plan C must be a multiple of 8 in 8..64 and of P");
+      return BTE_ERR_INVALID;
+    }
+  } else {
+    // the 1D/2D kernel works in chunks of kC2 steps
+    pl.C = kC2;
+    if (pl.G != 1 && pl.G != 2) {
+      set_err("plan G must be 1 or 2 in 1D/2D");
+      return BTE_ERR_INVALID;
+    }
+    if (pl.NR != 1 && pl.NR != 2 && pl.NR != 4) {
+      set_err("plan NR must be 1, 2 or 4");
+      return BTE_ERR_INVALID;
+    }
+    if (pl.P != 1 && pl.P != 2 && pl.P != 4 && pl.P != 8) {
+      set_err("plan P must be 1, 2, 4 or 8 in 1D/2D");
+      return BTE_ERR_INVALID;
+    }
   }
   if (pl.R < 1 || pl.P < 1 || pl.R * pl.P > 8) {
     set_err("plan needs R >= 1, P >= 1, R*P <= 8");
-    return BTE_ERR_INVALID;
-  }
-  if (pl.C < 8 || pl.C > 64 || pl.C % 8 || pl.C % pl.P) {
-    set_err("plan C must be a multiple of 8 in 8..64 and of P");
     return BTE_ERR_INVALID;
   }
   clear_graphs(h);
@@ -264,6 +284,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     HIPCHK(pp.upload(&I.d_pos, S.pos));
     HIPCHK(pp.upload(&I.d_in_slot, S.in_slot));
     HIPCHK(pp.upload(&I.d_in_chunk, S.in_chunk));
+    HIPCHK(pp.upload(&I.d_in_tab, S.in_tab));
     HIPCHK(pp.upload(&I.d_out_base, S.out_base));
     HIPCHK(pp.upload(&I.d_pre_slot, S.pre_slot));
     HIPCHK(pp.upload(&I.d_ofk, S.ofk));
@@ -326,6 +347,11 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       d.lag = S.lag;
       d.ring = S.ring;
       d.n_out_stride = S.n_out_stride;
+      d.nr = S.NR;
+      d.du = S.du;
+      d.n_strip = S.nS;
+      d.in_E = S.in_E;
+      d.in_tab = I.d_in_tab;
     }
     for (int b = 0; b < n_bund; ++b) {
       const int o = gs.bundle_oct[b];
@@ -354,13 +380,57 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     h->d_gt_a = pb;
   }
   // LDS carve-up
-  const bool L3 = h->dim == 3;
   const int R = L3 ? 1 : pl.R, P = pl.P, G = pl.G, Cc = pl.C;
   h->nacc_max = std::max(1 + h->dim, 2);
   auto al = [](size_t x) { return (x + 15) / 16 * 16; };
   size_t off = 0;
   SweepArgs& sa = h->sa;
   memset(&sa, 0, sizeof(sa));
+  if (!L3) {
+    // 1D/2D: ring [P][R][W_max + 1][G], cell ids [2][R][kC2][64], inflow
+    // [P*R][2][E], outflow [P*R][o_max], staging [planes][P*R][kC2][64*NR + 4]
+    // with max(2, nacc) planes (double-buffered for the temperature-only sweep)
+    int E = 64;
+    for (auto& I : h->inst) E = std::max(E, I.sch.in_E);
+    sa.lds_zring = (int)off;
+    off += al((size_t)P * R * (W_max + 1) * G * es);
+    sa.lds_cid = (int)off;
+    off += al((size_t)2 * R * kC2 * 64 * 4);
+    sa.lds_in = (int)off;
+    off += al((size_t)P * R * 2 * E * es);
+    sa.lds_out = (int)off;
+    off += al((size_t)P * R * o_max * es);
+    sa.lds_stage = (int)off;
+    h->lds_stage_plane = al((size_t)P * R * kC2 * (64 * pl.NR + 4) * es);
+    off += (size_t)std::max(2, h->nacc_max) * h->lds_stage_plane;
+    sa.lds_total = (int)off;
+    if (off > 160 * 1024 - 64) {
+      set_err("plan needs %zu bytes of LDS (limit 160 KiB): reduce P, R, NR or G", off);
+      return BTE_ERR_INVALID;
+    }
+    h->lds = off;
+    sa.inst = h->d_inst_f;
+    sa.jobs = h->d_jobs_f;
+    sa.n_jobs = h->n_jobs;
+    sa.counters = h->d_counters;
+    sa.grp_i = h->d_gi_f;
+    sa.grp_t = h->d_gt_f;
+    sa.B = h->B;
+    sa.R = R;
+    sa.P = P;
+    sa.C = kC2;
+    sa.zring_len = W_max;
+    sa.W_max = W_max;
+    sa.e_max = E;
+    sa.o_max = o_max;
+    h->block = R * P * 64;
+    int bpc = sweep2d_blocks_per_cu(prec, G, pl.NR, 1, SWEEP_PLAIN, h->block,
+                                    sa.lds_stage + 2 * h->lds_stage_plane);
+    if (bpc < 1) bpc = 1;
+    h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
+    h->plan = pl;
+    return BTE_OK;
+  }
   sa.lds_zring = (int)off;
   off += al(L3 ? 0 : (size_t)P * R * W_max * G * es);
   sa.lds_yring = (int)off;
@@ -550,21 +620,25 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
     pl.R = 1;
     pl.P = 4;
     pl.C = 8;
-  } else if (h->dim == 1) {
+    pl.NR = 1;
+  } else {
+    // one strip of 64*NR rows covers ny <= 256; P waves share the partial sums
+    int ny = 1;
+    for (auto& I : h->inst) ny = std::max(ny, I.hi.n[1]);
     pl.G = 1;
     pl.R = 1;
-    pl.P = 1;
-    pl.C = 16;
-  } else {
-    pl.G = precision == BTE_PREC_FP32 ? 4 : 2;
-    pl.R = std::min(8, std::max(1, (h->inst[0].hi.n[1] + 63) / 64));
-    pl.P = 1;
-    pl.C = 16;
+    pl.NR = ny <= 64 ? 1 : ny <= 128 ? 2 : 4;
+    pl.P = precision == BTE_PREC_FP32 ? 4 : 2;
+    pl.C = kC2;
   }
   s = build_plan(h.get(), pl);
-  if (s != BTE_OK && pl.C > 8) {
+  if (s != BTE_OK && h->dim == 3 && pl.C > 8) {
     // boundary-rich geometries need shorter chunks for the inflow stream buffer
     pl.C = 8;
+    s = build_plan(h.get(), pl);
+  }
+  if (s != BTE_OK && h->dim < 3 && pl.P > 1) {
+    pl.P = 1;
     s = build_plan(h.get(), pl);
   }
   if (s != BTE_OK) return s;
@@ -585,8 +659,13 @@ bte_status enqueue_sweep(bte_ctx* h, bool adj, int nacc, int mode, int force, hi
   a.grp_i = adj ? h->d_gi_a : h->d_gi_f;
   a.grp_t = adj ? h->d_gt_a : h->d_gt_f;
   a.force = force;
+  if (h->dim < 3) {
+    const size_t lds = (size_t)a.lds_stage + (size_t)std::max(2, nacc) * h->lds_stage_plane;
+    HIPCHK(launch_sweep2d(h->precision, h->plan.G, h->plan.NR, nacc, mode, a, h->grid, h->block, lds, st));
+    return BTE_OK;
+  }
   const size_t lds = (size_t)a.lds_stage + (size_t)nacc * h->lds_stage_plane;
-  HIPCHK(launch_sweep(h->precision, h->dim == 3, h->plan.G, nacc, mode, a, h->grid, h->block, lds, st));
+  HIPCHK(launch_sweep(h->precision, true, h->plan.G, nacc, mode, a, h->grid, h->block, lds, st));
   return BTE_OK;
 }
 
@@ -940,6 +1019,7 @@ bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
   if (plan->R) p.R = plan->R;
   if (plan->P) p.P = plan->P;
   if (plan->C) p.C = plan->C;
+  if (plan->NR) p.NR = plan->NR;
   const Plan old = h->plan;
   bte_status s = build_plan(h, p);
   if (s != BTE_OK) {
@@ -959,6 +1039,7 @@ bte_status bte_get_plan(bte_handle h, bte_plan* plan) {
   plan->R = h->plan.R;
   plan->P = h->plan.P;
   plan->C = h->plan.C;
+  plan->NR = h->plan.NR;
   return BTE_OK;
 }
 
@@ -1191,19 +1272,21 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<Plan> cand;
-  const int Gs[3] = {1, 2, 4};
-  const int Cs[3] = {8, 16, 32};
   if (h->dim == 3) {
-    for (int G : Gs)
+    for (int G : {1, 2, 4})
       for (int P : {1, 2, 4, 8})
-        for (int C : Cs) cand.push_back(Plan{G, 1, P, C});
+        for (int C : {8, 16, 32}) cand.push_back(Plan{G, 1, P, C, 1});
   } else {
-    const int nS = (h->inst[0].hi.n[1] + 63) / 64;
-    for (int G : Gs)
-      for (int R = 1; R <= std::min(8, nS); R *= 2)
-        for (int P : {1, 2, 4})
-          for (int C : Cs)
-            if (R * P <= 8) cand.push_back(Plan{G, R, P, C});
+    int ny = 1;
+    for (auto& I : h->inst) ny = std::max(ny, I.hi.n[1]);
+    for (int NR : {1, 2, 4}) {
+      if (NR > 1 && 32 * NR >= ny) continue;  // mostly idle rows
+      const int nS = (ny + 64 * NR - 1) / (64 * NR);
+      for (int G : {1, 2})
+        for (int R = 1; R <= std::min(8, nS); R *= 2)
+          for (int P : {1, 2, 4, 8})
+            if (R * P <= 8) cand.push_back(Plan{G, R, P, kC2, NR});
+    }
   }
   const Plan keep = h->plan;
   double best_ms = 1e300;
@@ -1227,6 +1310,7 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
     best->R = bestp.R;
     best->P = bestp.P;
     best->C = bestp.C;
+    best->NR = bestp.NR;
   }
   return BTE_OK;
 }

@@ -9,9 +9,51 @@
 
 namespace bte {
 
+// Sum over the jobs j = js, js + kFinSlices, ... of one partial-sum plane for
+// cell c, in FP64 with four loads in flight; the association is fixed, so the
+// result does not depend on timing.
 template <typename T>
-__global__ void __launch_bounds__(256) finalize_kernel(FinArgs A, const FinInst* FI) {
-  __shared__ double red[4][256];
+__device__ __forceinline__ double job_sum(const T* pl, int n_jobs, int ncell, int c, int js) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = js;
+  for (; j + 3 * kFinSlices < n_jobs; j += 4 * kFinSlices) {
+    s0 += (double)pl[(size_t)j * ncell + c];
+    s1 += (double)pl[(size_t)(j + kFinSlices) * ncell + c];
+    s2 += (double)pl[(size_t)(j + 2 * kFinSlices) * ncell + c];
+    s3 += (double)pl[(size_t)(j + 3 * kFinSlices) * ncell + c];
+  }
+  for (; j < n_jobs; j += kFinSlices) s0 += (double)pl[(size_t)j * ncell + c];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Block-wide reduction of (sum, max, sum, max) over the block's threads;
+// every thread calls it; the result is valid in thread 0.
+__device__ __forceinline__ void block_reduce4(double (*red)[kFinThreads], double v[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[i][t] = v[i];
+  __syncthreads();
+  for (int s = kFinThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] += red[0][t + s];
+      red[1][t] = fmax(red[1][t], red[1][t + s]);
+      red[2][t] += red[2][t + s];
+      red[3][t] = fmax(red[3][t], red[3][t + s]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = red[i][0];
+}
+
+// New state (Eq. updatee0_t: Delta T, or the adjoint lambda), heat flux (Eq. 4)
+// or dJ/dQ, and the residuals of Eq. 22. A block covers kFinCells cells with
+// kFinSlices threads per cell, each adding a slice of the jobs' partial sums.
+template <typename T>
+__global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const FinInst* FI) {
+  __shared__ double red[4][kFinThreads];
+  __shared__ double slc[4][kFinSlices][kFinCells];
+  __shared__ int s_last;
   const int2 bi = A.blocks[blockIdx.x];
   const InstDev& I = A.inst[bi.x];
   const FinInst& F = FI[bi.x];
@@ -19,15 +61,24 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs A, const FinInst*
   if (st->done) return;
   const int iter = st->iter;
   const int cur = iter & 1, nxt = cur ^ 1;
-  const int c = bi.y * 256 + threadIdx.x;
+  const int cl = threadIdx.x % kFinCells, js = threadIdx.x / kFinCells;
+  const int c = bi.y * kFinCells + cl;
   const size_t plane = (size_t)I.n_jobs * I.ncell;
   const T* part = reinterpret_cast<const T*>(I.part);
-  double sT = 0.0, mT = 0.0, sq = 0.0, mq = 0.0;
-  bool bad = false;
-  if (c < I.ncell) {
-    if (F.active[c]) {
-      double x = (A.flags & FIN_ADJ) ? F.g[c] : 0.0;
-      for (int j = 0; j < I.n_jobs; ++j) x += (double)part[(size_t)j * I.ncell + c];
+  const bool adj = (A.flags & FIN_ADJ) != 0, withq = (A.flags & FIN_Q) != 0;
+  const int nq = withq ? (adj ? 1 : I.dim) : 0;
+  const bool act = c < I.ncell && F.active[c];
+  // ---- the job slices of every needed plane
+  if (act) {
+    slc[0][js][cl] = job_sum(part, I.n_jobs, I.ncell, c, js);
+    for (int d = 0; d < nq; ++d) slc[1 + d][js][cl] = job_sum(part + (size_t)(1 + d) * plane, I.n_jobs, I.ncell, c, js);
+  }
+  __syncthreads();
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // sum dT^2, max |x|, sum d|q|^2, max |q| (+inf: non-finite)
+  if (js == 0 && c < I.ncell) {
+    if (act) {
+      double x = adj ? F.g[c] : 0.0;
+      x += (slc[0][0][cl] + slc[0][1][cl]) + (slc[0][2][cl] + slc[0][3][cl]);
       const double old = F.X[cur][c];
       F.X[nxt][c] = x;
       // scatter into the skewed layouts of every octant
@@ -36,34 +87,31 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs A, const FinInst*
         const int ps = I.pos[(size_t)o * I.ncell + c];
         xq[2 * ((size_t)o * I.pos_per_oct + ps)] = (T)x;
       }
-      bad = !isfinite(x);
+      bool bad = !isfinite(x);
       const double d = x - old;
-      sT = d * d;
-      mT = fabs(x);
-      if (A.flags & FIN_Q) {
-        if (A.flags & FIN_ADJ) {
-          double v = 0.0;
-          for (int j = 0; j < I.n_jobs; ++j) v += (double)part[plane + (size_t)j * I.ncell + c];
-          F.q[c] = v;
+      v[0] = d * d;
+      v[1] = fabs(x);
+      if (withq) {
+        if (adj) {
+          F.q[c] = (slc[1][0][cl] + slc[1][1][cl]) + (slc[1][2][cl] + slc[1][3][cl]);
         } else {
           double m2 = 0.0;
           for (int d2 = 0; d2 < I.dim; ++d2) {
-            double v = 0.0;
-            const T* pl = part + (size_t)(1 + d2) * plane;
-            for (int j = 0; j < I.n_jobs; ++j) v += (double)pl[(size_t)j * I.ncell + c];
-            F.q[(size_t)c * I.dim + d2] = v;
-            m2 += v * v;
-            bad = bad || !isfinite(v);
+            const double qv = (slc[1 + d2][0][cl] + slc[1 + d2][1][cl]) + (slc[1 + d2][2][cl] + slc[1 + d2][3][cl]);
+            F.q[(size_t)c * I.dim + d2] = qv;
+            m2 += qv * qv;
+            bad = bad || !isfinite(qv);
           }
           const double qm = sqrt(m2);
           if (A.flags & FIN_QPREV) {
             const double dq = qm - F.qmag_prev[c];
-            sq = dq * dq;
+            v[2] = dq * dq;
           }
-          mq = qm;
+          v[3] = qm;
           F.qmag_prev[c] = qm;
         }
       }
+      if (bad) v[3] = INFINITY;
     } else {
       F.X[nxt][c] = 0.0;
     }
@@ -82,60 +130,51 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs A, const FinInst*
     }
     return;
   }
-  red[0][threadIdx.x] = sT;
-  red[1][threadIdx.x] = mT;
-  red[2][threadIdx.x] = sq;
-  red[3][threadIdx.x] = mq + (bad ? INFINITY : 0.0);
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
-      red[2][threadIdx.x] += red[2][threadIdx.x + s];
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-    }
-    __syncthreads();
-  }
+  block_reduce4(red, v);
+  const int nb = A.n_blocks_inst[bi.x];
   if (threadIdx.x == 0) {
     double* bp = F.blockpart + (size_t)bi.y * 4;
-    bp[0] = red[0][0];
-    bp[1] = red[1][0];
-    bp[2] = red[2][0];
-    bp[3] = red[3][0];
+    bp[0] = v[0];
+    bp[1] = v[1];
+    bp[2] = v[2];
+    bp[3] = v[3];
     __threadfence();
-    const int nb = A.n_blocks_inst[bi.x];
-    const int t = atomicAdd(&st->ticket, 1);
-    if (t == nb - 1) {
-      __threadfence();
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (int b = 0; b < nb; ++b) {
-        const volatile double* q = F.blockpart + (size_t)b * 4;
-        a0 += q[0];
-        a1 = fmax(a1, q[1]);
-        a2 += q[2];
-        a3 = fmax(a3, q[3]);
-      }
-      // active cell count is stored by the host in red[0] of the status block
-      const double nact = st->red[0];
-      const double rT = sqrt(a0 / nact), rq = sqrt(a2 / nact);
-      const double eT = a1 > 0.0 ? rT / a1 : (rT == 0.0 ? 0.0 : INFINITY);
-      double eq = a3 > 0.0 ? rq / a3 : (rq == 0.0 ? 0.0 : INFINITY);
-      if (!(A.flags & FIN_Q) || (A.flags & FIN_ADJ)) eq = 0.0;
-      const bool nonfin = !isfinite(a1) || !isfinite(a3) || !isfinite(a0);
-      st->iter = iter + 1;
-      if (A.flags & FIN_CHECK) {
-        st->eps_T = eT;
-        st->eps_q = eq;
-        st->checked = iter + 1;
-        if (A.tol_T > 0.0 && A.tol_q > 0.0 && eT < A.tol_T && eq < A.tol_q) st->done = 1;
-      }
-      if (nonfin) {
-        st->nonfinite = 1;
-        st->done = 1;
-      }
-      st->ticket = 0;
-      __threadfence();
+    s_last = atomicAdd(&st->ticket, 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // the last block of the instance reduces the block partials (fixed order per
+  // thread, fixed tree across threads)
+  __threadfence();
+  double w[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kFinThreads) {
+    const volatile double* q = F.blockpart + (size_t)b * 4;
+    w[0] += q[0];
+    w[1] = fmax(w[1], q[1]);
+    w[2] += q[2];
+    w[3] = fmax(w[3], q[3]);
+  }
+  block_reduce4(red, w);
+  if (threadIdx.x == 0) {
+    const double a0 = w[0], a1 = w[1], a2 = w[2], a3 = w[3];
+    // active cell count is stored by the host in red[0] of the status block
+    const double nact = st->red[0];
+    const double rT = sqrt(a0 / nact), rq = sqrt(a2 / nact);
+    const double eT = a1 > 0.0 ? rT / a1 : (rT == 0.0 ? 0.0 : INFINITY);
+    double eq = a3 > 0.0 ? rq / a3 : (rq == 0.0 ? 0.0 : INFINITY);
+    if (!withq || adj) eq = 0.0;
+    const bool nonfin = !isfinite(a1) || !isfinite(a3) || !isfinite(a0);
+    st->iter = iter + 1;
+    st->eps_T = eT;
+    st->eps_q = eq;
+    st->checked = iter + 1;
+    if (A.tol_T > 0.0 && A.tol_q > 0.0 && eT < A.tol_T && eq < A.tol_q) st->done = 1;
+    if (nonfin) {
+      st->nonfinite = 1;
+      st->done = 1;
     }
+    st->ticket = 0;
+    __threadfence();
   }
 }
 
@@ -248,9 +287,9 @@ static inline int nblk(long long n) { return (int)((n + 255) / 256); }
 hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st) {
   if (a.n_blocks_total <= 0) return hipSuccess;
   if (prec == BTE_PREC_FP32)
-    hipLaunchKernelGGL(finalize_kernel<float>, dim3(a.n_blocks_total), dim3(256), 0, st, a, fi);
+    hipLaunchKernelGGL(finalize_kernel<float>, dim3(a.n_blocks_total), dim3(kFinThreads), 0, st, a, fi);
   else
-    hipLaunchKernelGGL(finalize_kernel<double>, dim3(a.n_blocks_total), dim3(256), 0, st, a, fi);
+    hipLaunchKernelGGL(finalize_kernel<double>, dim3(a.n_blocks_total), dim3(kFinThreads), 0, st, a, fi);
   return hipGetLastError();
 }
 

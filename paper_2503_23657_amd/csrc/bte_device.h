@@ -48,6 +48,23 @@ constexpr uint32_t F_OUT_Z = 1u << 6;
 constexpr int F_COL_SHIFT = 7;
 constexpr uint32_t F_COL_MASK = 0xFFFFu;
 
+// 1D/2D sweep (rows-per-lane layout): a lane owns NR consecutive rows of a
+// strip of 64*NR rows; the per-(step, lane) record is int2 {cid0 << 4 | am,
+// flags} where cid0 is the cell of the lane's first row and bit k of am says
+// that row k is an active cell (-1: no cell), and flags holds 5 bits per row k
+// at bit 5k (active, inflow x/y, outflow x/y) and, at bit 20, the
+// chunk-relative offset of the lane's first inflow entry.
+constexpr int kC2 = 8;                 // steps per chunk
+constexpr int kPad2 = 8;               // schedule padding steps (prefetch runs ahead)
+constexpr uint32_t F2_ACT = 1u << 0;
+constexpr uint32_t F2_INX = 1u << 1;
+constexpr uint32_t F2_INY = 1u << 2;
+constexpr uint32_t F2_OUTX = 1u << 3;
+constexpr uint32_t F2_OUTY = 1u << 4;
+constexpr int F2_ROW_BITS = 5;
+constexpr int F2_INOFF_SHIFT = 20;
+constexpr uint32_t F2_INOFF_MASK = 0xFFu;
+
 // group coefficient record: GS(G) values of the sweep type, in this order
 //   kS, cQ, a[3][G], den[G], wacc[kNAcc][G], wo[3][G], wt[2][G], inv[G]
 __host__ __device__ constexpr int grp_stride(int G) { return 2 + G * (3 + 1 + kNAcc + 3 + 2 + 1); }
@@ -92,7 +109,12 @@ struct InstDev {
   int lag;                  // 3D: clock lag between a z-front write and its read
   int ring;                 // 3D: global z-ring length in steps (power of two)
   int n_out_stride;         // stride of one group's row of outv
-  int pad1;
+  // 1D/2D rows-per-lane schedule
+  int nr;                   // rows per lane
+  int du;                   // clock distance between the starts of consecutive strips
+  int n_strip;              // strips of 64*nr rows
+  int in_E;                 // entries per chunk row of in_tab (multiple of 64, <= 256)
+  const int* in_tab;        // [n_oct][R][T/kC2 + 2][in_E] inflow face slot of each stream entry (-1 pad)
 };
 
 // Job: instance, first group of the bundle (global index), instance-local job
@@ -145,6 +167,9 @@ struct SweepArgs {
 
 // ---------------------------------------------------------------- aux kernels
 enum { FIN_Q = 1, FIN_CHECK = 2, FIN_ADJ = 4, FIN_QPREV = 8 };
+constexpr int kFinCells = 256;                        // cells per finalize block
+constexpr int kFinSlices = 4;                         // job slices per cell
+constexpr int kFinThreads = kFinCells * kFinSlices;   // threads per finalize block
 
 struct FinArgs {
   const InstDev* inst;

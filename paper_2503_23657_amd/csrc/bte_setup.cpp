@@ -280,7 +280,193 @@ static int next_pow2(int x) {
   return p;
 }
 
+// 1D/2D schedule of the rows-per-lane sweep. Lane l of wave slot r owns rows
+// 64*NR*s + NR*l + k (k < NR) of strip s and processes column i of it at clock
+// step t = s*du + l + i (strips r, r+R, ... belong to slot r). Positions of
+// the (X, Q) layout: ((r*Tp + t)*64 + l)*NR + k with Tp = T + kPad2.
+// Inflow entries: per step, lanes in order, rows k ascending, x before y.
+// Outflow entries: per step, rows k ascending, axis x before y, lanes in order.
+static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err) {
+  const int NR = plan.NR, R = plan.R, C = kC2;
+  if (NR != 1 && NR != 2 && NR != 4) {
+    err = "plan NR must be 1, 2 or 4";
+    return false;
+  }
+  const int dim = hi.dim;
+  const int nx = hi.n[0], ny = dim >= 2 ? hi.n[1] : 1;
+  const int H = 64 * NR;
+  const int nS = (ny + H - 1) / H;
+  const int V = nx;
+  const int du = R == 1 ? std::max(V, 63 + C) : std::max(63 + C, (V + R - 1) / R);
+  int T = (nS - 1) * du + V + 63;
+  T = (T + C - 1) / C * C;
+  const int Tp = T + kPad2;
+  s.T = T;
+  s.R = R;
+  s.C = C;
+  s.W = nx;
+  s.NR = NR;
+  s.du = du;
+  s.nS = nS;
+  s.lag = 0;
+  s.ring = 0;
+  s.n_oct = 1 << dim;
+  s.pos_per_oct = (long long)R * Tp * 64 * NR;
+  if (s.pos_per_oct * s.n_oct > (1ll << 31) - 1) {
+    err = "schedule too large";
+    return false;
+  }
+  const int n_oct = s.n_oct;
+  const int nch = T / C;
+  const int nbf = (int)hi.bf_cell.size();
+  s.sched.assign((size_t)n_oct * R * Tp * 64, make_int2(-1, 0));
+  s.pos.assign((size_t)n_oct * hi.ncell, -1);
+  s.in_slot.clear();
+  s.in_chunk.assign((size_t)n_oct * R * (nch + 1), 0);
+  s.out_base.assign((size_t)n_oct * R, 0);
+  s.ofk.assign((size_t)n_oct * std::max(nbf, 1), -1);
+  s.pre_slot.assign((size_t)n_oct * nx, -1);
+  s.e_max = 1;
+  s.o_max = 1;
+  int n_out_max = 1;
+  // strip and column of slot r at lane-relative clock q; false when idle
+  auto strip_at = [&](int r, int q, int& sidx, int& v) {
+    if (q < 0) return false;
+    if (R == 1) {
+      sidx = q / du;
+    } else {
+      const int m = q / du;
+      sidx = m - ((m - r) % R + R) % R;
+      if (sidx < 0) return false;
+    }
+    v = q - sidx * du;
+    return sidx < nS && v < V;
+  };
+  std::vector<int> out_face(64 * NR * 2);
+  for (int o = 0; o < n_oct; ++o) {
+    const bool fx = o & 1, fy = (o >> 1) & 1;
+    const int up[2] = {fx ? 1 : 0, fy ? 3 : 2};
+    const int dn[2] = {fx ? 0 : 1, fy ? 2 : 3};
+    int out_count = 0;
+    for (int r = 0; r < R; ++r) {
+      s.out_base[o * R + r] = out_count;
+      int* chk = &s.in_chunk[((size_t)o * R + r) * (nch + 1)];
+      int out_k = 0;
+      for (int tau = 0; tau < T; ++tau) {
+        if (tau % C == 0) chk[tau / C] = (int)s.in_slot.size();
+        int sidx, v;
+        std::fill(out_face.begin(), out_face.end(), -1);
+        for (int l = 0; l < 64; ++l) {
+          if (!strip_at(r, tau - l, sidx, v)) continue;
+          const int ip = v;
+          const int ix = fx ? nx - 1 - ip : ip;
+          unsigned fl = 0;
+          int cid0 = -1;
+          const int in_first = (int)s.in_slot.size() - chk[tau / C];
+          bool any_in = false;
+          for (int k = 0; k < NR; ++k) {
+            const int kp = sidx * H + l * NR + k;
+            if (kp >= ny) break;
+            const int iy = dim >= 2 ? (fy ? ny - 1 - kp : kp) : 0;
+            const int cell = ix + nx * iy;
+            if (k == 0) cid0 = cell;
+            if (!hi.active[cell]) continue;
+            const int sh = F2_ROW_BITS * k;
+            fl |= F2_ACT << sh;
+            s.pos[(size_t)o * hi.ncell + cell] = (int)((((long long)r * Tp + tau) * 64 + l) * NR + k);
+            for (int d = 0; d < dim; ++d) {
+              const int su = hi.bslot[(size_t)cell * 6 + up[d]];
+              if (su < 0) continue;
+              if (d == 1 && kp == 0) {
+                // strip 0, lane 0, row 0: the lane-0 ghost is prefilled with this face
+                s.pre_slot[(size_t)o * nx + ip] = su;
+              } else {
+                fl |= (F2_INX << d) << sh;
+                s.in_slot.push_back(su);
+                any_in = true;
+              }
+            }
+            for (int d = 0; d < dim; ++d) {
+              const int sd = hi.bslot[(size_t)cell * 6 + dn[d]];
+              if (sd >= 0 && hi.bc_kind[hi.bf_bc[sd]] == BTE_BC_DIFFUSE) {
+                fl |= (F2_OUTX << d) << sh;
+                out_face[(k * 2 + d) * 64 + l] = sd;
+              }
+            }
+          }
+          if (any_in) {
+            if (in_first > (int)F2_INOFF_MASK) {
+              err = "too many boundary inflows per chunk";
+              return false;
+            }
+            fl |= (unsigned)in_first << F2_INOFF_SHIFT;
+          }
+          int am = 0;
+          for (int k = 0; k < NR; ++k) am |= (int)((fl >> (F2_ROW_BITS * k)) & F2_ACT) << k;
+          s.sched[(((size_t)o * R + r) * Tp + tau) * 64 + l] = make_int2(cid0 >= 0 ? (cid0 << 4) | am : -1, (int)fl);
+        }
+        for (int kd = 0; kd < NR * 2; ++kd)
+          for (int l = 0; l < 64; ++l) {
+            const int sd = out_face[kd * 64 + l];
+            if (sd < 0) continue;
+            s.ofk[(size_t)o * nbf + sd] = out_count + out_k;
+            ++out_k;
+          }
+      }
+      chk[nch] = (int)s.in_slot.size();
+      for (int ch = 0; ch < nch; ++ch) s.e_max = std::max(s.e_max, chk[ch + 1] - chk[ch]);
+      out_count += out_k;
+    }
+    n_out_max = std::max(n_out_max, out_count);
+  }
+  for (int o = 0; o < n_oct; ++o)
+    for (int r = 0; r < R; ++r)
+      for (int ch = 0; ch < nch; ++ch) {
+        int cnt = 0;
+        for (int tau = ch * C; tau < (ch + 1) * C; ++tau)
+          for (int l = 0; l < 64; ++l) {
+            const unsigned fl = (unsigned)s.sched[(((size_t)o * R + r) * Tp + tau) * 64 + l].y;
+            for (int k = 0; k < NR; ++k) {
+              const unsigned b = fl >> (F2_ROW_BITS * k);
+              cnt += ((b & F2_OUTX) != 0) + ((b & F2_OUTY) != 0);
+            }
+          }
+        s.o_max = std::max(s.o_max, cnt);
+      }
+  s.n_out_stride = n_out_max;
+  if (s.e_max > 256) {
+    err = "too many boundary inflows per chunk";
+    return false;
+  }
+  if (s.o_max > 256) {
+    err = "too many diffuse-wall outflows per chunk";
+    return false;
+  }
+  // per-chunk inflow table, two padding chunk rows at the end of every slot
+  s.in_E = std::max(64, (s.e_max + 63) / 64 * 64);
+  s.in_tab.assign((size_t)n_oct * R * (nch + 2) * s.in_E, -1);
+  for (int o = 0; o < n_oct; ++o)
+    for (int r = 0; r < R; ++r) {
+      const int* chk = &s.in_chunk[((size_t)o * R + r) * (nch + 1)];
+      for (int ch = 0; ch < nch; ++ch)
+        for (int e = chk[ch]; e < chk[ch + 1]; ++e)
+          s.in_tab[(((size_t)o * R + r) * (nch + 2) + ch) * s.in_E + (e - chk[ch])] = s.in_slot[e];
+    }
+  if ((long long)hi.ncell >= (1ll << 27)) {
+    err = "too many cells for the 1D/2D sweep (limit 2^27)";
+    return false;
+  }
+  for (int o = 0; o < n_oct; ++o)
+    for (int c = 0; c < hi.ncell; ++c)
+      if (hi.active[c] && s.pos[(size_t)o * hi.ncell + c] < 0) {
+        err = "internal: cell missing from the schedule";
+        return false;
+      }
+  return true;
+}
+
 bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err) {
+  if (hi.dim < 3) return build_schedule_2d(hi, plan, s, err);
   const bool L3 = hi.dim == 3;
   const int LJ = L3 ? 8 : 1, LK = L3 ? 8 : 64;
   const int R = L3 ? 1 : plan.R;

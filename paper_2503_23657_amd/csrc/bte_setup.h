@@ -21,6 +21,7 @@ struct Ordinate {
 
 struct Plan {
   int G = 4, R = 4, P = 1, C = 16;
+  int NR = 1;  // 1D/2D: rows per lane (1, 2 or 4)
 };
 
 // One problem instance on the host.
@@ -52,8 +53,12 @@ struct GroupSet {
 };
 
 // Schedule of an instance for one plan (see bte_device.h).
+//   3D: sched[n_oct][R][T][64] (cell, flags F_*), positions (slot*T + t)*64 + l;
+//   1D/2D: sched[n_oct][R][T + kPad2][64] (cid0, flags F2_*), positions
+//          ((slot*(T + kPad2) + t)*64 + l)*NR + k, and the per-chunk inflow table.
 struct Schedule {
   int T = 0, n_oct = 0, R = 1, C = 16, W = 0, lag = 0, ring = 0;
+  int NR = 1, du = 0, nS = 0;
   int e_max = 0, o_max = 0;
   long long pos_per_oct = 0;
   std::vector<int2> sched;           // [n_oct][R][T][64] (cell, flags)
@@ -63,6 +68,8 @@ struct Schedule {
   std::vector<int> out_base;         // [n_oct][R]
   std::vector<int> ofk;              // [n_oct][n_bface]
   std::vector<int> pre_slot;         // 2D: [n_oct][W]
+  std::vector<int> in_tab;           // 1D/2D: [n_oct][R][T/C + 2][in_E]
+  int in_E = 64;
   int n_out_stride = 1;              // max out-stream length over octants
 };
 

@@ -1,0 +1,513 @@
+// 1D/2D transport sweep kernel for gfx950 (MI355X), rows-per-lane layout.
+//
+// One launch performs one source-iteration sweep (paper Methods, "Iterative
+// matrix formulation and solution scheme", step 2): for every (band,
+// direction) pair the first-order upwind system A e = b (Eqs. Axb, A_matrix with
+// first-order faces) is solved exactly by one pass in upwind order, and in the
+// same pass the band/direction sums of Eq. updatee0_t (new lattice temperature)
+// and Eq. 4 (heat flux) are accumulated, plus the outgoing partial currents of
+// the diffuse walls (Eq. 6).
+//
+// Work decomposition:
+//   * lane l of a wave owns NR consecutive rows (64*NR rows per strip) and
+//     sweeps them along x with a skew of one step per lane: at step t it
+//     updates column t - l of its rows, bottom row first, so the upwind y value
+//     of row k is row k-1 of the same step and, for row 0, the top row of lane
+//     l-1 from the previous step, moved with one DPP wave shift;
+//   * lane 0's upwind row (the previous strip, or the bottom wall) comes from a
+//     column-indexed LDS ring; the ring values of a whole chunk of kC2 steps are
+//     read once per chunk into one register (lane m holds step m) and taken
+//     with readlane, so no step waits on LDS;
+//   * the per-step inputs, a record {cell of row 0, flags} and the (X, Q) pairs
+//     of the lane's rows, are stored in the skewed order and prefetched a whole
+//     chunk ahead (fp32; half a chunk in fp64) without any conditional, the
+//     schedule being padded; no load inside the chunk loop depends on another
+//     one, so the loads stay in flight across steps and chunks;
+//   * boundary inflows are an ordered stream whose chunk values sit in LDS
+//     (gathered two chunks ahead from a padded per-chunk table); a lane finds
+//     its entries from the offset stored in its record;
+//   * the P waves of a workgroup sweep P ordinate groups of one octant in
+//     lockstep; per step each wave stages its per-row sums over its G ordinates
+//     in LDS, and after each chunk the P partials of every cell are added in a
+//     fixed order and written as contiguous row segments (one barrier per chunk,
+//     double-buffered staging for the temperature-only sweep);
+//   * the R wave slots of a workgroup pipeline successive strips (slot r owns
+//     strips r, r+R, ...), the top rows reaching the next slot through its ring.
+#include <hip/hip_runtime.h>
+
+#include "bte_device.h"
+
+namespace bte {
+namespace s2d {
+
+#define GAS __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ GAS T* gp(T* p) {
+  return (GAS T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GAS T* gp(const T* p) {
+  return (const GAS T*)p;
+}
+
+template <typename T, int N>
+struct Vec {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
+typedef int iv2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int2 ldrec(const GAS int2* p) {
+  const iv2_t v = *(const GAS iv2_t*)p;
+  return make_int2(v.x, v.y);
+}
+
+// DPP wave_shr:1 (GFX9 encoding 0x138): lane i takes lane i-1, lane 0 keeps `old`.
+__device__ __forceinline__ float shr1(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double shr1(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Workgroup barrier for LDS traffic only: wait for this wave's LDS operations,
+// then meet the other waves. Outstanding global loads (the prefetch) keep
+// flying across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unchanged
+  __builtin_amdgcn_s_barrier();
+}
+
+// Strip and column of wave slot r at lane-relative clock q (strips r, r+R, ...
+// of the slot start du steps apart); false when the slot is idle at q.
+__device__ __forceinline__ bool strip_at(int q, int r, int R, int du, int n_strip, int nx, int& s, int& v) {
+  if (q < 0) return false;
+  const int m = q / du;
+  s = R == 1 ? m : m - ((m - r) % R + R) % R;
+  if (s < 0) return false;
+  v = q - s * du;
+  return s < n_strip && v < nx;
+}
+
+// the flag bits `bits` repeated for rows 0..nr-1
+constexpr unsigned rowmask(unsigned bits, int nr) {
+  unsigned m = 0;
+  for (int k = 0; k < nr; ++k) m |= bits << (F2_ROW_BITS * k);
+  return m;
+}
+
+}  // namespace s2d
+
+enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2 };
+
+template <typename T, int G, int NR, int NACC, int MODE>
+__global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
+  using namespace s2d;
+  // prefetch distance in steps (divides kC2): a chunk for small records, half
+  // a chunk when one lane-step reads 32 bytes or more
+  constexpr int KD = sizeof(T) * 2 * NR >= 32 ? 4 : 8;
+  constexpr int NV = 2 * NR;                  // (X, Q) values of one lane-step
+  using VX = typename Vec<T, NV>::type;
+  using VR = typename Vec<T, NR>::type;
+  constexpr int GS = grp_stride(G);
+  constexpr int RS = 64 * NR + 4;             // staged row stride (elements)
+  constexpr int kEPL = 4;                     // inflow entries per lane per chunk (<= 256)
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_job;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int R = A.R, P = A.P;
+  const int r = wave % R;
+  const int p = wave / R;
+  const int rprev = (r + R - 1) % R;
+  const int W_max = A.W_max;
+  const int E = A.e_max;  // LDS inflow buffer entries per chunk (multiple of 64)
+
+  T* ring = reinterpret_cast<T*>(lds + A.lds_zring);    // [P][R][W_max + 1][G] (+1: dummy slot)
+  int* scid = reinterpret_cast<int*>(lds + A.lds_cid);  // [2][R][kC2][64]
+  T* inb = reinterpret_cast<T*>(lds + A.lds_in);        // [P*R][2][E]
+  T* outb = reinterpret_cast<T*>(lds + A.lds_out);      // [P*R][o_max]
+  T* stage = reinterpret_cast<T*>(lds + A.lds_stage);   // [planes][P*R][kC2][RS]
+  const int plane_sz = P * R * kC2 * RS;
+  const int RW = (W_max + 1) * G;  // ring slot stride
+  T* my_ring = ring + (size_t)(p * R + r) * RW;
+  const T* prev_ring = ring + (size_t)(p * R + rprev) * RW;
+  T* my_inb = inb + (size_t)(p * R + r) * 2 * E;
+  T* my_outb = outb + (size_t)(p * R + r) * A.o_max;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_job = atomicAdd(&A.counters[0], 1);
+    __syncthreads();
+    const int job = s_job;
+    if (job >= A.n_jobs) break;
+    const JobDev jd = A.jobs[job];
+    const InstDev& I = A.inst[jd.inst];
+    const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+    if (!A.force && st->done) continue;
+    const int iter = st->iter;
+
+    // ---- this wave's group: band constants and per-ordinate coefficients
+    const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
+    const int4 gi = A.grp_i[g_glob];
+    const int band = gi.x;
+    const int g_loc = gi.z;
+    const T* gt = reinterpret_cast<const T*>(A.grp_t) + (size_t)g_glob * GS;
+    const T kS = gt[0], cQ = gt[1];
+    T a0[G], a1[G], den[G], inv[G], wo0[G], wo1[G];
+    T wacc[NACC][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      a0[g] = gt[go_a(G, 0) + g];
+      a1[g] = gt[go_a(G, 1) + g];
+      den[g] = gt[go_den(G) + g];
+      inv[g] = gt[go_inv(G) + g];
+      wo0[g] = gt[go_wo(G, 0) + g];
+      wo1[g] = gt[go_wo(G, 1) + g];
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) wacc[a][g] = gt[go_wacc(G, a) + g];
+    }
+
+    const int o = jd.oct;
+    const int T_steps = I.T;
+    const int Tp = T_steps + kPad2;
+    const int nch = T_steps / kC2;
+    const int nx = I.nx, ny = I.ny;
+    const int du = I.du, n_strip = I.n_strip;
+    const int H = 64 * NR;
+    const int dy = (o & 2) ? -nx : nx;  // cell-index step from row k to row k+1
+    const long long slot = (long long)o * R + r;
+    // uniform bases; lanes add 32-bit offsets
+    const GAS int2* REC = gp(I.sched + slot * Tp * 64);
+    const GAS VX* XQ = gp(reinterpret_cast<const VX*>(I.xq[iter & 1]) + slot * Tp * 64);
+    const GAS VX* XF = MODE == M2_TAUGRAD ? gp(reinterpret_cast<const VX*>(I.xf) + slot * Tp * 64) : nullptr;
+    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
+    const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
+    const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
+    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[slot]);
+    const size_t part_plane = (size_t)I.n_jobs * I.ncell;
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.ncell);
+
+    // ---- clear the ring; prefill the ring read by strip 0 (slot R-1's) with
+    //      the bottom-wall inflow of every column
+    for (int e = lane; e < RW; e += 64) my_ring[e] = T(0);
+    __syncthreads();
+    if (r == 0) {
+      T* zr = ring + (size_t)(p * R + (R - 1)) * RW;
+      const GAS int* pre = gp(I.pre_slot + (size_t)o * I.W);
+      for (int c = lane; c < I.W; c += 64) {
+        const int sl = pre[c];
+        const T u = sl >= 0 ? UBF[sl] : T(0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) zr[c * G + g] = u * den[g];
+      }
+    }
+
+    // ---- inflow stream: the values of chunk k sit in LDS buffer (k & 1); the
+    //      values of chunk k+1 and the face slots of chunk k+2 wait in registers
+    const int NE = Ei >> 6;
+    int slot_n[kEPL];
+    T inval[kEPL];
+#pragma unroll
+    for (int m = 0; m < kEPL; ++m) {
+      if (m < NE) {
+        const int s0 = ITAB[m * 64 + lane];
+        my_inb[m * 64 + lane] = s0 >= 0 ? UBF[s0] : T(0);
+        const int s1 = ITAB[Ei + m * 64 + lane];
+        inval[m] = s1 >= 0 ? UBF[s1] : T(0);
+        slot_n[m] = ITAB[2 * Ei + m * 64 + lane];
+      } else {
+        inval[m] = T(0);
+        slot_n[m] = -1;
+      }
+    }
+    __syncthreads();
+
+    // ---- per-lane state
+    T f[G][NR];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) f[g][k] = T(0);
+    double tg0 = 0.0, tg1 = 0.0;
+    int out_tot = 0;
+
+    int2 RR[KD];
+    VX RX[KD];
+    VX RXF[KD];
+#pragma unroll
+    for (int u = 0; u < KD; ++u) {
+      RR[u] = ldrec(REC + u * 64 + lane);
+      RX[u] = XQ[u * 64 + lane];
+      if (MODE == M2_TAUGRAD) RXF[u] = XF[u * 64 + lane];
+    }
+
+    // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
+    // row; the dummy slot W_max when there is nothing to write) of a chunk:
+    // lane m < kC2 holds step m's
+    T ghv[G];
+    int wcv;
+    auto chunk_cols = [&](int ch) {
+      int s, v, gc = -1, wc = -1;
+      if (lane < kC2) {
+        const int q = ch * kC2 + lane;
+        if (strip_at(q, r, R, du, n_strip, nx, s, v)) gc = v;
+        if (strip_at(q - 63, r, R, du, n_strip, nx, s, v) && s * H + H - 1 < ny) wc = v;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) ghv[g] = gc >= 0 ? prev_ring[gc * G + g] : T(0);
+      wcv = (wc >= 0 ? wc : W_max) * G;
+    };
+    chunk_cols(0);
+
+    for (int ch = 0; ch < nch; ++ch) {
+      const int bufi = ch & 1;
+      const T* inbuf = my_inb + bufi * E;
+      T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
+      int* scw = scid + (bufi * R + r) * kC2 * 64;
+      int out_cnt = 0;
+
+#pragma unroll
+      for (int u = 0; u < kC2; ++u) {
+        const int sl = u % KD;
+        const int tau = ch * kC2 + u;
+        const int2 rec = RR[sl];
+        const VX xq = RX[sl];
+        VX xf;
+        if (MODE == M2_TAUGRAD) xf = RXF[sl];
+        const unsigned fl = (unsigned)rec.y;
+        T S[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) S[k] = kS * xq[2 * k] + cQ * xq[2 * k + 1];
+
+        // upwind value of row 0: the lane below's top row of the previous step;
+        // lane 0 takes the ring value of this step
+        T zc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), f[g][NR - 1]);
+
+        constexpr unsigned kInAll = rowmask(F2_INX | F2_INY, NR);
+        if (__ballot(fl & kInAll) != 0ull) {
+          // entries of this lane: rows ascending, x before y, from its offset
+          const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const unsigned b = fl >> (F2_ROW_BITS * k);
+            const unsigned below = fl & kInAll & ((1u << (F2_ROW_BITS * k)) - 1u);
+            const int ex = e0 + __builtin_popcount(below);
+            const int ey = ex + ((b & F2_INX) ? 1 : 0);
+            const T vx = inbuf[min(ex, E - 1)];
+            const T vy = inbuf[min(ey, E - 1)];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const T xu = (b & F2_INX) ? vx * den[g] : f[g][k];
+              const T zu = (b & F2_INY) ? vy * den[g] : zc[g];
+              const T fn = fma(a1[g], zu, fma(a0[g], xu, S[k]));
+              f[g][k] = fn;
+              zc[g] = fn;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const T fn = fma(a1[g], zc[g], fma(a0[g], f[g][k], S[k]));
+              f[g][k] = fn;
+              zc[g] = fn;
+            }
+        }
+
+        // ---- fused band/direction sums of the rows, staged for the workgroup
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+          VR acc;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            T sm = T(0);
+#pragma unroll
+            for (int g = 0; g < G; ++g) sm = fma(wacc[a][g], f[g][k], sm);
+            acc[k] = sm;
+          }
+          *reinterpret_cast<VR*>(stg0 + (size_t)(NACC == 1 ? 0 : a) * plane_sz + u * RS + lane * NR) = acc;
+        }
+        if (p == 0) scw[u * 64 + lane] = rec.x;
+
+        // ---- the strip's top row for the next slot (lane 63)
+        const int wc = rdlane(wcv, u);
+        if (lane == 63) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) my_ring[wc + g] = f[g][NR - 1];
+        }
+
+        // ---- diffuse-wall outflow stream: rows, then axes, then lanes
+        constexpr unsigned kOutAll = rowmask(F2_OUTX | F2_OUTY, NR);
+        if (__ballot(fl & kOutAll) != 0ull) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+              const unsigned bit = (F2_OUTX << d) << (F2_ROW_BITS * k);
+              const unsigned long long m = __ballot(fl & bit);
+              if (m != 0ull) {
+                if (fl & bit) {
+                  T v = T(0);
+#pragma unroll
+                  for (int g = 0; g < G; ++g) v = fma(d == 0 ? wo0[g] : wo1[g], f[g][k], v);
+                  my_outb[out_cnt + lanes_below(m)] = v;
+                }
+                out_cnt += __popcll(m);
+              }
+            }
+          }
+        }
+
+        // ---- stored angular field / tau-gradient sums
+        if (MODE == M2_STORE && rec.x >= 0) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
+              GAS T* su =
+                  gp(reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 4) + k * dy) * G);
+#pragma unroll
+              for (int g = 0; g < G; ++g) su[g] = f[g][k] * inv[g];
+            }
+        }
+        if (MODE == M2_TAUGRAD && rec.x >= 0) {
+          const T* wt0 = gt + go_wt(G, 0);
+          const T* wt1 = gt + go_wt(G, 1);
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
+              const GAS T* su =
+                  gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 4) + k * dy) * G);
+              double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const double uf = (double)su[g];
+                s0 += (double)wt0[g] * (double)f[g][k] * (uf - (double)xf[2 * k]);
+                s1 += (double)wt1[g] * uf;
+              }
+              tg0 += s0;
+              tg1 += (double)xq[2 * k] * s1;
+            }
+        }
+
+        // ---- prefetch step tau + KD into the slot just consumed (the schedule
+        //      is padded by kPad2 >= KD steps, so the read is always in bounds);
+        //      the fence keeps the loads after the last use of the old values,
+        //      so every slot is reloaded in place
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          const long long tn = (long long)(tau + KD) * 64;  // uniform part of the address
+          RR[sl] = ldrec(REC + tn + lane);
+          const GAS VX* xb = XQ + tn;
+          RX[sl] = xb[lane];
+          if (MODE == M2_TAUGRAD) {
+            const GAS VX* fb = XF + tn;
+            RXF[sl] = fb[lane];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+
+      // ---- end of chunk: the staged sums, the ring and the outflow entries
+      //      of every wave are complete
+      lds_barrier();
+      chunk_cols(ch + 1);
+      {
+        // the P waves of slot r add their partials in a fixed order and write
+        // contiguous row segments: entry e -> row e/8, step e%8 (a loop of
+        // compile-time trip count keeps the compiler's count of outstanding
+        // memory operations exact, so the steps never drain the prefetch;
+        // kept rolled to spare registers)
+        const int t = p * 64 + lane;
+        const int per = (kC2 * NR) / P;
+        const int* scr = scid + (bufi * R + r) * kC2 * 64;
+#pragma unroll 1
+        for (int m = 0; m < kC2 * NR; ++m) {
+          if (m < per) {
+            const int e = m * (P * 64) + t;
+            const int row = e >> 3, cc = e & 7;
+            const int ln = row / NR, k = row % NR;
+            const int v = scr[cc * 64 + ln];
+            if (v >= 0 && ((v >> k) & 1)) {
+              const int cid = (v >> 4) + k * dy;
+#pragma unroll
+              for (int a = 0; a < NACC; ++a) {
+                const T* sp = stage + (size_t)(NACC == 1 ? bufi : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + row;
+                T sum = sp[0];
+                for (int q = 1; q < P; ++q) sum += sp[(size_t)q * R * kC2 * RS];
+                PARTJ[a * part_plane + cid] = sum;
+              }
+            }
+          }
+        }
+      }
+      // flush this chunk's outflow entries (at most 256)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (lane + 64 * m < out_cnt) OUTV[out_tot + lane + 64 * m] = my_outb[lane + 64 * m];
+      out_tot += out_cnt;
+      // inflow pipeline: values of chunk ch+1 to LDS; gather chunk ch+2's
+      // values; load the face slots of chunk ch+3 (padded table: in bounds)
+#pragma unroll
+      for (int m = 0; m < kEPL; ++m) {
+        if (m < NE) {
+          my_inb[((ch + 1) & 1) * E + m * 64 + lane] = inval[m];
+          inval[m] = slot_n[m] >= 0 ? UBF[slot_n[m]] : T(0);
+          slot_n[m] = ch + 3 < nch + 2 ? ITAB[(ch + 3) * Ei + m * 64 + lane] : -1;
+        }
+      }
+      if (NACC > 1) lds_barrier();  // single-buffered staging: wait for every reader
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    if (MODE == M2_TAUGRAD) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        tg0 += __shfl_xor(tg0, off);
+        tg1 += __shfl_xor(tg1, off);
+      }
+      // the R slots share the group: add them in slot order
+      GAS double* tgp = gp(I.tgrad + (size_t)g_loc * 2);
+      for (int rr = 0; rr < R; ++rr) {
+        if (r == rr && lane == 0) {
+          tgp[0] += tg0;
+          tgp[1] += tg1;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // the last workgroup out resets the queue counters for the next launch
+  if (tid == 0) {
+    const int e = atomicAdd(&A.counters[1], 1);
+    if (e == (int)gridDim.x - 1) {
+      atomicExch(&A.counters[0], 0);
+      atomicExch(&A.counters[1], 0);
+    }
+  }
+}
+
+}  // namespace bte

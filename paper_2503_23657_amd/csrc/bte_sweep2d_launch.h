@@ -1,0 +1,78 @@
+// Instantiation and dispatch of the 1D/2D sweep kernel for one precision
+// (included once by bte_sweep2d_f.hip and once by bte_sweep2d_d.hip).
+#pragma once
+#include "bte_sweep2d.hip"
+#include "bte_launch.h"
+
+namespace bte {
+
+// Largest dynamic LDS a launch of kernel k may request: the device's per-block
+// limit minus the kernel's static LDS. The attribute is raised once per kernel;
+// a refused request is cleared so that no sticky error is left in the runtime.
+static inline int dyn_lds_limit_2d(const void* k) {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, k) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  const int dyn = lim - (int)fa.sharedSizeBytes;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return dyn;
+}
+
+template <typename T, int G, int NR, int NACC, int MODE>
+static hipError_t launch2d_one(const SweepArgs& a, int grid, int block, size_t lds, hipStream_t st) {
+  auto k = sweep2d_kernel<T, G, NR, NACC, MODE>;
+  static int lim = -1;
+  if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
+  if ((long long)lds > lim) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int G, int NR, int NACC, int MODE>
+static int occ2d_one(int block, size_t lds) {
+  int n = 0;
+  auto k = sweep2d_kernel<T, G, NR, NACC, MODE>;
+  static int lim = -1;
+  if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
+  if ((long long)lds > lim) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+// compiled variants: G in {1, 2}, NR in {1, 2, 4}; (NACC, mode) in
+// {(1..3, plain), (1, store), (2, tau-gradient)}
+#define BTE2D_KEY(G_, NR_, N_, M_) ((G_) * 1000 + (NR_) * 100 + (N_) * 10 + (M_))
+#define BTE2D_CASE(T_, G_, NR_, N_, M_, FN, ...) \
+  case BTE2D_KEY(G_, NR_, N_, M_): return FN<T_, G_, NR_, N_, M_>(__VA_ARGS__);
+#define BTE2D_CASES_NR(T_, G_, NR_, FN, ...)     \
+  BTE2D_CASE(T_, G_, NR_, 1, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 2, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 3, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 1, 1, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 2, 2, FN, __VA_ARGS__)
+#define BTE2D_DISPATCH(T_, FN, ...)                          \
+  switch (BTE2D_KEY(G, NR, nacc, mode)) {                    \
+    BTE2D_CASES_NR(T_, 1, 1, FN, __VA_ARGS__)                \
+    BTE2D_CASES_NR(T_, 1, 2, FN, __VA_ARGS__)                \
+    BTE2D_CASES_NR(T_, 1, 4, FN, __VA_ARGS__)                \
+    BTE2D_CASES_NR(T_, 2, 1, FN, __VA_ARGS__)                \
+    BTE2D_CASES_NR(T_, 2, 2, FN, __VA_ARGS__)                \
+    BTE2D_CASES_NR(T_, 2, 4, FN, __VA_ARGS__)                \
+    default: break;                                          \
+  }
+
+}  // namespace bte

@@ -62,11 +62,6 @@ static int occ_one_d(int block, size_t lds) {
 #define BTE_CASE(G_, N_, M_, L_, FN, ...) \
   case G_ * 1000 + N_ * 100 + M_ * 10 + L_: return FN<G_, N_, M_, (L_ != 0)>(__VA_ARGS__);
 #define BTE_CASES_G(G_, FN, ...)               \
-  BTE_CASE(G_, 1, 0, 0, FN, __VA_ARGS__)       \
-  BTE_CASE(G_, 2, 0, 0, FN, __VA_ARGS__)       \
-  BTE_CASE(G_, 3, 0, 0, FN, __VA_ARGS__)       \
-  BTE_CASE(G_, 1, 1, 0, FN, __VA_ARGS__)       \
-  BTE_CASE(G_, 2, 2, 0, FN, __VA_ARGS__)       \
   BTE_CASE(G_, 1, 0, 1, FN, __VA_ARGS__)       \
   BTE_CASE(G_, 2, 0, 1, FN, __VA_ARGS__)       \
   BTE_CASE(G_, 4, 0, 1, FN, __VA_ARGS__)       \

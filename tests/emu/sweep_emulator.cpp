@@ -1,4 +1,4 @@
-// CPU emulation of the sweep kernel's data flow (2D and 3D layouts) driven by
+// CPU emulation of the sweep kernels' data flow (1D/2D and 3D layouts) driven by
 // the library's own host-side schedule builder, inflow/outflow stream ordering
 // and group coefficient tables (bte_setup.cpp), in FP64. Used by the CPU test
 // suite to check that host logic against the oracle without a GPU: it mirrors
@@ -22,10 +22,10 @@ int main(int argc, char** argv) {
   int dim = hdr[0], n0 = hdr[1], n1 = hdr[2], n2 = hdr[3], B = hdr[4], M = hdr[5], nbc = hdr[6], iters = hdr[7];
   double h[3];
   fread(h, 8, 3, fp);
-  int G = 2, R = 2, P = 1, Cc = 16;
-  int pl[4];
-  fread(pl, 4, 4, fp);
-  G = pl[0]; R = pl[1]; P = pl[2]; Cc = pl[3];
+  int G = 2, R = 2, P = 1, Cc = 16, NR = 1;
+  int pl[5];
+  fread(pl, 4, 5, fp);
+  G = pl[0]; R = pl[1]; P = pl[2]; Cc = pl[3]; NR = pl[4];
   int ncell = n0 * n1 * n2;
   std::vector<uint8_t> mask(ncell), fbc(ncell * 6);
   fread(mask.data(), 1, ncell, fp);
@@ -53,8 +53,9 @@ int main(int argc, char** argv) {
   HostInst hi;
   build_instance(&g, hi);
   auto ords = fold_ordinates(&qq, dim);
-  Plan plan{G, R, P, Cc};
+  Plan plan{G, R, P, Cc, NR};
   if (dim == 3) plan.R = 1;
+  if (dim < 3) plan.C = Cc = kC2;
   Schedule S;
   std::string err;
   if (!build_schedule(hi, plan, S, err)) { printf("sched %s\n", err.c_str()); return 1; }
@@ -190,9 +191,127 @@ int main(int argc, char** argv) {
       }
     }
   };
+  // 1D/2D rows-per-lane kernel: lane l of slot r owns rows NR*l + k of its
+  // strip; per chunk of kC2 steps the ghost values of lane 0 and the ring-write
+  // columns of lane 63 are taken at the chunk start; inflows come from the
+  // per-chunk table at the offset stored in each record
+  auto sweep2d = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
+                     bool adj, const std::vector<double>& ub, std::vector<double>& acc0, std::vector<double>& acc1,
+                     std::vector<double>* store, const std::vector<double>* stored, const std::vector<double>* dTf,
+                     std::vector<double>* tg) {
+    acc0.assign(ncell, 0.0);
+    acc1.assign(ncell, 0.0);
+    const int Tp = T + kPad2, H = 64 * NR, nx = n0, ny = dim >= 2 ? n1 : 1;
+    const int nchk = T / kC2;
+    const unsigned kInAll = [&] { unsigned m = 0; for (int k = 0; k < NR; ++k) m |= (F2_INX | F2_INY) << (F2_ROW_BITS * k); return m; }();
+    auto strip_at = [&](int q, int r, int& sidx, int& v) {
+      if (q < 0) return false;
+      const int m = q / S.du;
+      sidx = R == 1 ? m : m - ((m - r) % R + R) % R;
+      if (sidx < 0) return false;
+      v = q - sidx * S.du;
+      return sidx < S.nS && v < nx;
+    };
+    for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
+      const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
+      const int dyc = (o & 2) ? -nx : nx;
+      for (int p = 0; p < P; ++p) {
+        const int grp = gs.bundle_first[bu] + p;
+        const double* gt = cf.data() + (size_t)grp * GS;
+        const int band = gs.band[grp];
+        const double kS = gt[0], cQ = gt[1];
+        std::vector<std::vector<double>> f(R, std::vector<double>((size_t)64 * NR * G, 0.0));
+        std::vector<std::vector<double>> ring(R, std::vector<double>((size_t)(W + 1) * G, 0.0));
+        for (int c = 0; c < W; ++c) {
+          const int sl = S.pre_slot[(size_t)o * W + c];
+          const double u = sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0;
+          for (int gg = 0; gg < G; ++gg) ring[R - 1][c * G + gg] = u * gt[go_den(G) + gg];
+        }
+        std::vector<int> out_cnt(R, 0);
+        std::vector<std::vector<double>> gh(R, std::vector<double>((size_t)kC2 * G));
+        std::vector<std::vector<int>> wc(R, std::vector<int>(kC2));
+        for (int tau_ = 0; tau_ < T; ++tau_) {
+          const int ch = tau_ / kC2, u = tau_ % kC2;
+          if (u == 0)
+            for (int r = 0; r < R; ++r) {
+              const int rprev = (r + R - 1) % R;
+              for (int m = 0; m < kC2; ++m) {
+                int sidx, v;
+                const int q = ch * kC2 + m;
+                const int gc = strip_at(q, r, sidx, v) ? v : -1;
+                for (int gg = 0; gg < G; ++gg) gh[r][m * G + gg] = gc >= 0 ? ring[rprev][gc * G + gg] : 0.0;
+                wc[r][m] = (strip_at(q - 63, r, sidx, v) && sidx * H + H - 1 < ny) ? v : W;
+              }
+            }
+          for (int r = 0; r < R; ++r) {
+            const long long slot = (long long)o * R + r;
+            const int* itab = &S.in_tab[(size_t)slot * (nchk + 2) * S.in_E + (size_t)ch * S.in_E];
+            std::vector<double> fold = f[r], fnew = f[r];
+            std::vector<int2> ent(64);
+            for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)slot * Tp + tau_) * 64 + l];
+            for (int l = 0; l < 64; ++l) {
+              const unsigned fl = (unsigned)ent[l].y;
+              const int cid0 = ent[l].x >= 0 ? (ent[l].x >> 4) : -1;
+              const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
+              std::vector<double> zc(G);
+              for (int gg = 0; gg < G; ++gg)
+                zc[gg] = l == 0 ? gh[r][u * G + gg] : fold[((size_t)(l - 1) * NR + NR - 1) * G + gg];
+              for (int k = 0; k < NR; ++k) {
+                const unsigned b = fl >> (F2_ROW_BITS * k);
+                const bool act = (b & F2_ACT) != 0;
+                const int cell = act ? cid0 + k * dyc : -1;
+                const double S_ = act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0;
+                const unsigned below = fl & kInAll & ((1u << (F2_ROW_BITS * k)) - 1u);
+                const int ex = e0 + __builtin_popcount(below);
+                const int ey = ex + ((b & F2_INX) ? 1 : 0);
+                double a0s = 0.0, a1s = 0.0;
+                for (int gg = 0; gg < G; ++gg) {
+                  const double den = gt[go_den(G) + gg];
+                  const double xu = (b & F2_INX) ? ub[(size_t)band * nbf + itab[ex]] * den : fold[((size_t)l * NR + k) * G + gg];
+                  const double zu = (b & F2_INY) ? ub[(size_t)band * nbf + itab[ey]] * den : zc[gg];
+                  const double fn = gt[go_a(G, 1) + gg] * zu + gt[go_a(G, 0) + gg] * xu + S_;
+                  fnew[((size_t)l * NR + k) * G + gg] = fn;
+                  zc[gg] = fn;
+                  a0s += gt[go_wacc(G, 0) + gg] * fn;
+                  a1s += gt[go_wacc(G, 1) + gg] * fn;
+                  if (act && store) (*store)[((size_t)grp * ncell + cell) * G + gg] = fn * gt[go_inv(G) + gg];
+                  if (act && tg) {
+                    const double uf = (*stored)[((size_t)grp * ncell + cell) * G + gg];
+                    (*tg)[2 * grp] += gt[go_wt(G, 0) + gg] * fn * (uf - (*dTf)[cell]);
+                    (*tg)[2 * grp + 1] += Xs[cell] * gt[go_wt(G, 1) + gg] * uf;
+                  }
+                }
+                if (act) { acc0[cell] += a0s; acc1[cell] += a1s; }
+              }
+            }
+            // outflow entries: rows, then axes, then lanes
+            for (int k = 0; k < NR; ++k)
+              for (int d = 0; d < 2; ++d)
+                for (int l = 0; l < 64; ++l) {
+                  const unsigned fl = (unsigned)ent[l].y;
+                  if (!((fl >> (F2_ROW_BITS * k)) & (F2_OUTX << d))) continue;
+                  double vv = 0.0;
+                  for (int gg = 0; gg < G; ++gg) vv += gt[go_wo(G, d) + gg] * fnew[((size_t)l * NR + k) * G + gg];
+                  outv[(size_t)grp * S.n_out_stride + S.out_base[slot] + out_cnt[r]++] = vv;
+                }
+            // lane 63's top row to the ring
+            for (int gg = 0; gg < G; ++gg) ring[r][wc[r][u] * G + gg] = fnew[((size_t)63 * NR + NR - 1) * G + gg];
+            f[r] = fnew;
+          }
+        }
+      }
+    }
+  };
+  auto run_sweep = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
+                       bool adj, const std::vector<double>& ub, std::vector<double>& a0v, std::vector<double>& a1v,
+                       std::vector<double>* store, const std::vector<double>* stored, const std::vector<double>* dTf,
+                       std::vector<double>* tg) {
+    if (dim < 3) sweep2d(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
+    else sweep(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
+  };
   std::vector<double> acc0, acc1;
   for (int it = 0; it < iters; ++it) {
-    sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+    run_sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
     for (int df : hi.dface) {
       for (int b = 0; b < B; ++b) {
         double sacc = 0.0;
@@ -214,16 +333,16 @@ int main(int argc, char** argv) {
     fread(g.data(), 8, ncell, fg);
     fclose(fg);
     std::vector<double> store((size_t)gs.band.size() * ncell * G, 0.0);
-    sweep(X, Q, coef, false, ubf, acc0, acc1, &store, nullptr, nullptr, nullptr);
+    run_sweep(X, Q, coef, false, ubf, acc0, acc1, &store, nullptr, nullptr, nullptr);
     std::vector<double> ca;
     group_coefficients(gs, ords, hi, v, tau, C, t0, true, ca);
     std::vector<double> zero(ubf.size(), 0.0), lam = g, dumQ(ncell, 0.0);
     for (int it = 0; it < iters; ++it) {
-      sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+      run_sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
       for (int c = 0; c < ncell; ++c) lam[c] = hi.active[c] ? g[c] + acc0[c] : 0.0;
     }
     std::vector<double> tg(2 * gs.band.size(), 0.0);
-    sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, &store, &X, &tg);
+    run_sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, &store, &X, &tg);
     double D = 0.0;
     for (int b = 0; b < B; ++b) D += C[b] / tau[b];
     double L = 0.0;

@@ -19,7 +19,7 @@ def _small_batch(n=6, seed=11):
 
 def test_batch_matches_single_and_oracle_fp64(hip_lib):
     insts = _small_batch()
-    bs = hip_lib.BatchSolver(insts, precision="fp64", plan=dict(G=2, R=1, P=1, C=16))
+    bs = hip_lib.BatchSolver(insts, precision="fp64", plan=dict(G=2, R=1, P=2, NR=2))
     Qs = [torch.tensor(p.Q, device="cuda") for p in insts]
     Ts, qs, reps = bs.solve(Qs, tol=1e-12, check_every=4)
     torch.cuda.synchronize()
@@ -27,7 +27,7 @@ def test_batch_matches_single_and_oracle_fp64(hip_lib):
     assert all(r["status"] == "ok" for r in reps)
     assert len(set(iters)) > 1  # uneven convergence: instances retire independently
     for k, p in enumerate(insts):
-        s = hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=1, C=16))
+        s = hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=2, NR=2))
         T1, _, r1 = s.solve(Qs[k], tol=1e-12, check_every=4)
         assert r1["iters"] == reps[k]["iters"]
         a = Ts[k].cpu().numpy()
@@ -51,7 +51,7 @@ def test_batch_fixed_iterations_fp32(hip_lib):
 
 def test_batch_adjoint_matches_single(hip_lib):
     insts = _small_batch(n=4, seed=13)
-    plan = dict(G=2, R=1, P=1, C=16)
+    plan = dict(G=2, R=1, P=2, NR=2)
     bs = hip_lib.BatchSolver(insts, precision="fp64", plan=plan)
     Qs = [torch.tensor(p.Q, device="cuda") for p in insts]
     Ts, _, _ = bs.solve(Qs, tol=1e-12, check_every=4, store_state=True)

@@ -101,8 +101,8 @@ def test_plans_agree_fp64(hip_lib):
     p = bi.square_2d(130, L=0.5e-6, n_bands=4, n_theta=2, n_phi=2)
     Q = torch.tensor(p.Q, device="cuda")
     ref = None
-    for plan in (dict(G=1, R=1, P=1, C=8), dict(G=2, R=3, P=1, C=16), dict(G=4, R=2, P=2, C=32),
-                 dict(G=2, R=1, P=4, C=16)):
+    for plan in (dict(G=1, R=1, P=1, NR=1), dict(G=2, R=3, P=1, NR=1), dict(G=2, R=2, P=2, NR=1),
+                 dict(G=1, R=1, P=4, NR=4), dict(G=2, R=1, P=2, NR=2)):
         s = hip_lib.Solver(p, precision="fp64", plan=plan)
         T, _, _ = s.solve(Q, tol=0.0, max_iters=3, check_every=3)
         T = T.cpu().numpy()
@@ -111,3 +111,10 @@ def test_plans_agree_fp64(hip_lib):
         else:
             assert np.abs(T - ref).max() < 1e-13 * np.abs(ref - 300).max()
         s.close()
+
+
+def test_oversized_plan_rejected(hip_lib):
+    """A plan whose LDS carve-up exceeds the per-workgroup limit is an input error."""
+    p = bi.square_2d(130, L=0.5e-6, n_bands=4, n_theta=2, n_phi=2)
+    with pytest.raises(hip_lib.BTEError, match="LDS"):
+        hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=8, NR=4))

@@ -50,10 +50,12 @@ def test_film_1d_converged(hip_lib):
     assert _rel(T, r["T"], p) < 1e-10
 
 
-@pytest.mark.parametrize("plan", [dict(G=1, R=1, P=1, C=16), dict(G=2, R=2, P=1, C=16),
-                                  dict(G=4, R=2, P=2, C=16), dict(G=2, R=1, P=4, C=32)])
+@pytest.mark.parametrize("plan", [dict(G=1, R=1, P=1, NR=1), dict(G=2, R=2, P=1, NR=1),
+                                  dict(G=1, R=1, P=2, NR=2), dict(G=2, R=1, P=4, NR=4),
+                                  dict(G=1, R=2, P=4, NR=1)])
 def test_square_2d_fp64_plans(hip_lib, plan):
-    """Several strips, partial last strip, all kernel shapes."""
+    """Strips processed in sequence and pipelined across waves, a partial last
+    strip, one to four rows per lane, one to four waves per workgroup."""
     p = bi.square_2d(100, L=0.4e-6, n_bands=4, n_theta=2, n_phi=2)
     T, q, rep = _solve_gpu(hip_lib, p, plan=plan, tol=0.0, max_iters=6, check_every=3)
     r = oracle.solve(p, tol=0.0, max_iters=6)
@@ -69,17 +71,30 @@ def test_rectangle_ragged_fp64(hip_lib):
     mask = np.ones(70 * 37, dtype=np.uint8)
     fbc = bi.face_bc_from_mask(n, 2, mask, lambda i, j, k, f: 0)
     p = p.replace(n=n, mask=mask, face_bc=fbc, Q=p.Q[: 70 * 37].copy())
-    T, q, rep = _solve_gpu(hip_lib, p, plan=dict(G=2, R=1, P=1, C=16), tol=0.0, max_iters=5, check_every=5)
+    T, q, rep = _solve_gpu(hip_lib, p, plan=dict(G=2, R=1, P=1, NR=1), tol=0.0, max_iters=5, check_every=5)
     r = oracle.solve(p, tol=0.0, max_iters=5)
     assert _rel(T, r["T"], p) < 1e-10
 
 
+@pytest.mark.parametrize("plan", [dict(G=2, R=1, P=1, NR=1), dict(G=1, R=1, P=2, NR=2)])
 @pytest.mark.parametrize("seed,kinds", [(0, (0, 1)), (1, (0, 0))])
-def test_masked_2d_with_diffuse_walls_fp64(hip_lib, seed, kinds):
+def test_masked_2d_with_diffuse_walls_fp64(hip_lib, seed, kinds, plan):
     p = bi.random_box_2d(23, 19, seed=seed, n_bands=3, n_theta=2, n_phi=1, kinds=kinds)
-    T, q, rep = _solve_gpu(hip_lib, p, plan=dict(G=2, R=1, P=1, C=16), tol=0.0, max_iters=9, check_every=3)
+    T, q, rep = _solve_gpu(hip_lib, p, plan=plan, tol=0.0, max_iters=9, check_every=3)
     r = oracle.solve(p, tol=0.0, max_iters=9)
     assert _rel(T, r["T"], p) < 1e-10
+
+
+@pytest.mark.parametrize("plan", [dict(G=1, R=2, P=1, NR=4), dict(G=2, R=1, P=2, NR=2)])
+def test_multi_hole_2d_diffuse_fp64(hip_lib, plan):
+    """Holes inside a lane's rows, across lanes and beside strip boundaries;
+    diffuse walls on every face but the bottom."""
+    p = bi.multi_hole_2d(50, 300, seed=4, n_bands=2, n_theta=2, n_phi=1)
+    T, q, rep = _solve_gpu(hip_lib, p, plan=plan, tol=0.0, max_iters=6, check_every=3)
+    r = oracle.solve(p, tol=0.0, max_iters=6, threads=oracle.num_threads())
+    assert _rel(T, r["T"], p) < 1e-10
+    qs = np.abs(r["q"]).max()
+    assert np.abs(q - r["q"]).max() < 1e-10 * qs
 
 
 def test_square_2d_converged_fp64(hip_lib):

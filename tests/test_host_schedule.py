@@ -37,7 +37,7 @@ def _write(p, iters, plan, path):
     with open(path, "wb") as f:
         f.write(struct.pack("8i", p.dim, *p.n, p.B, p.M, len(p.bc_kind), iters))
         f.write(np.array(p.h, dtype=np.float64).tobytes())
-        f.write(struct.pack("4i", *plan))
+        f.write(struct.pack("5i", *plan))
         f.write(p.mask.astype(np.uint8).tobytes())
         f.write(p.face_bc.astype(np.uint8).tobytes())
         f.write(p.bc_kind.astype(np.int32).tobytes())
@@ -47,14 +47,22 @@ def _write(p, iters, plan, path):
         f.write(struct.pack("d", p.T_ref))
 
 
+# plans: (G, R, P, C, NR); the 1D/2D kernel always uses chunks of 8 steps
 CASES = [
-    ("film", lambda: bi.film_1d(n_cells=50, n_mu=8), 5, (1, 1, 1, 16)),
-    ("square_r1", lambda: bi.square_2d(20, L=0.1e-6, n_bands=3, n_theta=2, n_phi=1), 4, (2, 1, 1, 16)),
-    ("square_r2", lambda: bi.square_2d(100, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 3, (2, 2, 1, 16)),
-    ("square_r3_p2", lambda: bi.square_2d(150, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 2, (4, 3, 2, 8)),
-    ("box_diffuse", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1), 5, (2, 1, 1, 16)),
-    ("box3d_diffuse", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4, (2, 1, 1, 8)),
-    ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8)),
+    ("film", lambda: bi.film_1d(n_cells=50, n_mu=8), 5, (1, 1, 1, 8, 1)),
+    ("square_nr1_g2", lambda: bi.square_2d(20, L=0.1e-6, n_bands=3, n_theta=2, n_phi=1), 4, (2, 1, 1, 8, 1)),
+    ("square_nr4_ragged_p2", lambda: bi.square_2d(150, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 2,
+     (1, 1, 2, 8, 4)),
+    ("square_nr1_r2", lambda: bi.square_2d(200, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 2, (1, 2, 1, 8, 1)),
+    ("square_nr2_r3_p2", lambda: bi.square_2d(300, L=0.5e-6, n_bands=2, n_theta=1, n_phi=1), 2, (2, 3, 2, 8, 2)),
+    ("box_diffuse", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1), 5, (2, 1, 1, 8, 1)),
+    ("box_diffuse_nr2", lambda: bi.random_box_2d(40, 100, seed=3, n_bands=2, n_theta=1, n_phi=1), 4,
+     (1, 1, 2, 8, 2)),
+    ("holes_nr4_r2", lambda: bi.multi_hole_2d(50, 300, seed=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 2, 2, 8, 4)),
+    ("holes_nr2_seq", lambda: bi.multi_hole_2d(30, 200, seed=5, n_bands=1, n_theta=1, n_phi=1), 3, (2, 1, 1, 8, 2)),
+    ("box3d_diffuse", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4,
+     (2, 1, 1, 8, 1)),
+    ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
 ]
 
 
@@ -70,7 +78,7 @@ def test_emulated_sweep_matches_oracle(emu, tmp_path, name, make, iters, plan):
     assert np.abs(T[act] - r["T"][act]).max() < 1e-11 * np.abs(r["T"][act] - p.T_ref).max()
 
 
-@pytest.mark.parametrize("plan", [(2, 1, 1, 16), (4, 1, 1, 8)])
+@pytest.mark.parametrize("plan", [(2, 1, 1, 8, 1), (1, 1, 2, 8, 2)])
 def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
     p = bi.square_2d(8, L=0.06e-6, n_bands=3, n_theta=1, n_phi=1)
     iters = 400

@@ -114,6 +114,11 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
       if (bad) v[3] = INFINITY;
     } else {
       F.X[nxt][c] = 0.0;
+      if (withq) {
+        if (adj) F.q[c] = 0.0;
+        else
+          for (int d2 = 0; d2 < I.dim; ++d2) F.q[(size_t)c * I.dim + d2] = 0.0;
+      }
     }
   }
   if (!(A.flags & FIN_CHECK)) {

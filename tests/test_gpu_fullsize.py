@@ -102,7 +102,7 @@ def test_plans_agree_fp64(hip_lib):
     Q = torch.tensor(p.Q, device="cuda")
     ref = None
     for plan in (dict(G=1, R=1, P=1, NR=1), dict(G=2, R=3, P=1, NR=1), dict(G=2, R=2, P=2, NR=1),
-                 dict(G=1, R=1, P=4, NR=4), dict(G=2, R=1, P=2, NR=2)):
+                 dict(G=1, R=1, P=2, NR=4), dict(G=2, R=1, P=2, NR=2)):
         s = hip_lib.Solver(p, precision="fp64", plan=plan)
         T, _, _ = s.solve(Q, tol=0.0, max_iters=3, check_every=3)
         T = T.cpu().numpy()

@@ -51,7 +51,7 @@ def test_film_1d_converged(hip_lib):
 
 
 @pytest.mark.parametrize("plan", [dict(G=1, R=1, P=1, NR=1), dict(G=2, R=2, P=1, NR=1),
-                                  dict(G=1, R=1, P=2, NR=2), dict(G=2, R=1, P=4, NR=4),
+                                  dict(G=1, R=1, P=2, NR=2), dict(G=2, R=1, P=2, NR=4),
                                   dict(G=1, R=2, P=4, NR=1)])
 def test_square_2d_fp64_plans(hip_lib, plan):
     """Strips processed in sequence and pipelined across waves, a partial last
@@ -62,6 +62,8 @@ def test_square_2d_fp64_plans(hip_lib, plan):
     assert _rel(T, r["T"], p) < 1e-10
     qs = np.abs(r["q"]).max()
     assert np.abs(q - r["q"]).max() < 1e-10 * qs
+    off = p.mask == 0
+    assert (T[off] == 0).all() and (q[off] == 0).all()  # inactive cells are written as zeros
 
 
 def test_rectangle_ragged_fp64(hip_lib):
@@ -95,6 +97,8 @@ def test_multi_hole_2d_diffuse_fp64(hip_lib, plan):
     assert _rel(T, r["T"], p) < 1e-10
     qs = np.abs(r["q"]).max()
     assert np.abs(q - r["q"]).max() < 1e-10 * qs
+    off = p.mask == 0
+    assert off.any() and (T[off] == 0).all() and (q[off] == 0).all()  # inactive cells are written as zeros
 
 
 def test_square_2d_converged_fp64(hip_lib):

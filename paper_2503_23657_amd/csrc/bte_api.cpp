@@ -229,8 +229,8 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       set_err("plan NR must be 1, 2 or 4");
       return BTE_ERR_INVALID;
     }
-    if (pl.P != 1 && pl.P != 2 && pl.P != 4 && pl.P != 8) {
-      set_err("plan P must be 1, 2, 4 or 8 in 1D/2D");
+    if (pl.P != 1 && pl.P != 2 && pl.P != 4) {
+      set_err("plan P must be 1, 2 or 4 in 1D/2D");
       return BTE_ERR_INVALID;
     }
   }
@@ -424,7 +424,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     sa.e_max = E;
     sa.o_max = o_max;
     h->block = R * P * 64;
-    int bpc = sweep2d_blocks_per_cu(prec, G, pl.NR, 1, SWEEP_PLAIN, h->block,
+    int bpc = sweep2d_blocks_per_cu(prec, G, pl.NR, P, 1, SWEEP_PLAIN, h->block,
                                     sa.lds_stage + 2 * h->lds_stage_plane);
     if (bpc < 1) bpc = 1;
     h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
@@ -661,7 +661,8 @@ bte_status enqueue_sweep(bte_ctx* h, bool adj, int nacc, int mode, int force, hi
   a.force = force;
   if (h->dim < 3) {
     const size_t lds = (size_t)a.lds_stage + (size_t)std::max(2, nacc) * h->lds_stage_plane;
-    HIPCHK(launch_sweep2d(h->precision, h->plan.G, h->plan.NR, nacc, mode, a, h->grid, h->block, lds, st));
+    HIPCHK(launch_sweep2d(h->precision, h->plan.G, h->plan.NR, h->plan.P, nacc, mode, a, h->grid, h->block, lds,
+                          st));
     return BTE_OK;
   }
   const size_t lds = (size_t)a.lds_stage + (size_t)nacc * h->lds_stage_plane;
@@ -1284,7 +1285,7 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
       const int nS = (ny + 64 * NR - 1) / (64 * NR);
       for (int G : {1, 2})
         for (int R = 1; R <= std::min(8, nS); R *= 2)
-          for (int P : {1, 2, 4, 8})
+          for (int P : {1, 2, 4})
             if (R * P <= 8) cand.push_back(Plan{G, R, P, kC2, NR});
     }
   }

@@ -49,11 +49,12 @@ constexpr int F_COL_SHIFT = 7;
 constexpr uint32_t F_COL_MASK = 0xFFFFu;
 
 // 1D/2D sweep (rows-per-lane layout): a lane owns NR consecutive rows of a
-// strip of 64*NR rows; the per-(step, lane) record is int2 {cid0 << 4 | am,
-// flags} where cid0 is the cell of the lane's first row and bit k of am says
-// that row k is an active cell (-1: no cell), and flags holds 5 bits per row k
-// at bit 5k (active, inflow x/y, outflow x/y) and, at bit 20, the
-// chunk-relative offset of the lane's first inflow entry.
+// strip of 64*NR rows; the per-(step, lane) record is int2 {cid0 << 5 | full
+// << 4 | gm, flags} where cid0 is the cell of the lane's first row, bit k of gm
+// says that row k lies inside the grid and full that all NR rows do (-1: no
+// cell), and flags holds 5 bits per row k at bit 5k (active, inflow x/y,
+// outflow x/y) and, at bit 20, the chunk-relative offset of the lane's first
+// inflow entry.
 constexpr int kC2 = 8;                 // steps per chunk
 constexpr int kPad2 = 8;               // schedule padding steps (prefetch runs ahead)
 constexpr uint32_t F2_ACT = 1u << 0;

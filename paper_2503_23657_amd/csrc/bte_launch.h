@@ -19,10 +19,10 @@ hipError_t launch_sweep(int prec, bool l3, int G, int nacc, int mode, const Swee
 int sweep_blocks_per_cu(int prec, bool l3, int G, int nacc, int mode, int block, size_t lds);
 
 // One launch of the 1D/2D rows-per-lane sweep (bte_sweep2d.hip); returns
-// hipErrorInvalidValue for a (G, NR, nacc, mode) combination that is not compiled.
-hipError_t launch_sweep2d(int prec, int G, int NR, int nacc, int mode, const SweepArgs& a, int grid, int block,
-                          size_t lds, hipStream_t st);
-int sweep2d_blocks_per_cu(int prec, int G, int NR, int nacc, int mode, int block, size_t lds);
+// hipErrorInvalidValue for a (G, NR, P, nacc, mode) combination that is not compiled.
+hipError_t launch_sweep2d(int prec, int G, int NR, int P, int nacc, int mode, const SweepArgs& a, int grid,
+                          int block, size_t lds, hipStream_t st);
+int sweep2d_blocks_per_cu(int prec, int G, int NR, int P, int nacc, int mode, int block, size_t lds);
 
 hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st);
 hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st);

@@ -401,9 +401,13 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
             }
             fl |= (unsigned)in_first << F2_INOFF_SHIFT;
           }
-          int am = 0;
-          for (int k = 0; k < NR; ++k) am |= (int)((fl >> (F2_ROW_BITS * k)) & F2_ACT) << k;
-          s.sched[(((size_t)o * R + r) * Tp + tau) * 64 + l] = make_int2(cid0 >= 0 ? (cid0 << 4) | am : -1, (int)fl);
+          // rows of the lane inside the grid (their partial sums are written;
+          // inactive cells' entries are ignored downstream)
+          int gm = 0;
+          for (int k = 0; k < NR; ++k)
+            if (sidx * H + l * NR + k < ny) gm |= 1 << k;
+          const int full = gm == (1 << NR) - 1 ? 16 : 0;
+          s.sched[(((size_t)o * R + r) * Tp + tau) * 64 + l] = make_int2(cid0 >= 0 ? (cid0 << 5) | full | gm : -1, (int)fl);
         }
         for (int kd = 0; kd < NR * 2; ++kd)
           for (int l = 0; l < 64; ++l) {
@@ -452,8 +456,8 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
         for (int e = chk[ch]; e < chk[ch + 1]; ++e)
           s.in_tab[(((size_t)o * R + r) * (nch + 2) + ch) * s.in_E + (e - chk[ch])] = s.in_slot[e];
     }
-  if ((long long)hi.ncell >= (1ll << 27)) {
-    err = "too many cells for the 1D/2D sweep (limit 2^27)";
+  if ((long long)hi.ncell >= (1ll << 26)) {
+    err = "too many cells for the 1D/2D sweep (limit 2^26)";
     return false;
   }
   for (int o = 0; o < n_oct; ++o)

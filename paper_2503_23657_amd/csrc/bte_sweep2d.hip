@@ -96,15 +96,12 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
 }
 
-// Strip and column of wave slot r at lane-relative clock q (strips r, r+R, ...
-// of the slot start du steps apart); false when the slot is idle at q.
-__device__ __forceinline__ bool strip_at(int q, int r, int R, int du, int n_strip, int nx, int& s, int& v) {
-  if (q < 0) return false;
-  const int m = q / du;
-  s = R == 1 ? m : m - ((m - r) % R + R) % R;
-  if (s < 0) return false;
-  v = q - s * du;
-  return s < n_strip && v < nx;
+constexpr int min_c(int a, int b) { return a < b ? a : b; }
+// largest power of two <= x (1 for x < 1)
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
 }
 
 // the flag bits `bits` repeated for rows 0..nr-1
@@ -118,7 +115,7 @@ constexpr unsigned rowmask(unsigned bits, int nr) {
 
 enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2 };
 
-template <typename T, int G, int NR, int NACC, int MODE>
+template <typename T, int G, int NR, int P, int NACC, int MODE>
 __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
   using namespace s2d;
   // prefetch distance in steps (divides kC2): a chunk for small records, half
@@ -136,7 +133,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int R = A.R, P = A.P;
+  const int R = A.R;
   const int r = wave % R;
   const int p = wave / R;
   const int rprev = (r + R - 1) % R;
@@ -264,21 +261,39 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
 
     // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
     // row; the dummy slot W_max when there is nothing to write) of a chunk:
-    // lane m < kC2 holds step m's
+    // lane m < kC2 holds step m's. The strip s and column v of lane 0 at clock
+    // q = chunk*kC2 + m, and of lane 63 at q - 63, advance by kC2 per chunk
+    // (v = q - s*du, s = r mod R, 0 <= v < R*du; strips start du apart).
+    const int Rdu = R * du;
+    auto strip_of = [&](int q, int& s, int& v) {
+      const int a = q - r * du;
+      const int m = a >= 0 ? a / Rdu : -((-a + Rdu - 1) / Rdu);
+      s = r + m * R;
+      v = q - s * du;
+    };
+    int gs_, gv_, ws_, wv_;
+    strip_of(lane, gs_, gv_);
+    strip_of(lane - 63, ws_, wv_);
     T ghv[G];
     int wcv;
-    auto chunk_cols = [&](int ch) {
-      int s, v, gc = -1, wc = -1;
-      if (lane < kC2) {
-        const int q = ch * kC2 + lane;
-        if (strip_at(q, r, R, du, n_strip, nx, s, v)) gc = v;
-        if (strip_at(q - 63, r, R, du, n_strip, nx, s, v) && s * H + H - 1 < ny) wc = v;
-      }
+    auto chunk_cols = [&]() {
+      const bool gok = lane < kC2 && gs_ >= 0 && gs_ < n_strip && gv_ < nx;
+      const bool wok = lane < kC2 && ws_ >= 0 && ws_ < n_strip && wv_ < nx && ws_ * H + H - 1 < ny;
 #pragma unroll
-      for (int g = 0; g < G; ++g) ghv[g] = gc >= 0 ? prev_ring[gc * G + g] : T(0);
-      wcv = (wc >= 0 ? wc : W_max) * G;
+      for (int g = 0; g < G; ++g) ghv[g] = gok ? prev_ring[gv_ * G + g] : T(0);
+      wcv = (wok ? wv_ : W_max) * G;
+      gv_ += kC2;
+      if (gv_ >= Rdu) {
+        gv_ -= Rdu;
+        gs_ += R;
+      }
+      wv_ += kC2;
+      if (wv_ >= Rdu) {
+        wv_ -= Rdu;
+        ws_ += R;
+      }
     };
-    chunk_cols(0);
+    chunk_cols();
 
     for (int ch = 0; ch < nch; ++ch) {
       const int bufi = ch & 1;
@@ -388,7 +403,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
           for (int k = 0; k < NR; ++k)
             if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
               GAS T* su =
-                  gp(reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 4) + k * dy) * G);
+                  gp(reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 5) + k * dy) * G);
 #pragma unroll
               for (int g = 0; g < G; ++g) su[g] = f[g][k] * inv[g];
             }
@@ -400,7 +415,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
           for (int k = 0; k < NR; ++k)
             if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
               const GAS T* su =
-                  gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 4) + k * dy) * G);
+                  gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 5) + k * dy) * G);
               double s0 = 0.0, s1 = 0.0;
 #pragma unroll
               for (int g = 0; g < G; ++g) {
@@ -434,31 +449,56 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
       // ---- end of chunk: the staged sums, the ring and the outflow entries
       //      of every wave are complete
       lds_barrier();
-      chunk_cols(ch + 1);
+      chunk_cols();
       {
         // the P waves of slot r add their partials in a fixed order and write
-        // contiguous row segments: entry e -> row e/8, step e%8 (a loop of
-        // compile-time trip count keeps the compiler's count of outstanding
-        // memory operations exact, so the steps never drain the prefetch;
-        // kept rolled to spare registers)
+        // contiguous row segments. A thread takes whole (lane, step) pairs:
+        // pair e -> lane e/8, step e%8, so 8 neighbouring threads write 8
+        // consecutive cells of each of the lane's rows; the NR rows of a pair
+        // are one vector read per wave, all reads issued before any add.
+        constexpr int PAIRS = kC2 / P;
+        // pairs per batch: a power of two (so it divides PAIRS) that keeps the
+        // batch's sums within ~32 registers
+        constexpr int MB = pow2_floor(min_c(PAIRS, 32 / (NACC * NR * (int)(sizeof(T) / 4))));
+        static_assert(MB >= 1 && PAIRS % MB == 0, "write-out batches must tile the pairs exactly");
         const int t = p * 64 + lane;
-        const int per = (kC2 * NR) / P;
         const int* scr = scid + (bufi * R + r) * kC2 * 64;
-#pragma unroll 1
-        for (int m = 0; m < kC2 * NR; ++m) {
-          if (m < per) {
-            const int e = m * (P * 64) + t;
-            const int row = e >> 3, cc = e & 7;
-            const int ln = row / NR, k = row % NR;
-            const int v = scr[cc * 64 + ln];
-            if (v >= 0 && ((v >> k) & 1)) {
-              const int cid = (v >> 4) + k * dy;
 #pragma unroll
-              for (int a = 0; a < NACC; ++a) {
-                const T* sp = stage + (size_t)(NACC == 1 ? bufi : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + row;
-                T sum = sp[0];
-                for (int q = 1; q < P; ++q) sum += sp[(size_t)q * R * kC2 * RS];
-                PARTJ[a * part_plane + cid] = sum;
+        for (int m0 = 0; m0 < PAIRS; m0 += MB) {
+          int vv[MB];
+          VR sums[NACC][MB];
+#pragma unroll
+          for (int mi = 0; mi < MB; ++mi) {
+            const int e = (m0 + mi) * (P * 64) + t;
+            const int ln = e >> 3, cc = e & 7;
+            vv[mi] = scr[cc * 64 + ln];
+#pragma unroll
+            for (int a = 0; a < NACC; ++a) {
+              const T* sp =
+                  stage + (size_t)(NACC == 1 ? bufi : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + ln * NR;
+              sums[a][mi] = *reinterpret_cast<const VR*>(sp);
+#pragma unroll
+              for (int q = 1; q < P; ++q) sums[a][mi] += *reinterpret_cast<const VR*>(sp + (size_t)q * R * kC2 * RS);
+            }
+          }
+#pragma unroll
+          for (int mi = 0; mi < MB; ++mi) {
+            if (vv[mi] >= 0) {
+              // rows inside the grid (inactive cells' entries are ignored by
+              // the finalize); usually all NR of them
+              const int cid0 = vv[mi] >> 5;
+              if (vv[mi] & 16) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k)
+#pragma unroll
+                  for (int a = 0; a < NACC; ++a) PARTJ[a * part_plane + cid0 + k * dy] = sums[a][mi][k];
+              } else {
+#pragma unroll
+                for (int k = 0; k < NR; ++k)
+                  if ((vv[mi] >> k) & 1) {
+#pragma unroll
+                    for (int a = 0; a < NACC; ++a) PARTJ[a * part_plane + cid0 + k * dy] = sums[a][mi][k];
+                  }
               }
             }
           }

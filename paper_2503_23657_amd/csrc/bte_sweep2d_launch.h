@@ -29,9 +29,9 @@ static inline int dyn_lds_limit_2d(const void* k) {
   return dyn;
 }
 
-template <typename T, int G, int NR, int NACC, int MODE>
+template <typename T, int G, int NR, int P, int NACC, int MODE>
 static hipError_t launch2d_one(const SweepArgs& a, int grid, int block, size_t lds, hipStream_t st) {
-  auto k = sweep2d_kernel<T, G, NR, NACC, MODE>;
+  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE>;
   static int lim = -1;
   if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
   if ((long long)lds > lim) return hipErrorInvalidValue;
@@ -39,10 +39,10 @@ static hipError_t launch2d_one(const SweepArgs& a, int grid, int block, size_t l
   return hipGetLastError();
 }
 
-template <typename T, int G, int NR, int NACC, int MODE>
+template <typename T, int G, int NR, int P, int NACC, int MODE>
 static int occ2d_one(int block, size_t lds) {
   int n = 0;
-  auto k = sweep2d_kernel<T, G, NR, NACC, MODE>;
+  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE>;
   static int lim = -1;
   if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
   if ((long long)lds > lim) return 0;
@@ -53,26 +53,40 @@ static int occ2d_one(int block, size_t lds) {
   return n;
 }
 
-// compiled variants: G in {1, 2}, NR in {1, 2, 4}; (NACC, mode) in
-// {(1..3, plain), (1, store), (2, tau-gradient)}
-#define BTE2D_KEY(G_, NR_, N_, M_) ((G_) * 1000 + (NR_) * 100 + (N_) * 10 + (M_))
-#define BTE2D_CASE(T_, G_, NR_, N_, M_, FN, ...) \
-  case BTE2D_KEY(G_, NR_, N_, M_): return FN<T_, G_, NR_, N_, M_>(__VA_ARGS__);
+// compiled variants: NR in {1, 2, 4}, P in {1, 2, 4} and (NACC, mode) in
+// {(1..3, plain), (1, store), (2, tau-gradient)}; each translation unit
+// instantiates one (precision, G) pair
+#define BTE2D_KEY(NR_, P_, N_, M_) ((NR_) * 1000 + (P_) * 100 + (N_) * 10 + (M_))
+#define BTE2D_CASE(T_, G_, NR_, P_, N_, M_, FN, ...) \
+  case BTE2D_KEY(NR_, P_, N_, M_): return FN<T_, G_, NR_, P_, N_, M_>(__VA_ARGS__);
+#define BTE2D_CASES_P(T_, G_, NR_, P_, FN, ...)       \
+  BTE2D_CASE(T_, G_, NR_, P_, 1, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, P_, 2, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, P_, 3, 0, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, P_, 1, 1, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, P_, 2, 2, FN, __VA_ARGS__)
 #define BTE2D_CASES_NR(T_, G_, NR_, FN, ...)     \
-  BTE2D_CASE(T_, G_, NR_, 1, 0, FN, __VA_ARGS__) \
-  BTE2D_CASE(T_, G_, NR_, 2, 0, FN, __VA_ARGS__) \
-  BTE2D_CASE(T_, G_, NR_, 3, 0, FN, __VA_ARGS__) \
-  BTE2D_CASE(T_, G_, NR_, 1, 1, FN, __VA_ARGS__) \
-  BTE2D_CASE(T_, G_, NR_, 2, 2, FN, __VA_ARGS__)
-#define BTE2D_DISPATCH(T_, FN, ...)                          \
-  switch (BTE2D_KEY(G, NR, nacc, mode)) {                    \
-    BTE2D_CASES_NR(T_, 1, 1, FN, __VA_ARGS__)                \
-    BTE2D_CASES_NR(T_, 1, 2, FN, __VA_ARGS__)                \
-    BTE2D_CASES_NR(T_, 1, 4, FN, __VA_ARGS__)                \
-    BTE2D_CASES_NR(T_, 2, 1, FN, __VA_ARGS__)                \
-    BTE2D_CASES_NR(T_, 2, 2, FN, __VA_ARGS__)                \
-    BTE2D_CASES_NR(T_, 2, 4, FN, __VA_ARGS__)                \
-    default: break;                                          \
+  BTE2D_CASES_P(T_, G_, NR_, 1, FN, __VA_ARGS__) \
+  BTE2D_CASES_P(T_, G_, NR_, 2, FN, __VA_ARGS__) \
+  BTE2D_CASES_P(T_, G_, NR_, 4, FN, __VA_ARGS__)
+#define BTE2D_DISPATCH(T_, G_, FN, ...)                 \
+  switch (BTE2D_KEY(NR, P, nacc, mode)) {               \
+    BTE2D_CASES_NR(T_, G_, 1, FN, __VA_ARGS__)          \
+    BTE2D_CASES_NR(T_, G_, 2, FN, __VA_ARGS__)          \
+    BTE2D_CASES_NR(T_, G_, 4, FN, __VA_ARGS__)          \
+    default: break;                                     \
+  }
+
+// one (precision, G) translation unit
+#define BTE2D_UNIT(T_, G_, SUFFIX)                                                                      \
+  hipError_t launch_sweep2d_##SUFFIX(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, \
+                                     int block, size_t lds, hipStream_t st) {                         \
+    BTE2D_DISPATCH(T_, G_, launch2d_one, a, grid, block, lds, st)                                     \
+    return hipErrorInvalidValue;                                                                      \
+  }                                                                                                   \
+  int sweep2d_blocks_per_cu_##SUFFIX(int NR, int P, int nacc, int mode, int block, size_t lds) {      \
+    BTE2D_DISPATCH(T_, G_, occ2d_one, block, lds)                                                     \
+    return 0;                                                                                         \
   }
 
 }  // namespace bte

@@ -8,6 +8,7 @@
 //   prints T after n iterations, or, with dJ/dT, the adjoint gradients.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -251,11 +252,19 @@ int main(int argc, char** argv) {
             for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)slot * Tp + tau_) * 64 + l];
             for (int l = 0; l < 64; ++l) {
               const unsigned fl = (unsigned)ent[l].y;
-              const int cid0 = ent[l].x >= 0 ? (ent[l].x >> 4) : -1;
+              const int cid0 = ent[l].x >= 0 ? (ent[l].x >> 5) : -1;
               const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
               std::vector<double> zc(G);
               for (int gg = 0; gg < G; ++gg)
                 zc[gg] = l == 0 ? gh[r][u * G + gg] : fold[((size_t)(l - 1) * NR + NR - 1) * G + gg];
+              // the kernel's write-out decodes rows from the record: every active
+              // row must be marked inside the grid, and "full" must mean all rows
+              if (ent[l].x >= 0) {
+                const int gm = ent[l].x & 15, full = (ent[l].x >> 4) & 1;
+                if (full != (gm == (1 << NR) - 1 ? 1 : 0)) { printf("bad full bit\n"); exit(2); }
+                for (int k = 0; k < NR; ++k)
+                  if (((fl >> (F2_ROW_BITS * k)) & F2_ACT) && !((gm >> k) & 1)) { printf("bad grid mask\n"); exit(2); }
+              }
               for (int k = 0; k < NR; ++k) {
                 const unsigned b = fl >> (F2_ROW_BITS * k);
                 const bool act = (b & F2_ACT) != 0;

@@ -117,4 +117,4 @@ def test_oversized_plan_rejected(hip_lib):
     """A plan whose LDS carve-up exceeds the per-workgroup limit is an input error."""
     p = bi.square_2d(130, L=0.5e-6, n_bands=4, n_theta=2, n_phi=2)
     with pytest.raises(hip_lib.BTEError, match="LDS"):
-        hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=8, NR=4))
+        hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=4, NR=4))

@@ -35,17 +35,51 @@ def flops_per_update(dim: int, with_q: bool) -> float:
     return 2.0 * (dim + 1 + (dim if with_q else 0))
 
 
-def cpu_baseline(p, iters: int):
-    """The FP64 oracle timed on the host over a bounded number of iterations."""
+def cpu_baseline(p, iters: int, m_swept: int):
+    """The FP64 oracle timed on the host over a bounded number of iterations,
+    as a rate in the metric's own counting (swept projections per band)."""
     import oracle
     threads = oracle.num_threads()
     t0 = time.perf_counter()
     oracle.solve(p, tol=0.0, max_iters=iters, threads=threads)
     dt = time.perf_counter() - t0
-    upd = p.n_active * p.M * p.B * iters
-    return dict(value=upd / dt, unit="cell-ordinate-band updates/s", cores=threads, kind="oracle",
-                sample=f"{iters} source iterations of the full 256x256x15x128 problem "
-                       f"({p.M} directions swept, FP64, {dt:.1f} s)")
+    upd = p.n_active * m_swept * p.B * iters
+    return dict(value=upd / dt, unit="updates/s", cores=threads, kind="oracle",
+                sample=f"{iters} source iterations of the full 256x256 problem in FP64 ({dt:.1f} s; the oracle "
+                       f"sweeps all {p.M} directions, counted as the {m_swept} swept projections per band)")
+
+
+SWEEP_SOURCES = ("bte_sweep2d.hip", "bte_sweep2d_launch.h")
+
+
+def sweep_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_23657_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none for this kernel or the sweep sources changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "sweep2d_square256_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel") != kernel or kv.get("sweep source hash") != sweep_source_hash():
+        return None
+    try:
+        return float(kv["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -55,11 +89,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--batch-kn-min", type=float, default=0.3)
     ap.add_argument("--plan", type=str, default=None,
                     help="fixed kernel plan 'G,R,P,NR' instead of the autotuned one")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 256 MiB three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(64 * 1024 * 1024, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
         sys.exit(2)
@@ -100,10 +145,10 @@ def main():
     sweep_ms, _ = solver.time_sweep(n_launches=50)
     flop = n_upd * flops_per_update(2, False)
     achieved_tf = flop / (sweep_ms * 1e-3) / 1e12
+    kname = f"sweep2d_kernel<float, {plan['G']}, {plan['NR']}, {plan['P']}, 1, 0>"
     roofline = dict(bound="alu", achieved=achieved_tf, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved_tf / FP32_VALU_PEAK_TFLOPS, traffic=None,
-                    kernel="sweep_kernel<float,G,1,0,false>", kernel_ms=sweep_ms,
-                    sweep_updates_per_s=n_upd / (sweep_ms * 1e-3))
+                    frac=achieved_tf / FP32_VALU_PEAK_TFLOPS, traffic=profiled_traffic(kname),
+                    kernel=kname, kernel_ms=sweep_ms, sweep_updates_per_s=n_upd / (sweep_ms * 1e-3))
 
     extra = {}
     if not args.no_extra:
@@ -184,7 +229,7 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters, M_swept)
     print(json.dumps(out))
 
 

@@ -26,6 +26,18 @@ __device__ __forceinline__ double job_sum(const T* pl, int n_jobs, int ncell, in
   return (s0 + s1) + (s2 + s3);
 }
 
+// Sum of the kFinSlices job slices of one cell, pairwise in a fixed order.
+__device__ __forceinline__ double slice_sum(const double (*sl)[kFinCells], int cl) {
+  double v[kFinSlices];
+#pragma unroll
+  for (int i = 0; i < kFinSlices; ++i) v[i] = sl[i][cl];
+#pragma unroll
+  for (int w = 1; w < kFinSlices; w *= 2)
+#pragma unroll
+    for (int i = 0; i + w < kFinSlices; i += 2 * w) v[i] += v[i + w];
+  return v[0];
+}
+
 // Block-wide reduction of (sum, max, sum, max) over the block's threads;
 // every thread calls it; the result is valid in thread 0.
 __device__ __forceinline__ void block_reduce4(double (*red)[kFinThreads], double v[4]) {
@@ -78,7 +90,7 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
   if (js == 0 && c < I.ncell) {
     if (act) {
       double x = adj ? F.g[c] : 0.0;
-      x += (slc[0][0][cl] + slc[0][1][cl]) + (slc[0][2][cl] + slc[0][3][cl]);
+      x += slice_sum(slc[0], cl);
       const double old = F.X[cur][c];
       F.X[nxt][c] = x;
       // scatter into the skewed layouts of every octant
@@ -93,11 +105,11 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
       v[1] = fabs(x);
       if (withq) {
         if (adj) {
-          F.q[c] = (slc[1][0][cl] + slc[1][1][cl]) + (slc[1][2][cl] + slc[1][3][cl]);
+          F.q[c] = slice_sum(slc[1], cl);
         } else {
           double m2 = 0.0;
           for (int d2 = 0; d2 < I.dim; ++d2) {
-            const double qv = (slc[1 + d2][0][cl] + slc[1 + d2][1][cl]) + (slc[1 + d2][2][cl] + slc[1 + d2][3][cl]);
+            const double qv = slice_sum(slc[1 + d2], cl);
             F.q[(size_t)c * I.dim + d2] = qv;
             m2 += qv * qv;
             bad = bad || !isfinite(qv);

@@ -65,6 +65,10 @@ constexpr uint32_t F2_OUTY = 1u << 4;
 constexpr int F2_ROW_BITS = 5;
 constexpr int F2_INOFF_SHIFT = 20;
 constexpr uint32_t F2_INOFF_MASK = 0xFFu;
+// per-chunk flags of the 1D/2D schedule
+constexpr int CF2_IN = 1;       // some inflow entry in the chunk
+constexpr int CF2_INY_UP = 2;   // some y-inflow on a row k >= 1 of a lane
+constexpr int CF2_OUT = 4;      // some outflow entry in the chunk
 
 // group coefficient record: GS(G) values of the sweep type, in this order
 //   kS, cQ, a[3][G], den[G], wacc[kNAcc][G], wo[3][G], wt[2][G], inv[G]
@@ -116,6 +120,7 @@ struct InstDev {
   int n_strip;              // strips of 64*nr rows
   int in_E;                 // entries per chunk row of in_tab (multiple of 64, <= 256)
   const int* in_tab;        // [n_oct][R][T/kC2 + 2][in_E] inflow face slot of each stream entry (-1 pad)
+  const int* chunk_fl;      // [n_oct][R][T/kC2 + 1] CF2_* flags of each chunk (0 pad)
 };
 
 // Job: instance, first group of the bundle (global index), instance-local job

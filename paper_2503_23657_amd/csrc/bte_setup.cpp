@@ -446,6 +446,33 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
     err = "too many diffuse-wall outflows per chunk";
     return false;
   }
+  // per-chunk flags (one padding row: the kernel reads a chunk ahead)
+  s.chunk_fl.assign((size_t)n_oct * R * (nch + 1), 0);
+  {
+    const unsigned in_up = [&] {
+      unsigned m = 0;
+      for (int k = 1; k < NR; ++k) m |= F2_INY << (F2_ROW_BITS * k);
+      return m;
+    }();
+    unsigned in_all = 0, out_all = 0;
+    for (int k = 0; k < NR; ++k) {
+      in_all |= (F2_INX | F2_INY) << (F2_ROW_BITS * k);
+      out_all |= (F2_OUTX | F2_OUTY) << (F2_ROW_BITS * k);
+    }
+    for (int o = 0; o < n_oct; ++o)
+      for (int r = 0; r < R; ++r)
+        for (int ch = 0; ch < nch; ++ch) {
+          int cf = 0;
+          for (int tau = ch * C; tau < (ch + 1) * C; ++tau)
+            for (int l = 0; l < 64; ++l) {
+              const unsigned fl = (unsigned)s.sched[(((size_t)o * R + r) * Tp + tau) * 64 + l].y;
+              if (fl & in_all) cf |= CF2_IN;
+              if (fl & in_up) cf |= CF2_INY_UP;
+              if (fl & out_all) cf |= CF2_OUT;
+            }
+          s.chunk_fl[((size_t)o * R + r) * (nch + 1) + ch] = cf;
+        }
+  }
   // per-chunk inflow table, two padding chunk rows at the end of every slot
   s.in_E = std::max(64, (s.e_max + 63) / 64 * 64);
   s.in_tab.assign((size_t)n_oct * R * (nch + 2) * s.in_E, -1);

@@ -69,6 +69,7 @@ struct Schedule {
   std::vector<int> ofk;              // [n_oct][n_bface]
   std::vector<int> pre_slot;         // 2D: [n_oct][W]
   std::vector<int> in_tab;           // 1D/2D: [n_oct][R][T/C + 2][in_E]
+  std::vector<int> chunk_fl;         // 1D/2D: [n_oct][R][T/C + 1] CF2_* flags
   int in_E = 64;
   int n_out_stride = 1;              // max out-stream length over octants
 };

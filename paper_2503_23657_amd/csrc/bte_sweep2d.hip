@@ -35,6 +35,8 @@
 //     strips r, r+R, ...), the top rows reaching the next slot through its ring.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bte_device.h"
 
 namespace bte {
@@ -294,6 +296,10 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
       }
     };
     chunk_cols();
+    // per-chunk flags (CF2_*), uniform: scalar loads from read-only memory
+    const __attribute__((address_space(4))) int* CFL =
+        (const __attribute__((address_space(4))) int*)(I.chunk_fl + slot * (nch + 1));
+    int cfl = CFL[0];
 
     for (int ch = 0; ch < nch; ++ch) {
       const int bufi = ch & 1;
@@ -302,8 +308,12 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
       int* scw = scid + (bufi * R + r) * kC2 * 64;
       int out_cnt = 0;
 
-#pragma unroll
-      for (int u = 0; u < kC2; ++u) {
+      // one step; IN: 0 no inflow entries in this chunk, 1 x-inflows and
+      // row-0 y-inflows only (folded into the chain inputs), 2 any inflow (its
+      // own chain with selects); OUT: diffuse-wall outflow entries present
+      auto step = [&](auto in_tag, auto out_tag, const int u) {
+        constexpr int IN = decltype(in_tag)::value;
+        constexpr bool OUT = decltype(out_tag)::value;
         const int sl = u % KD;
         const int tau = ch * kC2 + u;
         const int2 rec = RR[sl];
@@ -322,7 +332,26 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
         for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), f[g][NR - 1]);
 
         constexpr unsigned kInAll = rowmask(F2_INX | F2_INY, NR);
-        if (__ballot(fl & kInAll) != 0ull) {
+        if (IN == 1 && __ballot(fl & kInAll) != 0ull) {
+          // x-inflows replace the rows' x-upwind values and a row-0 y-inflow
+          // the lane-below value before the common chain (the lane's entries:
+          // rows ascending, x before y, from its offset)
+          const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const unsigned b = fl >> (F2_ROW_BITS * k);
+            const int ex = e0 + __builtin_popcount(fl & kInAll & ((1u << (F2_ROW_BITS * k)) - 1u));
+            const T vx = inbuf[min(ex, E - 1)];
+#pragma unroll
+            for (int g = 0; g < G; ++g) f[g][k] = (b & F2_INX) ? vx * den[g] : f[g][k];
+            if (k == 0) {
+              const T vy = inbuf[min(ex + ((b & F2_INX) ? 1 : 0), E - 1)];
+#pragma unroll
+              for (int g = 0; g < G; ++g) zc[g] = (b & F2_INY) ? vy * den[g] : zc[g];
+            }
+          }
+        }
+        if (IN == 2 && __ballot(fl & kInAll) != 0ull) {
           // entries of this lane: rows ascending, x before y, from its offset
           const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
 #pragma unroll
@@ -343,6 +372,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
             }
           }
         } else {
+          // the common chain
 #pragma unroll
           for (int k = 0; k < NR; ++k)
 #pragma unroll
@@ -377,7 +407,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
 
         // ---- diffuse-wall outflow stream: rows, then axes, then lanes
         constexpr unsigned kOutAll = rowmask(F2_OUTX | F2_OUTY, NR);
-        if (__ballot(fl & kOutAll) != 0ull) {
+        if (OUT && __ballot(fl & kOutAll) != 0ull) {
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
 #pragma unroll
@@ -444,11 +474,29 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
           }
         }
         __builtin_amdgcn_sched_barrier(0);
+      };
+      // the chunk's flags (read a chunk ahead with a scalar load) pick the
+      // body: most chunks have no boundary entries at all
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      using B0 = std::integral_constant<bool, false>;
+      using B1 = std::integral_constant<bool, true>;
+      if (cfl == 0) {
+#pragma unroll
+        for (int u = 0; u < kC2; ++u) step(I0(), B0(), u);
+      } else if (!(cfl & CF2_INY_UP)) {
+#pragma unroll
+        for (int u = 0; u < kC2; ++u) step(I1(), B1(), u);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kC2; ++u) step(I2(), B1(), u);
       }
 
       // ---- end of chunk: the staged sums, the ring and the outflow entries
       //      of every wave are complete
       lds_barrier();
+      cfl = CFL[ch + 1];
       chunk_cols();
       {
         // the P waves of slot r add their partials in a fixed order and write

@@ -165,8 +165,11 @@ bte_status bte_set_tau(bte_handle h, const double* h_tau);
 bte_status bte_set_plan(bte_handle h, const bte_plan* plan);
 bte_status bte_get_plan(bte_handle h, bte_plan* plan);
 
-/* Time candidate kernel shapes on this problem (n_iters sweeps each, after one
-   warm-up) and keep the fastest; writes it to *best (may be NULL).
+/* Time candidate kernel shapes on this problem and keep the fastest; writes it
+   to *best (may be NULL). Each candidate runs n_iters whole source iterations
+   (sweep, finalize, diffuse-wall update) after one warm-up iteration, from a
+   fresh state; the current shape is kept unless another is at least 3% faster.
+   The solver state afterwards is that of a fresh start (solve again).
    d_Q: [ncell] heat source used for the timing runs (NULL = zero). */
 bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_stream,
                         bte_plan* best);

@@ -297,7 +297,10 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
   const int H = 64 * NR;
   const int nS = (ny + H - 1) / H;
   const int V = nx;
-  const int du = R == 1 ? std::max(V, 63 + C) : std::max(63 + C, (V + R - 1) / R);
+  // strips start du steps apart: at least 63 + C (the previous strip's top
+  // row reaches the ring a chunk before it is read) and, when a slot owns
+  // several strips, long enough for its strips not to overlap (R*du >= V)
+  const int du = nS > R ? std::max(63 + C, (V + R - 1) / R) : 63 + C;
   int T = (nS - 1) * du + V + 63;
   T = (T + C - 1) / C * C;
   const int Tp = T + kPad2;
@@ -329,18 +332,18 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
   s.e_max = 1;
   s.o_max = 1;
   int n_out_max = 1;
-  // strip and column of slot r at lane-relative clock q; false when idle
+  // strip and column of slot r at lane-relative clock q; false when idle.
+  // Slot r owns strips r, r+R, ...; strip s starts at s*du, so consecutive
+  // strips of a slot start SP = R*du apart (SP unbounded when a slot owns one
+  // strip at most)
+  const long long SP = nS > R ? (long long)R * du : (1ll << 40);
   auto strip_at = [&](int r, int q, int& sidx, int& v) {
-    if (q < 0) return false;
-    if (R == 1) {
-      sidx = q / du;
-    } else {
-      const int m = q / du;
-      sidx = m - ((m - r) % R + R) % R;
-      if (sidx < 0) return false;
-    }
+    const long long a = (long long)q - (long long)r * du;
+    const long long m = a >= 0 ? a / SP : -((-a + SP - 1) / SP);
+    sidx = (int)(r + m * R);
+    if (sidx < 0) return false;
     v = q - sidx * du;
-    return sidx < nS && v < V;
+    return sidx < nS && v >= 0 && v < V;
   };
   std::vector<int> out_face(64 * NR * 2);
   for (int o = 0; o < n_oct; ++o) {

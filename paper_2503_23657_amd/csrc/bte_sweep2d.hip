@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "bte_device.h"
+#include "bte_strips.h"
 
 namespace bte {
 namespace s2d {
@@ -263,37 +264,20 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
 
     // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
     // row; the dummy slot W_max when there is nothing to write) of a chunk:
-    // lane m < kC2 holds step m's. The strip s and column v of lane 0 at clock
-    // q = chunk*kC2 + m, and of lane 63 at q - 63, advance by kC2 per chunk
-    // (v = q - s*du, s = r mod R, 0 <= v < R*du; strips start du apart).
-    const int Rdu = R * du;
-    auto strip_of = [&](int q, int& s, int& v) {
-      const int a = q - r * du;
-      const int m = a >= 0 ? a / Rdu : -((-a + Rdu - 1) / Rdu);
-      s = r + m * R;
-      v = q - s * du;
-    };
-    int gs_, gv_, ws_, wv_;
-    strip_of(lane, gs_, gv_);
-    strip_of(lane - 63, ws_, wv_);
+    // lane m < kC2 holds step m's
+    StripTrack gt_, wt_;  // lane 0 at clock chunk*kC2 + m, lane 63 at that clock - 63
+    gt_.init(lane, r, R, du, n_strip);
+    wt_.init(lane - 63, r, R, du, n_strip);
     T ghv[G];
     int wcv;
     auto chunk_cols = [&]() {
-      const bool gok = lane < kC2 && gs_ >= 0 && gs_ < n_strip && gv_ < nx;
-      const bool wok = lane < kC2 && ws_ >= 0 && ws_ < n_strip && wv_ < nx && ws_ * H + H - 1 < ny;
+      const bool gok = lane < kC2 && gt_.valid(n_strip, nx);
+      const bool wok = lane < kC2 && wt_.valid(n_strip, nx) && wt_.s * H + H - 1 < ny;
 #pragma unroll
-      for (int g = 0; g < G; ++g) ghv[g] = gok ? prev_ring[gv_ * G + g] : T(0);
-      wcv = (wok ? wv_ : W_max) * G;
-      gv_ += kC2;
-      if (gv_ >= Rdu) {
-        gv_ -= Rdu;
-        gs_ += R;
-      }
-      wv_ += kC2;
-      if (wv_ >= Rdu) {
-        wv_ -= Rdu;
-        ws_ += R;
-      }
+      for (int g = 0; g < G; ++g) ghv[g] = gok ? prev_ring[gt_.v * G + g] : T(0);
+      wcv = (wok ? wt_.v : W_max) * G;
+      gt_.advance(kC2, R);
+      wt_.advance(kC2, R);
     };
     chunk_cols();
     // per-chunk flags (CF2_*), uniform: scalar loads from read-only memory
@@ -473,7 +457,6 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
             RXF[sl] = fb[lane];
           }
         }
-        __builtin_amdgcn_sched_barrier(0);
       };
       // the chunk's flags (read a chunk ahead with a scalar load) pick the
       // body: most chunks have no boundary entries at all

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../paper_2503_23657_amd/csrc/bte_setup.h"
+#include "../../paper_2503_23657_amd/csrc/bte_strips.h"
 
 using namespace bte;
 
@@ -205,13 +206,14 @@ int main(int argc, char** argv) {
     const int Tp = T + kPad2, H = 64 * NR, nx = n0, ny = dim >= 2 ? n1 : 1;
     const int nchk = T / kC2;
     const unsigned kInAll = [&] { unsigned m = 0; for (int k = 0; k < NR; ++k) m |= (F2_INX | F2_INY) << (F2_ROW_BITS * k); return m; }();
+    const long long SPe = S.nS > R ? (long long)R * S.du : (1ll << 40);
     auto strip_at = [&](int q, int r, int& sidx, int& v) {
-      if (q < 0) return false;
-      const int m = q / S.du;
-      sidx = R == 1 ? m : m - ((m - r) % R + R) % R;
+      const long long a = (long long)q - (long long)r * S.du;
+      const long long m = a >= 0 ? a / SPe : -((-a + SPe - 1) / SPe);
+      sidx = (int)(r + m * R);
       if (sidx < 0) return false;
       v = q - sidx * S.du;
-      return sidx < S.nS && v < nx;
+      return sidx < S.nS && v >= 0 && v < nx;
     };
     for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
       const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
@@ -231,6 +233,13 @@ int main(int argc, char** argv) {
         std::vector<int> out_cnt(R, 0);
         std::vector<std::vector<double>> gh(R, std::vector<double>((size_t)kC2 * G));
         std::vector<std::vector<int>> wc(R, std::vector<int>(kC2));
+        // the kernel's incremental strip tracking, one tracker per chunk lane m
+        std::vector<std::vector<StripTrack>> gtr(R, std::vector<StripTrack>(kC2)), wtr = gtr;
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < kC2; ++m) {
+            gtr[r][m].init(m, r, R, S.du, S.nS);
+            wtr[r][m].init(m - 63, r, R, S.du, S.nS);
+          }
         for (int tau_ = 0; tau_ < T; ++tau_) {
           const int ch = tau_ / kC2, u = tau_ % kC2;
           if (u == 0)
@@ -239,9 +248,22 @@ int main(int argc, char** argv) {
               for (int m = 0; m < kC2; ++m) {
                 int sidx, v;
                 const int q = ch * kC2 + m;
-                const int gc = strip_at(q, r, sidx, v) ? v : -1;
+                // the tracker must agree with the schedule's own strip mapping
+                const bool gref = strip_at(q, r, sidx, v);
+                if (gref != gtr[r][m].valid(S.nS, nx) || (gref && (v != gtr[r][m].v || sidx != gtr[r][m].s))) {
+                  printf("strip tracker mismatch (lane 0)\n");
+                  exit(2);
+                }
+                const bool wref = strip_at(q - 63, r, sidx, v);
+                if (wref != wtr[r][m].valid(S.nS, nx) || (wref && (v != wtr[r][m].v || sidx != wtr[r][m].s))) {
+                  printf("strip tracker mismatch (lane 63)\n");
+                  exit(2);
+                }
+                const int gc = gtr[r][m].valid(S.nS, nx) ? gtr[r][m].v : -1;
                 for (int gg = 0; gg < G; ++gg) gh[r][m * G + gg] = gc >= 0 ? ring[rprev][gc * G + gg] : 0.0;
-                wc[r][m] = (strip_at(q - 63, r, sidx, v) && sidx * H + H - 1 < ny) ? v : W;
+                wc[r][m] = (wtr[r][m].valid(S.nS, nx) && wtr[r][m].s * H + H - 1 < ny) ? wtr[r][m].v : W;
+                gtr[r][m].advance(kC2, R);
+                wtr[r][m].advance(kC2, R);
               }
             }
           for (int r = 0; r < R; ++r) {

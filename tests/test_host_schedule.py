@@ -55,6 +55,8 @@ CASES = [
      (1, 1, 2, 8, 4)),
     ("square_nr1_r2", lambda: bi.square_2d(200, L=0.4e-6, n_bands=2, n_theta=1, n_phi=1), 2, (1, 2, 1, 8, 1)),
     ("square_nr2_r3_p2", lambda: bi.square_2d(300, L=0.5e-6, n_bands=2, n_theta=1, n_phi=1), 2, (2, 3, 2, 8, 2)),
+    ("square_nr1_r2_multi", lambda: bi.square_2d(330, L=0.5e-6, n_bands=1, n_theta=1, n_phi=1), 2, (1, 2, 1, 8, 1)),
+    ("square_nr1_r8_single", lambda: bi.square_2d(300, L=0.5e-6, n_bands=1, n_theta=1, n_phi=1), 2, (1, 8, 1, 8, 1)),
     ("box_diffuse", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1), 5, (2, 1, 1, 8, 1)),
     ("box_diffuse_nr2", lambda: bi.random_box_2d(40, 100, seed=3, n_bands=2, n_theta=1, n_phi=1), 4,
      (1, 1, 2, 8, 2)),

@@ -91,10 +91,10 @@ typedef struct {
 /* Kernel shape of the sweep (chosen by bte_autotune, or set by hand).
    G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D: 1, 2 or 4).
    R: 1D/2D only, waves per workgroup that pipeline successive strips of
-      64*NR rows (R*P <= 8); 3D: always 1.
+      64*NR rows (R*P <= 4); 3D: always 1.
    P: waves per workgroup that sweep different ordinate groups of one octant
       in lockstep and add their partial sums per cell before writing them
-      (1D/2D: 1, 2 or 4; 3D: 1..8; R*P <= 8).
+      (1D/2D: 1, 2 or 4 with R*P <= 4; 3D: 1..8).
    C: 3D only, steps between workgroup barriers (multiple of 8 in 8..64 and of
       P); 1D/2D always use chunks of 8 steps.
    NR: 1D/2D only, rows owned by each lane of a strip (1, 2 or 4).

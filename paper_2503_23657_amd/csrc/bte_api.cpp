@@ -234,6 +234,12 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       set_err("plan P must be 1, 2 or 4 in 1D/2D");
       return BTE_ERR_INVALID;
     }
+    if (pl.R * pl.P > 4) {
+      // the 1D/2D kernel is built for workgroups of at most 256 threads (one
+      // wave per SIMD, with the accumulation registers free for its state)
+      set_err("plan needs R*P <= 4 in 1D/2D");
+      return BTE_ERR_INVALID;
+    }
   }
   if (pl.R < 1 || pl.P < 1 || pl.R * pl.P > 8) {
     set_err("plan needs R >= 1, P >= 1, R*P <= 8");
@@ -1287,9 +1293,9 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
       if (NR > 1 && 32 * NR >= ny) continue;  // mostly idle rows
       const int nS = (ny + 64 * NR - 1) / (64 * NR);
       for (int G : {1, 2})
-        for (int R = 1; R <= std::min(8, nS); R *= 2)
+        for (int R = 1; R <= std::min(4, nS); R *= 2)
           for (int P : {1, 2, 4})
-            if (R * P <= 8) cand.push_back(Plan{G, R, P, kC2, NR});
+            if (R * P <= 4) cand.push_back(Plan{G, R, P, kC2, NR});
     }
   }
   // the current plan is timed first and kept unless another is at least 3%

@@ -20,17 +20,23 @@
 //     with readlane, so no step waits on LDS;
 //   * the per-step inputs, a record {cell of row 0, flags} and the (X, Q) pairs
 //     of the lane's rows, are stored in the skewed order and prefetched a whole
-//     chunk ahead (fp32; half a chunk in fp64) without any conditional, the
-//     schedule being padded; no load inside the chunk loop depends on another
-//     one, so the loads stay in flight across steps and chunks;
+//     chunk ahead (half a chunk when the ring would not fit in ~96 registers)
+//     without any conditional, the schedule being padded; no load inside the
+//     chunk loop depends on another one, and no global access in it sits
+//     behind a branch (masked lanes get an offset past the buffer), so every
+//     wait is for data loaded a chunk earlier;
 //   * boundary inflows are an ordered stream whose chunk values sit in LDS
 //     (gathered two chunks ahead from a padded per-chunk table); a lane finds
 //     its entries from the offset stored in its record;
 //   * the P waves of a workgroup sweep P ordinate groups of one octant in
 //     lockstep; per step each wave stages its per-row sums over its G ordinates
-//     in LDS, and after each chunk the P partials of every cell are added in a
-//     fixed order and written as contiguous row segments (one barrier per chunk,
-//     double-buffered staging for the temperature-only sweep);
+//     in LDS, and the P partials of every cell are added in a fixed order and
+//     written as contiguous row segments: for the temperature-only sweep
+//     (double-buffered staging, one barrier per chunk) during the next chunk's
+//     steps, otherwise after the chunk;
+//   * chunks run in runs of one kind (no boundary entries / x- and row-0
+//     y-inflows / any inflow), each kind in a loop of its own, so that the
+//     registers of the prefetch ring stay in place from chunk to chunk;
 //   * the R wave slots of a workgroup pipeline successive strips (slot r owns
 //     strips r, r+R, ...), the top rows reaching the next slot through its ring.
 #include <hip/hip_runtime.h>
@@ -54,6 +60,20 @@ __device__ __forceinline__ const GAS T* gp(const T* p) {
   return (const GAS T*)p;
 }
 
+// Read-only tables (job list, instance records, group constants, flags, the
+// status written by the previous kernel) read at uniform addresses through the
+// constant address space: scalar loads into SGPRs, so everything derived from
+// them, the loop bounds and the choice of step body included, stays uniform.
+#ifdef __HIP_DEVICE_COMPILE__
+#define CAS __attribute__((address_space(4)))
+#else
+#define CAS  // the host pass only parses the kernels
+#endif
+template <typename T>
+__device__ __forceinline__ const CAS T* cp(const T* p) {
+  return (const CAS T*)p;
+}
+
 template <typename T, int N>
 struct Vec {
   typedef T type __attribute__((ext_vector_type(N)));
@@ -63,6 +83,65 @@ typedef int iv2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ int2 ldrec(const GAS int2* p) {
   const iv2_t v = *(const GAS iv2_t*)p;
   return make_int2(v.x, v.y);
+}
+
+// Raw buffer access with per-lane masking by offset: a byte offset at or past
+// the buffer's size reads 0 and drops a store (the hardware range check), so
+// a masked access needs no branch. Every global access inside the chunk loop
+// is written this way: with no branch around them the memory counters seen
+// by each wait are exact, and a wait for prefetched data never also waits
+// for the loads issued after it.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kBufWord3 = 0x00020000;  // raw 32-bit elements, no swizzle
+constexpr int kOOB = (int)0x80000000;  // past every buffer
+template <typename Ptr>
+__device__ __forceinline__ rsrc_t mkrsrc(Ptr p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ void bst(float v, rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bst(double v, rsrc_t r, int off) {
+  typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ T bld(rsrc_t r, int off);
+template <>
+__device__ __forceinline__ float bld<float>(rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ int bld<int>(rsrc_t r, int off) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// a record {cell, flags} and a vector of V at byte offsets voff (per lane) +
+// soff (uniform)
+__device__ __forceinline__ int2 ldrec_b(rsrc_t r, int voff, int soff) {
+  typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+  const u2_t v = __builtin_bit_cast(u2_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return make_int2((int)v.x, (int)v.y);
+}
+template <typename V>
+__device__ __forceinline__ V ldv(rsrc_t r, int voff, int soff) {
+  constexpr int B = (int)sizeof(V);
+  static_assert(B == 8 || B % 16 == 0, "vector loads of 8 bytes or whole 16-byte parts");
+  if constexpr (B == 8) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    typedef unsigned u4_t __attribute__((ext_vector_type(4)));
+    struct Parts {
+      u4_t q[B / 16];
+    } t;
+#pragma unroll
+    for (int i = 0; i < B / 16; ++i) t.q[i] = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16 * i, soff, 0);
+    return __builtin_bit_cast(V, t);
+  }
 }
 
 // DPP wave_shr:1 (GFX9 encoding 0x138): lane i takes lane i-1, lane 0 keeps `old`.
@@ -119,12 +198,14 @@ constexpr unsigned rowmask(unsigned bits, int nr) {
 enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2 };
 
 template <typename T, int G, int NR, int P, int NACC, int MODE>
-__global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
+__global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
   using namespace s2d;
-  // prefetch distance in steps (divides kC2): a chunk for small records, half
-  // a chunk when one lane-step reads 32 bytes or more
-  constexpr int KD = sizeof(T) * 2 * NR >= 32 ? 4 : 8;
   constexpr int NV = 2 * NR;                  // (X, Q) values of one lane-step
+  // prefetch distance in steps (divides kC2): a whole chunk while the ring of
+  // prefetched records and values fits in ~96 registers (G ordinates' worth
+  // of other state scales with it), half a chunk above that
+  constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1);
+  constexpr int KD = kRingRegs * kC2 * G <= 96 ? kC2 : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
   constexpr int GS = grp_stride(G);
@@ -159,20 +240,20 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
     __syncthreads();
     if (tid == 0) s_job = atomicAdd(&A.counters[0], 1);
     __syncthreads();
-    const int job = s_job;
+    const int job = __builtin_amdgcn_readfirstlane(s_job);
     if (job >= A.n_jobs) break;
-    const JobDev jd = A.jobs[job];
-    const InstDev& I = A.inst[jd.inst];
-    const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+    const JobDev jd = cp(A.jobs)[job];
+    const CAS InstDev& I = cp(A.inst)[jd.inst];
+    const CAS StatusDev* st = cp(reinterpret_cast<const StatusDev*>(I.status));
     if (!A.force && st->done) continue;
     const int iter = st->iter;
 
     // ---- this wave's group: band constants and per-ordinate coefficients
     const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
-    const int4 gi = A.grp_i[g_glob];
+    const int4 gi = cp(A.grp_i)[g_glob];
     const int band = gi.x;
     const int g_loc = gi.z;
-    const T* gt = reinterpret_cast<const T*>(A.grp_t) + (size_t)g_glob * GS;
+    const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
     const T kS = gt[0], cQ = gt[1];
     T a0[G], a1[G], den[G], inv[G], wo0[G], wo1[G];
     T wacc[NACC][G];
@@ -204,9 +285,17 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
     const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
-    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[slot]);
+    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[slot]);
     const size_t part_plane = (size_t)I.n_jobs * I.ncell;
     GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.ncell);
+    // buffer views of the chunk loop's global data (sizes in bytes)
+    const int out_b = cp(I.out_base)[slot];
+    const rsrc_t UBR = mkrsrc(UBF, (unsigned)I.n_bface * (unsigned)sizeof(T));
+    const rsrc_t ITR = mkrsrc(ITAB, (unsigned)((nch + 2) * Ei) * 4u);
+    const rsrc_t OUR = mkrsrc(OUTV, (unsigned)(I.n_out_stride - out_b) * (unsigned)sizeof(T));
+    rsrc_t PRS[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
 
     // ---- clear the ring; prefill the ring read by strip 0 (slot R-1's) with
     //      the bottom-wall inflow of every column
@@ -252,14 +341,25 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
     double tg0 = 0.0, tg1 = 0.0;
     int out_tot = 0;
 
+    // ---- per-step inputs, prefetched KD steps ahead into a register ring;
+    //      every chunk reads them through buffer views based at its first
+    //      prefetched step (the schedule is padded by kPad2 >= KD steps)
+    const int lo_rec = lane * 8, lo_xq = lane * (int)sizeof(VX);
+    auto vbase = [&](auto base, int esz, int step0) {
+      return mkrsrc((const char*)base + (size_t)step0 * 64 * esz, 0xFFFFFFFFu);
+    };
     int2 RR[KD];
     VX RX[KD];
     VX RXF[KD];
+    {
+      const rsrc_t rr = vbase(REC, 8, 0), rx = vbase(XQ, sizeof(VX), 0);
+      const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), 0) : rx;
 #pragma unroll
-    for (int u = 0; u < KD; ++u) {
-      RR[u] = ldrec(REC + u * 64 + lane);
-      RX[u] = XQ[u * 64 + lane];
-      if (MODE == M2_TAUGRAD) RXF[u] = XF[u * 64 + lane];
+      for (int u = 0; u < KD; ++u) {
+        RR[u] = ldrec_b(rr, lo_rec, u * 64 * 8);
+        RX[u] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_TAUGRAD) RXF[u] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
+      }
     }
 
     // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
@@ -281,26 +381,106 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
     };
     chunk_cols();
     // per-chunk flags (CF2_*), uniform: scalar loads from read-only memory
-    const __attribute__((address_space(4))) int* CFL =
-        (const __attribute__((address_space(4))) int*)(I.chunk_fl + slot * (nch + 1));
+    const CAS int* CFL = cp(I.chunk_fl) + slot * (nch + 1);
     int cfl = CFL[0];
+    int cfl_next = CFL[nch > 0 ? 1 : 0];
+    // let the loads above land before the chunk loop: the loop's waits are
+    // counted for its steady state (a whole chunk of loads after each slot's),
+    // which a partly drained prologue would otherwise cut to its own shorter
+    // tail for every chunk
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unchanged
 
-    for (int ch = 0; ch < nch; ++ch) {
+    // ---- write-out of the staged sums: the P waves of slot r add their
+    //      partials in a fixed order and write contiguous row segments. A
+    //      thread takes whole (lane, step) pairs: pair e -> lane e/8, step e%8,
+    //      so 8 neighbouring threads write 8 consecutive cells of each of the
+    //      lane's rows; the NR rows of a pair are one vector read per wave.
+    //      Temperature-only sweeps (NACC == 1, double-buffered staging) write a
+    //      chunk out during the next chunk's steps, a batch of pairs read at
+    //      an even step and stored at the odd step after it, so no step waits
+    //      on LDS and the stores need no wait at all.
+    constexpr bool PIPE = NACC == 1;
+    constexpr int PAIRS = kC2 / P;
+    constexpr int NB = PIPE ? (PAIRS < kC2 / 2 ? PAIRS : kC2 / 2) : 1;
+    // pairs per batch: the pipelined write-out splits the pairs over NB
+    // batches; the chunk-end write-out takes a power of two (so it divides
+    // PAIRS) that keeps a batch's reads within ~32 registers
+    constexpr int MB = PIPE ? PAIRS / NB
+                            : pow2_floor(min_c(PAIRS, 32 / (NACC * NR * (int)(sizeof(T) / 4))));
+    static_assert(MB >= 1 && PAIRS % MB == 0 && (!PIPE || MB * NB == PAIRS),
+                  "write-out batches must tile the pairs exactly");
+    const int t_wo = p * 64 + lane;
+    int wvv[MB];
+    // the pipelined write-out holds every wave's partial until the store step
+    // (its adds then wait on nothing); the chunk-end one adds as it reads
+    constexpr int PQ = PIPE ? P : 1;
+    VR wraw[NACC][MB][PQ];
+    // read a batch of pairs of chunk chw (its records and every wave's sums)
+    auto wo_read = [&](int b, int chw) {
+      const int bw = chw & 1;
+      const int* scr = scid + (bw * R + r) * kC2 * 64;
+#pragma unroll
+      for (int mi = 0; mi < MB; ++mi) {
+        const int e = (b * MB + mi) * (P * 64) + t_wo;
+        const int ln = e >> 3, cc = e & 7;
+        wvv[mi] = scr[cc * 64 + ln];
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+          const T* sp = stage + (size_t)(NACC == 1 ? bw : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + ln * NR;
+          if constexpr (PIPE) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) wraw[a][mi][q] = *reinterpret_cast<const VR*>(sp + (size_t)q * R * kC2 * RS);
+          } else {
+            wraw[a][mi][0] = *reinterpret_cast<const VR*>(sp);
+#pragma unroll
+            for (int q = 1; q < P; ++q) wraw[a][mi][0] += *reinterpret_cast<const VR*>(sp + (size_t)q * R * kC2 * RS);
+          }
+        }
+      }
+    };
+    // add the batch's partials and store the rows inside the grid (inactive
+    // cells' entries are ignored by the finalize); `on` false: nothing
+    auto wo_store = [&](bool on) {
+#pragma unroll
+      for (int mi = 0; mi < MB; ++mi) {
+        const int v = on ? wvv[mi] : -1;
+        const int cid0 = v >> 5;
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+          VR sm = wraw[a][mi][0];
+#pragma unroll
+          for (int q = 1; q < PQ; ++q) sm += wraw[a][mi][q];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const bool ok = (v >= 0) & ((((v >> 4) | (v >> k)) & 1) != 0);  // no branch
+            bst(sm[k], PRS[a], ok ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
+          }
+        }
+      }
+    };
+
+    // ---- one chunk of kC2 steps; IN: 0 no inflow entries in the chunk, 1
+    //      x-inflows and row-0 y-inflows only (folded into the chain inputs),
+    //      2 any inflow (its own chain with selects); OUT: diffuse-wall
+    //      outflow entries present
+    auto chunk = [&](auto in_tag, auto out_tag, const int ch) {
+      constexpr int IN = decltype(in_tag)::value;
+      constexpr bool OUT = decltype(out_tag)::value;
       const int bufi = ch & 1;
       const T* inbuf = my_inb + bufi * E;
       T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
       int* scw = scid + (bufi * R + r) * kC2 * 64;
       int out_cnt = 0;
+      const rsrc_t rr = vbase(REC, 8, ch * kC2 + KD), rx = vbase(XQ, sizeof(VX), ch * kC2 + KD);
+      const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), ch * kC2 + KD) : rx;
 
-      // one step; IN: 0 no inflow entries in this chunk, 1 x-inflows and
-      // row-0 y-inflows only (folded into the chain inputs), 2 any inflow (its
-      // own chain with selects); OUT: diffuse-wall outflow entries present
-      auto step = [&](auto in_tag, auto out_tag, const int u) {
-        constexpr int IN = decltype(in_tag)::value;
-        constexpr bool OUT = decltype(out_tag)::value;
+      auto step = [&](const int u) {
         const int sl = u % KD;
-        const int tau = ch * kC2 + u;
         const int2 rec = RR[sl];
+        // both halves of the record stay live until here, whatever the body
+        // uses: a half the body ignores would otherwise free its register
+        // while the load is in flight, and reusing it waits for that load
+        asm volatile("" ::"v"(rec.x), "v"(rec.y));
         const VX xq = RX[sl];
         VX xf;
         if (MODE == M2_TAUGRAD) xf = RXF[sl];
@@ -380,7 +560,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
           }
           *reinterpret_cast<VR*>(stg0 + (size_t)(NACC == 1 ? 0 : a) * plane_sz + u * RS + lane * NR) = acc;
         }
-        if (p == 0) scw[u * 64 + lane] = rec.x;
+        scw[u * 64 + lane] = rec.x;  // every wave of the slot writes the same records
 
         // ---- the strip's top row for the next slot (lane 63)
         const int wc = rdlane(wcv, u);
@@ -423,8 +603,8 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
             }
         }
         if (MODE == M2_TAUGRAD && rec.x >= 0) {
-          const T* wt0 = gt + go_wt(G, 0);
-          const T* wt1 = gt + go_wt(G, 1);
+          const CAS T* wt0 = gt + go_wt(G, 0);
+          const CAS T* wt1 = gt + go_wt(G, 1);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
             if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
@@ -442,116 +622,113 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(SweepArgs A) {
             }
         }
 
-        // ---- prefetch step tau + KD into the slot just consumed (the schedule
-        //      is padded by kPad2 >= KD steps, so the read is always in bounds);
-        //      the fence keeps the loads after the last use of the old values,
-        //      so every slot is reloaded in place
-        __builtin_amdgcn_sched_barrier(0);
-        {
-          const long long tn = (long long)(tau + KD) * 64;  // uniform part of the address
-          RR[sl] = ldrec(REC + tn + lane);
-          const GAS VX* xb = XQ + tn;
-          RX[sl] = xb[lane];
-          if (MODE == M2_TAUGRAD) {
-            const GAS VX* fb = XF + tn;
-            RXF[sl] = fb[lane];
-          }
+        // ---- the previous chunk's write-out (temperature-only sweeps)
+        if constexpr (PIPE) {
+          if (u % 2 == 0 && u / 2 < NB) wo_read(u / 2, ch - 1);
+          if (u % 2 == 1 && u / 2 < NB) wo_store(ch > 0);
         }
+        // ---- inflow pipeline, one stream row per step at the chunk's end,
+        //      rows in descending order: values of chunk ch+1 to LDS (a row
+        //      past the stream writes row 0, which row 0's own write then
+        //      replaces: no branch); gather chunk ch+2's values (a slot of -1
+        //      reads 0); load the face slots of chunk ch+3
+        if (u >= kC2 - kEPL) {
+          const int m = kC2 - 1 - u;
+          my_inb[((ch + 1) & 1) * E + (m < NE ? m : 0) * 64 + lane] = inval[m];
+          inval[m] = bld<T>(UBR, slot_n[m] * (int)sizeof(T));
+          slot_n[m] = bld<int>(ITR, m < NE && ch + 3 < nch + 2 ? ((ch + 3) * Ei + m * 64 + lane) * 4 : kOOB);
+        }
+
+        // ---- prefetch step ch*kC2 + u + KD into the slot just consumed; the
+        //      fence keeps the loads after the last use of the old values, so
+        //      every slot is reloaded in place
+        __builtin_amdgcn_sched_barrier(0);
+        RR[sl] = ldrec_b(rr, lo_rec, u * 64 * 8);
+        RX[sl] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
       };
-      // the chunk's flags (read a chunk ahead with a scalar load) pick the
-      // body: most chunks have no boundary entries at all
-      using I0 = std::integral_constant<int, 0>;
-      using I1 = std::integral_constant<int, 1>;
-      using I2 = std::integral_constant<int, 2>;
-      using B0 = std::integral_constant<bool, false>;
-      using B1 = std::integral_constant<bool, true>;
-      if (cfl == 0) {
 #pragma unroll
-        for (int u = 0; u < kC2; ++u) step(I0(), B0(), u);
-      } else if (!(cfl & CF2_INY_UP)) {
-#pragma unroll
-        for (int u = 0; u < kC2; ++u) step(I1(), B1(), u);
-      } else {
-#pragma unroll
-        for (int u = 0; u < kC2; ++u) step(I2(), B1(), u);
-      }
+      for (int u = 0; u < kC2; ++u) step(u);
 
       // ---- end of chunk: the staged sums, the ring and the outflow entries
       //      of every wave are complete
       lds_barrier();
-      cfl = CFL[ch + 1];
+      // flags of the next chunk were read a chunk ago; read the one after
+      cfl = cfl_next;
+      cfl_next = CFL[min(ch + 2, nch)];
       chunk_cols();
-      {
-        // the P waves of slot r add their partials in a fixed order and write
-        // contiguous row segments. A thread takes whole (lane, step) pairs:
-        // pair e -> lane e/8, step e%8, so 8 neighbouring threads write 8
-        // consecutive cells of each of the lane's rows; the NR rows of a pair
-        // are one vector read per wave, all reads issued before any add.
-        constexpr int PAIRS = kC2 / P;
-        // pairs per batch: a power of two (so it divides PAIRS) that keeps the
-        // batch's sums within ~32 registers
-        constexpr int MB = pow2_floor(min_c(PAIRS, 32 / (NACC * NR * (int)(sizeof(T) / 4))));
-        static_assert(MB >= 1 && PAIRS % MB == 0, "write-out batches must tile the pairs exactly");
-        const int t = p * 64 + lane;
-        const int* scr = scid + (bufi * R + r) * kC2 * 64;
+      if (OUT) {
+        // flush this chunk's outflow entries (at most 256)
 #pragma unroll
-        for (int m0 = 0; m0 < PAIRS; m0 += MB) {
-          int vv[MB];
-          VR sums[NACC][MB];
-#pragma unroll
-          for (int mi = 0; mi < MB; ++mi) {
-            const int e = (m0 + mi) * (P * 64) + t;
-            const int ln = e >> 3, cc = e & 7;
-            vv[mi] = scr[cc * 64 + ln];
-#pragma unroll
-            for (int a = 0; a < NACC; ++a) {
-              const T* sp =
-                  stage + (size_t)(NACC == 1 ? bufi : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + ln * NR;
-              sums[a][mi] = *reinterpret_cast<const VR*>(sp);
-#pragma unroll
-              for (int q = 1; q < P; ++q) sums[a][mi] += *reinterpret_cast<const VR*>(sp + (size_t)q * R * kC2 * RS);
-            }
-          }
-#pragma unroll
-          for (int mi = 0; mi < MB; ++mi) {
-            if (vv[mi] >= 0) {
-              // rows inside the grid (inactive cells' entries are ignored by
-              // the finalize); usually all NR of them
-              const int cid0 = vv[mi] >> 5;
-              if (vv[mi] & 16) {
-#pragma unroll
-                for (int k = 0; k < NR; ++k)
-#pragma unroll
-                  for (int a = 0; a < NACC; ++a) PARTJ[a * part_plane + cid0 + k * dy] = sums[a][mi][k];
-              } else {
-#pragma unroll
-                for (int k = 0; k < NR; ++k)
-                  if ((vv[mi] >> k) & 1) {
-#pragma unroll
-                    for (int a = 0; a < NACC; ++a) PARTJ[a * part_plane + cid0 + k * dy] = sums[a][mi][k];
-                  }
-              }
-            }
-          }
+        for (int m = 0; m < 4; ++m) {
+          const int e = lane + 64 * m;
+          const T v = my_outb[min(e, A.o_max - 1)];
+          bst(v, OUR, e < out_cnt ? (out_tot + e) * (int)sizeof(T) : kOOB);
         }
+        out_tot += out_cnt;
       }
-      // flush this chunk's outflow entries (at most 256)
+      if constexpr (!PIPE) {
+        // single-buffered staging: write the chunk out now, then wait for
+        // every reader before the next chunk stages again
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (lane + 64 * m < out_cnt) OUTV[out_tot + lane + 64 * m] = my_outb[lane + 64 * m];
-      out_tot += out_cnt;
-      // inflow pipeline: values of chunk ch+1 to LDS; gather chunk ch+2's
-      // values; load the face slots of chunk ch+3 (padded table: in bounds)
-#pragma unroll
-      for (int m = 0; m < kEPL; ++m) {
-        if (m < NE) {
-          my_inb[((ch + 1) & 1) * E + m * 64 + lane] = inval[m];
-          inval[m] = slot_n[m] >= 0 ? UBF[slot_n[m]] : T(0);
-          slot_n[m] = ch + 3 < nch + 2 ? ITAB[(ch + 3) * Ei + m * 64 + lane] : -1;
+        for (int b = 0; b < PAIRS / MB; ++b) {
+          wo_read(b, ch);
+          wo_store(true);
         }
+        lds_barrier();
       }
-      if (NACC > 1) lds_barrier();  // single-buffered staging: wait for every reader
       __builtin_amdgcn_wave_barrier();
+    };
+
+    // runs of chunks of one kind, each in a loop of its own: the registers of
+    // the prefetch ring stay in place within a run (a join of differently
+    // compiled bodies would copy them, waiting for every load in flight);
+    // most chunks have no boundary entries at all
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using B0 = std::integral_constant<bool, false>;
+    using B1 = std::integral_constant<bool, true>;
+    auto kind = [](int fl) { return fl == 0 ? 0 : ((fl & CF2_INY_UP) ? 2 : 1); };
+    // a run's entry copies the ring between the runs' registers; draining
+    // there keeps those copies' loads out of the waits inside the run. Each
+    // run's drain is a distinct instruction (vmcnt(0) with a different, unused
+    // export count) so that none is merged into a common block the compiler
+    // could route around.
+    auto drain0 = []() { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0) expcnt(7)
+    auto drain1 = []() { __builtin_amdgcn_s_waitcnt(0x0F60); };  // vmcnt(0) expcnt(6)
+    auto drain2 = []() { __builtin_amdgcn_s_waitcnt(0x0F50); };  // vmcnt(0) expcnt(5)
+    int ch = 0;
+    while (ch < nch) {
+      const int kd = kind(cfl);
+      if (kd == 0) {
+        drain0();
+        do {
+          chunk(I0(), B0(), ch);
+          ++ch;
+        } while (ch < nch && kind(cfl) == 0);
+      } else if (kd == 1) {
+        drain1();
+        do {
+          chunk(I1(), B1(), ch);
+          ++ch;
+        } while (ch < nch && kind(cfl) == 1);
+      } else {
+        drain2();
+        do {
+          chunk(I2(), B1(), ch);
+          ++ch;
+        } while (ch < nch && kind(cfl) == 2);
+      }
+    }
+    if constexpr (PIPE) {
+      // the last chunk's write-out (its staging is complete: the chunk ended
+      // with a barrier)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        wo_read(b, nch - 1);
+        wo_store(nch > 0);
+      }
     }
 
     if (MODE == M2_TAUGRAD) {

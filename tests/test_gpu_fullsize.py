@@ -118,3 +118,10 @@ def test_oversized_plan_rejected(hip_lib):
     p = bi.square_2d(130, L=0.5e-6, n_bands=4, n_theta=2, n_phi=2)
     with pytest.raises(hip_lib.BTEError, match="LDS"):
         hip_lib.Solver(p, precision="fp64", plan=dict(G=2, R=1, P=4, NR=4))
+
+
+def test_plan_wave_limit_rejected(hip_lib):
+    """The 1D/2D kernel takes at most four waves per workgroup (R*P <= 4)."""
+    p = bi.square_2d(130, L=0.5e-6, n_bands=4, n_theta=2, n_phi=2)
+    with pytest.raises(hip_lib.BTEError, match="R\\*P <= 4"):
+        hip_lib.Solver(p, precision="fp32", plan=dict(G=1, R=2, P=4, NR=1))

@@ -52,7 +52,7 @@ def test_film_1d_converged(hip_lib):
 
 @pytest.mark.parametrize("plan", [dict(G=1, R=1, P=1, NR=1), dict(G=2, R=2, P=1, NR=1),
                                   dict(G=1, R=1, P=2, NR=2), dict(G=2, R=1, P=2, NR=4),
-                                  dict(G=1, R=2, P=4, NR=1)])
+                                  dict(G=1, R=2, P=2, NR=1)])
 def test_square_2d_fp64_plans(hip_lib, plan):
     """Strips processed in sequence and pipelined across waves, a partial last
     strip, one to four rows per lane, one to four waves per workgroup."""

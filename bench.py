@@ -63,8 +63,9 @@ def sweep_source_hash() -> str:
 
 def profiled_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none for this kernel or the sweep sources changed since
-    the counters were taken."""
+    None when it holds none for this kernel or the sweep sources changed since
+    the counters were taken. The summary lists `- sweep source hash: ...` and
+    one `- hbm bytes per launch of <kernel>: <bytes>` line per kernel."""
     path = os.path.join(ROOT, "profiles", "sweep2d_square256_hbm_counters.md")
     if not os.path.exists(path):
         return None
@@ -72,12 +73,12 @@ def profiled_traffic(kernel: str):
     with open(path) as fh:
         for line in fh:
             if line.startswith("- ") and ":" in line:
-                k, v = line[2:].split(":", 1)
-                kv[k.strip()] = v.strip().strip("`")
-    if kv.get("kernel") != kernel or kv.get("sweep source hash") != sweep_source_hash():
+                k, v = line[2:].rsplit(":", 1)
+                kv[k.strip().replace("`", "")] = v.strip().strip("`")
+    if kv.get("sweep source hash") != sweep_source_hash():
         return None
     try:
-        return float(kv["hbm bytes per launch"])
+        return float(kv[f"hbm bytes per launch of {kernel}"])
     except (KeyError, ValueError):
         return None
 

@@ -121,6 +121,7 @@ struct Inst {
   void* d_xqa[2] = {nullptr, nullptr};
   void* d_outv = nullptr;
   void* d_part = nullptr;
+  int part_ld = 0;  // padded row stride of d_part (cells)
   void* d_store = nullptr;
   double* d_tgrad = nullptr;
   std::vector<int> grp_band;    // instance-local group -> band
@@ -314,7 +315,8 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     HIPCHK(pp.alloc(&ov, (size_t)n_grp_inst * S.n_out_stride * es));
     I.d_outv = ov;
     char* pt;
-    HIPCHK(pp.alloc(&pt, (size_t)kNAcc * n_bund * I.hi.ncell * es));
+    I.part_ld = (I.hi.ncell + kPartAlign - 1) / kPartAlign * kPartAlign;
+    HIPCHK(pp.alloc(&pt, (size_t)kNAcc * n_bund * I.part_ld * es));
     I.d_part = pt;
     I.d_store = nullptr;
     I.stored = false;
@@ -349,6 +351,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       d.ubf = adj ? I.d_ubf0 : I.d_ubf;
       d.outv = I.d_outv;
       d.part = I.d_part;
+      d.part_ld = I.part_ld;
       d.store_u = nullptr;
       d.tgrad = I.d_tgrad;
       d.status = reinterpret_cast<int*>((adj ? h->d_st_a : h->d_st_f) + k);

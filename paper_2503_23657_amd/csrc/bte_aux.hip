@@ -9,33 +9,74 @@
 
 namespace bte {
 
-// Sum over the jobs j = js, js + kFinSlices, ... of one partial-sum plane for
-// cell c, in FP64 with four loads in flight; the association is fixed, so the
-// result does not depend on timing.
+// The finalize gathers the jobs' partial sums of kFinCells cells with
+// 16-byte loads: a thread holds VW = 16 / sizeof(T) neighbouring cells and a
+// slice of the jobs (j = js, js + S, ...), eight loads in flight; the S slices
+// of a cell are then added in LDS, pairwise in a fixed order.
 template <typename T>
-__device__ __forceinline__ double job_sum(const T* pl, int n_jobs, int ncell, int c, int js) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+struct FinShape {
+  static constexpr int VW = 16 / (int)sizeof(T);       // cells per load
+  static constexpr int NG = kFinCells / VW;             // cell groups per block
+  static constexpr int S = kFinThreads / NG;            // job slices
+  static_assert(NG * S == kFinThreads && kPartAlign % VW == 0, "finalize shape");
+};
+
+template <typename T>
+__device__ __forceinline__ void job_sum_vec(const T* pl, int n_jobs, int ld, int c0, int js, double* acc) {
+  using Sh = FinShape<T>;
+  typedef T V __attribute__((ext_vector_type(Sh::VW)));
+#pragma unroll
+  for (int e = 0; e < Sh::VW; ++e) acc[e] = 0.0;
   int j = js;
-  for (; j + 3 * kFinSlices < n_jobs; j += 4 * kFinSlices) {
-    s0 += (double)pl[(size_t)j * ncell + c];
-    s1 += (double)pl[(size_t)(j + kFinSlices) * ncell + c];
-    s2 += (double)pl[(size_t)(j + 2 * kFinSlices) * ncell + c];
-    s3 += (double)pl[(size_t)(j + 3 * kFinSlices) * ncell + c];
+  for (; j + 7 * Sh::S < n_jobs; j += 8 * Sh::S) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const V*>(pl + (size_t)(j + u * Sh::S) * ld + c0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int e = 0; e < Sh::VW; ++e) acc[e] += (double)v[u][e];
   }
-  for (; j < n_jobs; j += kFinSlices) s0 += (double)pl[(size_t)j * ncell + c];
-  return (s0 + s1) + (s2 + s3);
+  for (; j < n_jobs; j += Sh::S) {
+    const V v = *reinterpret_cast<const V*>(pl + (size_t)j * ld + c0);
+#pragma unroll
+    for (int e = 0; e < Sh::VW; ++e) acc[e] += (double)v[e];
+  }
 }
 
-// Sum of the kFinSlices job slices of one cell, pairwise in a fixed order.
-__device__ __forceinline__ double slice_sum(const double (*sl)[kFinCells], int cl) {
-  double v[kFinSlices];
+// One plane's per-cell totals: every thread gathers its slice, the slices meet
+// in LDS, and thread cl < kFinCells returns cell cl's total (pairwise over the
+// slices in a fixed order); the others return 0.
+template <typename T>
+__device__ __forceinline__ double plane_total(const T* pl, int n_jobs, int ld, int ncell, int cbase,
+                                              double (*slc)[kFinCells]) {
+  using Sh = FinShape<T>;
+  const int t = threadIdx.x;
+  const int gi = t % Sh::NG, js = t / Sh::NG;
+  const int c0 = cbase + gi * Sh::VW;
+  double acc[Sh::VW];
+  if (c0 < ncell) {
+    job_sum_vec(pl, n_jobs, ld, c0, js, acc);
+  } else {
 #pragma unroll
-  for (int i = 0; i < kFinSlices; ++i) v[i] = sl[i][cl];
+    for (int e = 0; e < Sh::VW; ++e) acc[e] = 0.0;
+  }
 #pragma unroll
-  for (int w = 1; w < kFinSlices; w *= 2)
+  for (int e = 0; e < Sh::VW; ++e) slc[js][gi * Sh::VW + e] = acc[e];
+  __syncthreads();
+  double r = 0.0;
+  if (t < kFinCells) {
+    double v[Sh::S];
 #pragma unroll
-    for (int i = 0; i + w < kFinSlices; i += 2 * w) v[i] += v[i + w];
-  return v[0];
+    for (int i = 0; i < Sh::S; ++i) v[i] = slc[i][t];
+#pragma unroll
+    for (int w = 1; w < Sh::S; w *= 2)
+#pragma unroll
+      for (int i = 0; i + w < Sh::S; i += 2 * w) v[i] += v[i + w];
+    r = v[0];
+  }
+  __syncthreads();  // the next plane reuses slc
+  return r;
 }
 
 // Block-wide reduction of (sum, max, sum, max) over the block's threads;
@@ -59,38 +100,45 @@ __device__ __forceinline__ void block_reduce4(double (*red)[kFinThreads], double
 }
 
 // New state (Eq. updatee0_t: Delta T, or the adjoint lambda), heat flux (Eq. 4)
-// or dJ/dQ, and the residuals of Eq. 22. A block covers kFinCells cells with
-// kFinSlices threads per cell, each adding a slice of the jobs' partial sums.
+// or dJ/dQ, and the residuals of Eq. 22. A block covers kFinCells cells; its
+// threads first gather the jobs' partial sums (plane_total), then thread
+// cl < kFinCells finishes cell cl.
 template <typename T>
 __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const FinInst* FI) {
   __shared__ double red[4][kFinThreads];
-  __shared__ double slc[4][kFinSlices][kFinCells];
-  __shared__ int s_last;
+  __shared__ double slc[FinShape<T>::S][kFinCells];
+  __shared__ int s_last, s_iter;
   const int2 bi = A.blocks[blockIdx.x];
   const InstDev& I = A.inst[bi.x];
   const FinInst& F = FI[bi.x];
   StatusDev* st = reinterpret_cast<StatusDev*>(I.status);
   if (st->done) return;
-  const int iter = st->iter;
+  // thread 0 reads the counter for the block: its read has returned before it
+  // takes the block's ticket below, so the last block's increment can never
+  // reach a block that has not read it yet
+  if (threadIdx.x == 0) s_iter = st->iter;
+  __syncthreads();
+  const int iter = s_iter;
   const int cur = iter & 1, nxt = cur ^ 1;
-  const int cl = threadIdx.x % kFinCells, js = threadIdx.x / kFinCells;
-  const int c = bi.y * kFinCells + cl;
-  const size_t plane = (size_t)I.n_jobs * I.ncell;
+  const int cl = threadIdx.x;  // the cell of threads < kFinCells
+  const int cbase = bi.y * kFinCells;
+  const int c = cbase + cl;
+  const size_t plane = (size_t)I.n_jobs * I.part_ld;
   const T* part = reinterpret_cast<const T*>(I.part);
   const bool adj = (A.flags & FIN_ADJ) != 0, withq = (A.flags & FIN_Q) != 0;
   const int nq = withq ? (adj ? 1 : I.dim) : 0;
-  const bool act = c < I.ncell && F.active[c];
-  // ---- the job slices of every needed plane
-  if (act) {
-    slc[0][js][cl] = job_sum(part, I.n_jobs, I.ncell, c, js);
-    for (int d = 0; d < nq; ++d) slc[1 + d][js][cl] = job_sum(part + (size_t)(1 + d) * plane, I.n_jobs, I.ncell, c, js);
-  }
-  __syncthreads();
+  // ---- per-cell totals of every needed plane (inactive cells' entries are
+  //      gathered with their neighbours and dropped below)
+  double tot[4];
+  tot[0] = plane_total(part, I.n_jobs, I.part_ld, I.ncell, cbase, slc);
+  for (int d = 0; d < nq; ++d) tot[1 + d] = plane_total(part + (size_t)(1 + d) * plane, I.n_jobs, I.part_ld, I.ncell, cbase, slc);
+  const bool in_blk = cl < kFinCells && c < I.ncell;
+  const bool act = in_blk && F.active[c];
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // sum dT^2, max |x|, sum d|q|^2, max |q| (+inf: non-finite)
-  if (js == 0 && c < I.ncell) {
+  if (in_blk) {
     if (act) {
       double x = adj ? F.g[c] : 0.0;
-      x += slice_sum(slc[0], cl);
+      x += tot[0];
       const double old = F.X[cur][c];
       F.X[nxt][c] = x;
       // scatter into the skewed layouts of every octant
@@ -105,11 +153,11 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
       v[1] = fabs(x);
       if (withq) {
         if (adj) {
-          F.q[c] = slice_sum(slc[1], cl);
+          F.q[c] = tot[1];
         } else {
           double m2 = 0.0;
           for (int d2 = 0; d2 < I.dim; ++d2) {
-            const double qv = slice_sum(slc[1 + d2], cl);
+            const double qv = tot[1 + d2];
             F.q[(size_t)c * I.dim + d2] = qv;
             m2 += qv * qv;
             bad = bad || !isfinite(qv);
@@ -135,14 +183,14 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
   }
   if (!(A.flags & FIN_CHECK)) {
     // no residual needed: only the iteration counter moves (last block);
-    // non-finite values are caught at the next check
+    // non-finite values are caught at the next check. No block reads another
+    // block's results here, and each block read the counter before taking its
+    // ticket, so no fence is needed: the kernel's end publishes the writes.
     if (threadIdx.x == 0) {
-      __threadfence();
       const int t = atomicAdd(&st->ticket, 1);
       if (t == A.n_blocks_inst[bi.x] - 1) {
         st->ticket = 0;
         st->iter = iter + 1;
-        __threadfence();
       }
     }
     return;

@@ -107,7 +107,8 @@ struct InstDev {
   const void* xf;           // tau-gradient pass: forward (Delta T, Q) pairs per position
   const void* ubf;          // [B][n_bface] inflow u of every boundary face (K); zeros for the adjoint
   void* outv;               // [n_grp][n_out_entries_of_octant] outflow stream values
-  void* part;               // [kNAcc][n_jobs][ncell] partial sums (sweep precision)
+  void* part;               // [kNAcc][n_jobs][part_ld] partial sums (sweep precision)
+  int part_ld;              // row stride of part: ncell rounded up to a multiple of 4
   void* store_u;            // [n_grp][ncell][G] angular field u (forward, when stored)
   double* tgrad;            // [n_grp][2] tau-gradient partial sums
   int* status;              // StatusDev
@@ -173,9 +174,9 @@ struct SweepArgs {
 
 // ---------------------------------------------------------------- aux kernels
 enum { FIN_Q = 1, FIN_CHECK = 2, FIN_ADJ = 4, FIN_QPREV = 8 };
-constexpr int kFinCells = 256;                        // cells per finalize block
-constexpr int kFinSlices = 4;                         // job slices per cell
-constexpr int kFinThreads = kFinCells * kFinSlices;   // threads per finalize block
+constexpr int kFinCells = 256;    // cells per finalize block
+constexpr int kFinThreads = 512;  // threads per finalize block: cell groups x job slices
+constexpr int kPartAlign = 4;     // partial-sum rows are padded to this many cells
 
 struct FinArgs {
   const InstDev* inst;

@@ -183,8 +183,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const GAS int* ISLOT = gp(I.in_slot);
     const GAS int* ich = gp(I.in_chunk + (size_t)(o * R + r) * (nch + 1));
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[o * R + r]);
-    const size_t part_plane = (size_t)I.n_jobs * I.ncell;
-    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.ncell);
+    const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
     const int zmask = L3 ? I.ring - 1 : 0;
     const int zlag = L3 ? I.lag : 0;
 

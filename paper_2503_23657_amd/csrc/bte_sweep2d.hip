@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const int nch = T_steps / kC2;
     const int nx = I.nx, ny = I.ny;
     const int du = I.du, n_strip = I.n_strip;
+    const bool ring_w = n_strip > 1;  // some strip has a successor
     const int H = 64 * NR;
     const int dy = (o & 2) ? -nx : nx;  // cell-index step from row k to row k+1
     const long long slot = (long long)o * R + r;
@@ -286,8 +287,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[slot]);
-    const size_t part_plane = (size_t)I.n_jobs * I.ncell;
-    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.ncell);
+    const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
     // buffer views of the chunk loop's global data (sizes in bytes)
     const int out_b = cp(I.out_base)[slot];
     const rsrc_t UBR = mkrsrc(UBF, (unsigned)I.n_bface * (unsigned)sizeof(T));
@@ -438,8 +439,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         }
       }
     };
-    // add the batch's partials and store the rows inside the grid (inactive
-    // cells' entries are ignored by the finalize); `on` false: nothing
+    // add the batch's partials and store the lane's rows (inactive cells'
+    // entries are ignored by the finalize); `on` false: nothing
     auto wo_store = [&](bool on) {
 #pragma unroll
       for (int mi = 0; mi < MB; ++mi) {
@@ -450,11 +451,10 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           VR sm = wraw[a][mi][0];
 #pragma unroll
           for (int q = 1; q < PQ; ++q) sm += wraw[a][mi][q];
+          // a row of the lane outside the grid has a cell index past either
+          // end of the partial-sum plane, so the buffer's range check drops it
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const bool ok = (v >= 0) & ((((v >> 4) | (v >> k)) & 1) != 0);  // no branch
-            bst(sm[k], PRS[a], ok ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
-          }
+          for (int k = 0; k < NR; ++k) bst(sm[k], PRS[a], v >= 0 ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
         }
       }
     };
@@ -562,11 +562,14 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         }
         scw[u * 64 + lane] = rec.x;  // every wave of the slot writes the same records
 
-        // ---- the strip's top row for the next slot (lane 63)
-        const int wc = rdlane(wcv, u);
-        if (lane == 63) {
+        // ---- the strip's top row for the next slot (lane 63), when a strip
+        //      follows at all
+        if (ring_w) {
+          const int wc = rdlane(wcv, u);
+          if (lane == 63) {
 #pragma unroll
-          for (int g = 0; g < G; ++g) my_ring[wc + g] = f[g][NR - 1];
+            for (int g = 0; g < G; ++g) my_ring[wc + g] = f[g][NR - 1];
+          }
         }
 
         // ---- diffuse-wall outflow stream: rows, then axes, then lanes

@@ -399,21 +399,22 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   SweepArgs& sa = h->sa;
   memset(&sa, 0, sizeof(sa));
   if (!L3) {
-    // 1D/2D: ring [P][R][W_max + 1][G], cell ids [2][R][kC2][64], inflow
-    // [P*R][2][E], outflow [P*R][o_max], staging [planes][P*R][kC2][64*NR + 4]
-    // with max(2, nacc) planes (double-buffered for the temperature-only sweep)
+    // 1D/2D: ring [P][R][W_max + 1][G], cell ids [2][R][kC2][72], inflow
+    // [P*R][2][E], outflow [P*R][o_max], staging [planes][P*R][kC2][64*NR + 8
+    // dwords] with max(2, nacc) planes (double-buffered for the
+    // temperature-only sweep)
     int E = 64;
     for (auto& I : h->inst) E = std::max(E, I.sch.in_E);
     sa.lds_zring = (int)off;
     off += al((size_t)P * R * (W_max + 1) * G * es);
     sa.lds_cid = (int)off;
-    off += al((size_t)2 * R * kC2 * 64 * 4);
+    off += al((size_t)2 * R * kC2 * (64 + 8) * 4);  // records, rows padded to 72 ints
     sa.lds_in = (int)off;
     off += al((size_t)P * R * 2 * E * es);
     sa.lds_out = (int)off;
     off += al((size_t)P * R * o_max * es);
     sa.lds_stage = (int)off;
-    h->lds_stage_plane = al((size_t)P * R * kC2 * (64 * pl.NR + 4) * es);
+    h->lds_stage_plane = al((size_t)P * R * kC2 * (64 * pl.NR + 32 / es) * es);  // rows padded by 8 dwords
     off += (size_t)std::max(2, h->nacc_max) * h->lds_stage_plane;
     sa.lds_total = (int)off;
     if (off > 160 * 1024 - 64) {

@@ -203,13 +203,18 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
   constexpr int NV = 2 * NR;                  // (X, Q) values of one lane-step
   // prefetch distance in steps (divides kC2): a whole chunk while the ring of
   // prefetched records and values fits in ~96 registers (G ordinates' worth
-  // of other state scales with it), half a chunk above that
+  // of other state scales with it), half a chunk above that; a chunk and half
+  // a chunk time the same on the bench shapes, so registers decide
   constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1);
   constexpr int KD = kRingRegs * kC2 * G <= 96 ? kC2 : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
   constexpr int GS = grp_stride(G);
-  constexpr int RS = 64 * NR + 4;             // staged row stride (elements)
+  // staged row stride (elements) and record row stride (ints): 8 dwords of
+  // padding put the (step, lane) pairs a write-out read takes in one LDS pass
+  // on distinct banks
+  constexpr int RS = 64 * NR + 32 / (int)sizeof(T);
+  constexpr int CS = 64 + 8;
   constexpr int kEPL = 4;                     // inflow entries per lane per chunk (<= 256)
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_job;
@@ -225,7 +230,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
   const int E = A.e_max;  // LDS inflow buffer entries per chunk (multiple of 64)
 
   T* ring = reinterpret_cast<T*>(lds + A.lds_zring);    // [P][R][W_max + 1][G] (+1: dummy slot)
-  int* scid = reinterpret_cast<int*>(lds + A.lds_cid);  // [2][R][kC2][64]
+  int* scid = reinterpret_cast<int*>(lds + A.lds_cid);  // [2][R][kC2][CS]
   T* inb = reinterpret_cast<T*>(lds + A.lds_in);        // [P*R][2][E]
   T* outb = reinterpret_cast<T*>(lds + A.lds_out);      // [P*R][o_max]
   T* stage = reinterpret_cast<T*>(lds + A.lds_stage);   // [planes][P*R][kC2][RS]
@@ -419,12 +424,12 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     // read a batch of pairs of chunk chw (its records and every wave's sums)
     auto wo_read = [&](int b, int chw) {
       const int bw = chw & 1;
-      const int* scr = scid + (bw * R + r) * kC2 * 64;
+      const int* scr = scid + (bw * R + r) * kC2 * CS;
 #pragma unroll
       for (int mi = 0; mi < MB; ++mi) {
         const int e = (b * MB + mi) * (P * 64) + t_wo;
         const int ln = e >> 3, cc = e & 7;
-        wvv[mi] = scr[cc * 64 + ln];
+        wvv[mi] = scr[cc * CS + ln];
 #pragma unroll
         for (int a = 0; a < NACC; ++a) {
           const T* sp = stage + (size_t)(NACC == 1 ? bw : a) * plane_sz + (size_t)r * kC2 * RS + cc * RS + ln * NR;
@@ -469,7 +474,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       const int bufi = ch & 1;
       const T* inbuf = my_inb + bufi * E;
       T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
-      int* scw = scid + (bufi * R + r) * kC2 * 64;
+      int* scw = scid + (bufi * R + r) * kC2 * CS;
       int out_cnt = 0;
       const rsrc_t rr = vbase(REC, 8, ch * kC2 + KD), rx = vbase(XQ, sizeof(VX), ch * kC2 + KD);
       const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), ch * kC2 + KD) : rx;
@@ -560,7 +565,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           }
           *reinterpret_cast<VR*>(stg0 + (size_t)(NACC == 1 ? 0 : a) * plane_sz + u * RS + lane * NR) = acc;
         }
-        scw[u * 64 + lane] = rec.x;  // every wave of the slot writes the same records
+        scw[u * CS + lane] = rec.x;  // every wave of the slot writes the same records
 
         // ---- the strip's top row for the next slot (lane 63), when a strip
         //      follows at all

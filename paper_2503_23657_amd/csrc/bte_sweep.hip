@@ -89,6 +89,20 @@ __device__ __forceinline__ double2 ld2(const GAS double2* p) {
   const dv2_t v = *(const GAS dv2_t*)p;
   return make_double2(v.x, v.y);
 }
+// Read-only tables (job list, instance records, group constants, the status
+// written by the previous kernel) read at uniform addresses through the
+// constant address space: scalar loads into SGPRs, so everything derived from
+// them stays uniform.
+#ifdef __HIP_DEVICE_COMPILE__
+#define CAS __attribute__((address_space(4)))
+#else
+#define CAS  // the host pass only parses the kernels
+#endif
+template <typename T>
+__device__ __forceinline__ const CAS T* cp(const T* p) {
+  return (const CAS T*)p;
+}
+
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
@@ -144,20 +158,20 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     __syncthreads();
     if (tid == 0) s_job = atomicAdd(&A.counters[0], 1);
     __syncthreads();
-    const int job = s_job;
+    const int job = __builtin_amdgcn_readfirstlane(s_job);
     if (job >= A.n_jobs) break;
-    const JobDev jd = A.jobs[job];
-    const InstDev& I = A.inst[jd.inst];
-    const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+    const JobDev jd = cp(A.jobs)[job];
+    const CAS InstDev& I = cp(A.inst)[jd.inst];
+    const CAS StatusDev* st = cp(reinterpret_cast<const StatusDev*>(I.status));
     if (!A.force && st->done) continue;
     const int iter = st->iter;
 
     // ---- this wave's group: band constants and per-ordinate coefficients
     const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
-    const int4 gi = A.grp_i[g_glob];
+    const int4 gi = cp(A.grp_i)[g_glob];
     const int band = gi.x;
     const int g_loc = gi.z;
-    const T* gt = reinterpret_cast<const T*>(A.grp_t) + (size_t)g_glob * GS;
+    const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
     const T kS = gt[0], cQ = gt[1];
     T a0[G], a1[G], a2[G], den[G], inv[G];
     T wacc[NACC][G];
@@ -182,7 +196,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
     const GAS int* ISLOT = gp(I.in_slot);
     const GAS int* ich = gp(I.in_chunk + (size_t)(o * R + r) * (nch + 1));
-    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + I.out_base[o * R + r]);
+    GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[o * R + r]);
     const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
     GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
     const int zmask = L3 ? I.ring - 1 : 0;
@@ -415,7 +429,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
             const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = L3 && (fl & F_OUT_Z);
             const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = L3 ? ballot64(oz) : 0ull;
             int k = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
-            const T* wo = gt + go_wo(G, 0);
+            const CAS T* wo = gt + go_wo(G, 0);
             if (ox) {
               T v = T(0);
 #pragma unroll
@@ -445,8 +459,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           }
           if (MODE == M_TAUGRAD && cid >= 0 && (fl & F_ACTIVE)) {
             const GAS T* su = gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + cid) * G);
-            const T* wt0 = gt + go_wt(G, 0);
-            const T* wt1 = gt + go_wt(G, 1);
+            const CAS T* wt0 = gt + go_wt(G, 0);
+            const CAS T* wt1 = gt + go_wt(G, 1);
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {

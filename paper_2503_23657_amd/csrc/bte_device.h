@@ -65,10 +65,15 @@ constexpr uint32_t F2_OUTY = 1u << 4;
 constexpr int F2_ROW_BITS = 5;
 constexpr int F2_INOFF_SHIFT = 20;
 constexpr uint32_t F2_INOFF_MASK = 0xFFu;
+// the lane enters its strip at the x wall in this step: its NR x-inflows are the
+// stream entries from its offset on (rows ascending, -1 for a row without one)
+// and replace the rows' x-upwind values; no other inflow in the lane-step
+constexpr uint32_t F2_XSTART = 1u << 28;
 // per-chunk flags of the 1D/2D schedule
 constexpr int CF2_IN = 1;       // some inflow entry in the chunk
 constexpr int CF2_INY_UP = 2;   // some y-inflow on a row k >= 1 of a lane
 constexpr int CF2_OUT = 4;      // some outflow entry in the chunk
+constexpr int CF2_XST = 8;      // some lane-step with F2_XSTART in the chunk
 
 // group coefficient record: GS(G) values of the sweep type, in this order
 //   kS, cQ, a[3][G], den[G], wacc[kNAcc][G], wo[3][G], wt[2][G], inv[G]

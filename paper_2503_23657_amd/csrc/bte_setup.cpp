@@ -367,6 +367,32 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
           int cid0 = -1;
           const int in_first = (int)s.in_slot.size() - chk[tau / C];
           bool any_in = false;
+          // a lane entering its strip at the x wall with no other inflow takes
+          // its x-inflows as NR consecutive entries (F2_XSTART) instead of
+          // per-row flags
+          bool xstart = ip == 0;
+          for (int k = 0; k < NR && xstart; ++k) {
+            const int kp = sidx * H + l * NR + k;
+            if (kp >= ny) break;
+            const int iy = dim >= 2 ? (fy ? ny - 1 - kp : kp) : 0;
+            const int cell = ix + nx * iy;
+            if (!hi.active[cell]) continue;
+            if (dim >= 2 && kp > 0 && hi.bslot[(size_t)cell * 6 + up[1]] >= 0) xstart = false;
+          }
+          if (xstart) {
+            fl |= F2_XSTART;
+            for (int k = 0; k < NR; ++k) {
+              const int kp = sidx * H + l * NR + k;
+              int su = -1;
+              if (kp < ny) {
+                const int iy = dim >= 2 ? (fy ? ny - 1 - kp : kp) : 0;
+                const int cell = ix + nx * iy;
+                if (hi.active[cell]) su = hi.bslot[(size_t)cell * 6 + up[0]];
+              }
+              s.in_slot.push_back(su);
+            }
+            any_in = true;
+          }
           for (int k = 0; k < NR; ++k) {
             const int kp = sidx * H + l * NR + k;
             if (kp >= ny) break;
@@ -380,6 +406,7 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
             for (int d = 0; d < dim; ++d) {
               const int su = hi.bslot[(size_t)cell * 6 + up[d]];
               if (su < 0) continue;
+              if (d == 0 && xstart) continue;  // taken as an F2_XSTART entry
               if (d == 1 && kp == 0) {
                 // strip 0, lane 0, row 0: the lane-0 ghost is prefilled with this face
                 s.pre_slot[(size_t)o * nx + ip] = su;
@@ -472,6 +499,7 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
               if (fl & in_all) cf |= CF2_IN;
               if (fl & in_up) cf |= CF2_INY_UP;
               if (fl & out_all) cf |= CF2_OUT;
+              if (fl & F2_XSTART) cf |= CF2_XST;
             }
           s.chunk_fl[((size_t)o * R + r) * (nch + 1) + ch] = cf;
         }

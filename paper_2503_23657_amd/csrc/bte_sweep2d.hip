@@ -464,13 +464,15 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       }
     };
 
-    // ---- one chunk of kC2 steps; IN: 0 no inflow entries in the chunk, 1
-    //      x-inflows and row-0 y-inflows only (folded into the chain inputs),
-    //      2 any inflow (its own chain with selects); OUT: diffuse-wall
-    //      outflow entries present
-    auto chunk = [&](auto in_tag, auto out_tag, const int ch) {
+    // ---- one chunk of kC2 steps; IN: 0 no flagged inflow entries in the
+    //      chunk, 1 x-inflows and row-0 y-inflows only (folded into the chain
+    //      inputs), 2 any inflow (its own chain with selects); OUT: diffuse-wall
+    //      outflow entries present; XS: lanes entering their strip at the x wall
+    //      (F2_XSTART), whose x-inflows are read from LDS a step ahead
+    auto chunk = [&](auto in_tag, auto out_tag, auto xs_tag, const int ch) {
       constexpr int IN = decltype(in_tag)::value;
       constexpr bool OUT = decltype(out_tag)::value;
+      constexpr bool XS = decltype(xs_tag)::value;
       const int bufi = ch & 1;
       const T* inbuf = my_inb + bufi * E;
       T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
@@ -478,6 +480,19 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       int out_cnt = 0;
       const rsrc_t rr = vbase(REC, 8, ch * kC2 + KD), rx = vbase(XQ, sizeof(VX), ch * kC2 + KD);
       const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), ch * kC2 + KD) : rx;
+      // strip-entry x-inflows of the step about to run (read one step ahead;
+      // the chunk's first step reads its own after the chunk barrier)
+      // (two register sets by step parity, so no value is copied)
+      T xv[2][NR];
+      auto read_xv = [&](const int2 rnext, T* dst) {
+        // a lane-step's entries end inside the chunk's stream: clamping the
+        // offset keeps the reads of the other lanes in bounds
+        const int e0 = min((int)(((unsigned)rnext.y >> F2_INOFF_SHIFT) & F2_INOFF_MASK), E - NR);
+        const T* ip = inbuf + e0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) dst[k] = ip[k];
+      };
+      if constexpr (XS) read_xv(RR[0], xv[0]);
 
       auto step = [&](const int u) {
         const int sl = u % KD;
@@ -499,6 +514,17 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         T zc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), f[g][NR - 1]);
+
+        // a lane entering its strip at the x wall takes its x-inflows as the
+        // rows' x-upwind values (after the lane below has had the old top row)
+        if constexpr (XS) {
+          const bool xs = (fl & F2_XSTART) != 0;
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int g = 0; g < G; ++g) f[g][k] = xs ? xv[u & 1][k] * den[g] : f[g][k];
+          if (u + 1 < kC2) read_xv(RR[(u + 1) % KD], xv[(u + 1) & 1]);
+        }
 
         constexpr unsigned kInAll = rowmask(F2_INX | F2_INY, NR);
         if (IN == 1 && __ballot(fl & kInAll) != 0ull) {
@@ -691,13 +717,16 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     // runs of chunks of one kind, each in a loop of its own: the registers of
     // the prefetch ring stay in place within a run (a join of differently
     // compiled bodies would copy them, waiting for every load in flight);
-    // most chunks have no boundary entries at all
+    // most chunks have no boundary entries at all, and on a rectangle the rest
+    // only have lanes entering their strip at the x wall (kind 3)
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using B0 = std::integral_constant<bool, false>;
     using B1 = std::integral_constant<bool, true>;
-    auto kind = [](int fl) { return fl == 0 ? 0 : ((fl & CF2_INY_UP) ? 2 : 1); };
+    auto kind = [](int fl) {
+      return fl == 0 ? 0 : (fl == CF2_XST ? 3 : ((fl & CF2_INY_UP) ? 2 : 1));
+    };
     // a run's entry copies the ring between the runs' registers; draining
     // there keeps those copies' loads out of the waits inside the run. Each
     // run's drain is a distinct instruction (vmcnt(0) with a different, unused
@@ -706,25 +735,32 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     auto drain0 = []() { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0) expcnt(7)
     auto drain1 = []() { __builtin_amdgcn_s_waitcnt(0x0F60); };  // vmcnt(0) expcnt(6)
     auto drain2 = []() { __builtin_amdgcn_s_waitcnt(0x0F50); };  // vmcnt(0) expcnt(5)
+    auto drain3 = []() { __builtin_amdgcn_s_waitcnt(0x0F40); };  // vmcnt(0) expcnt(4)
     int ch = 0;
     while (ch < nch) {
       const int kd = kind(cfl);
       if (kd == 0) {
         drain0();
         do {
-          chunk(I0(), B0(), ch);
+          chunk(I0(), B0(), B0(), ch);
           ++ch;
         } while (ch < nch && kind(cfl) == 0);
+      } else if (kd == 3) {
+        drain3();
+        do {
+          chunk(I0(), B0(), B1(), ch);
+          ++ch;
+        } while (ch < nch && kind(cfl) == 3);
       } else if (kd == 1) {
         drain1();
         do {
-          chunk(I1(), B1(), ch);
+          chunk(I1(), B1(), B1(), ch);
           ++ch;
         } while (ch < nch && kind(cfl) == 1);
       } else {
         drain2();
         do {
-          chunk(I2(), B1(), ch);
+          chunk(I2(), B1(), B1(), ch);
           ++ch;
         } while (ch < nch && kind(cfl) == 2);
       }

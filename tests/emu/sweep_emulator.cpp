@@ -287,6 +287,19 @@ int main(int argc, char** argv) {
                 for (int k = 0; k < NR; ++k)
                   if (((fl >> (F2_ROW_BITS * k)) & F2_ACT) && !((gm >> k) & 1)) { printf("bad grid mask\n"); exit(2); }
               }
+              // a lane entering its strip at the x wall: its NR x-inflows are the
+              // entries from its offset on (slot -1: zero), replacing the rows'
+              // x-upwind values
+              std::vector<double> xst;
+              if (fl & F2_XSTART) {
+                if (fl & kInAll) { printf("F2_XSTART with other inflows\n"); exit(2); }
+                xst.resize((size_t)NR * G);
+                for (int k = 0; k < NR; ++k)
+                  for (int gg = 0; gg < G; ++gg) {
+                    const int sl = itab[e0 + k];
+                    xst[(size_t)k * G + gg] = (sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0) * gt[go_den(G) + gg];
+                  }
+              }
               for (int k = 0; k < NR; ++k) {
                 const unsigned b = fl >> (F2_ROW_BITS * k);
                 const bool act = (b & F2_ACT) != 0;
@@ -298,7 +311,9 @@ int main(int argc, char** argv) {
                 double a0s = 0.0, a1s = 0.0;
                 for (int gg = 0; gg < G; ++gg) {
                   const double den = gt[go_den(G) + gg];
-                  const double xu = (b & F2_INX) ? ub[(size_t)band * nbf + itab[ex]] * den : fold[((size_t)l * NR + k) * G + gg];
+                  const double xu = (b & F2_INX) ? ub[(size_t)band * nbf + itab[ex]] * den
+                                    : !xst.empty() ? xst[(size_t)k * G + gg]
+                                                   : fold[((size_t)l * NR + k) * G + gg];
                   const double zu = (b & F2_INY) ? ub[(size_t)band * nbf + itab[ey]] * den : zc[gg];
                   const double fn = gt[go_a(G, 1) + gg] * zu + gt[go_a(G, 0) + gg] * xu + S_;
                   fnew[((size_t)l * NR + k) * G + gg] = fn;

@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const int band = gi.x;
     const int g_loc = gi.z;
     const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
-    const T kS = gt[0], cQ = gt[1];
+    T kS = gt[0], cQ = gt[1];
     T a0[G], a1[G], den[G], inv[G], wo0[G], wo1[G];
     T wacc[NACC][G];
 #pragma unroll
@@ -272,6 +272,25 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       wo1[g] = gt[go_wo(G, 1) + g];
 #pragma unroll
       for (int a = 0; a < NACC; ++a) wacc[a][g] = gt[go_wacc(G, a) + g];
+    }
+    // one ordinate per lane: the lane carries w0 * f, w0 the ordinate's weight
+    // in the temperature sum (the recurrence is linear), so that sum needs no
+    // multiply; what enters f is scaled by w0 and what is read from it by
+    // 1 / w0 (a padding ordinate has w0 = 0: its lanes carry 0)
+    constexpr bool PS = G == 1;
+    double tg_scale = 1.0;
+    if constexpr (PS) {
+      const T w0 = wacc[0][0];
+      const T iw = w0 > T(0) ? T(1) / w0 : T(0);
+      kS *= w0;
+      cQ *= w0;
+      den[0] *= w0;
+      inv[0] *= iw;
+      wo0[0] *= iw;
+      wo1[0] *= iw;
+#pragma unroll
+      for (int a = 1; a < NACC; ++a) wacc[a][0] *= iw;
+      tg_scale = (double)iw;
     }
 
     const int o = jd.oct;
@@ -586,7 +605,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           for (int k = 0; k < NR; ++k) {
             T sm = T(0);
 #pragma unroll
-            for (int g = 0; g < G; ++g) sm = fma(wacc[a][g], f[g][k], sm);
+            for (int g = 0; g < G; ++g) sm = (PS && a == 0) ? f[g][k] : fma(wacc[a][g], f[g][k], sm);
             acc[k] = sm;
           }
           *reinterpret_cast<VR*>(stg0 + (size_t)(NACC == 1 ? 0 : a) * plane_sz + u * RS + lane * NR) = acc;
@@ -648,7 +667,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
 #pragma unroll
               for (int g = 0; g < G; ++g) {
                 const double uf = (double)su[g];
-                s0 += (double)wt0[g] * (double)f[g][k] * (uf - (double)xf[2 * k]);
+                s0 += (double)wt0[g] * tg_scale * (double)f[g][k] * (uf - (double)xf[2 * k]);
                 s1 += (double)wt1[g] * uf;
               }
               tg0 += s0;

@@ -552,7 +552,9 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
   s.n_oct = 1 << hi.dim;
   s.lag = L3 ? du - (LK - 1) : 0;
   s.ring = L3 ? next_pow2(s.lag + C + 16 + 8) : 0;
-  s.pos_per_oct = (long long)R * T * 64;
+  // padded by kPad2 steps so that the kernel's prefetch needs no condition
+  const int Tp = T + kPad2;
+  s.pos_per_oct = (long long)R * Tp * 64;
   const long long npos = s.pos_per_oct * s.n_oct;
   if (npos > (1ll << 31) - 1) {
     err = "schedule too large";
@@ -625,11 +627,11 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
             iz = 0;
           }
           const int cell = ix + n0 * (iy + n1 * iz);
-          const long long pidx = ((long long)o * R + r) * T * 64 + (long long)tau * 64 + l;
+          const long long pidx = ((long long)o * R + r) * Tp * 64 + (long long)tau * 64 + l;
           unsigned fl = (unsigned)ip << F_COL_SHIFT;
           if (hi.active[cell]) {
             fl |= F_ACTIVE;
-            s.pos[(size_t)o * hi.ncell + cell] = (int)(((long long)r * T + tau) * 64 + l);
+            s.pos[(size_t)o * hi.ncell + cell] = (int)(((long long)r * Tp + tau) * 64 + l);
             for (int d = 0; d < hi.dim; ++d) {
               const int su = hi.bslot[(size_t)cell * 6 + up[d]];
               if (su >= 0) {
@@ -667,7 +669,7 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
         int cnt = 0;
         for (int tau = ch * C; tau < (ch + 1) * C; ++tau)
           for (int l = 0; l < 64; ++l) {
-            const unsigned fl = (unsigned)s.sched[((long long)o * R + r) * T * 64 + (long long)tau * 64 + l].y;
+            const unsigned fl = (unsigned)s.sched[((long long)o * R + r) * Tp * 64 + (long long)tau * 64 + l].y;
             cnt += ((fl & F_OUT_X) != 0) + ((fl & F_OUT_Y) != 0) + ((fl & F_OUT_Z) != 0);
           }
         s.o_max = std::max(s.o_max, cnt);

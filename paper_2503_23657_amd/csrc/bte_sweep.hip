@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bte_device.h"
+#include "bte_kutil.h"
 
 namespace bte {
 
@@ -60,18 +61,6 @@ __device__ __forceinline__ double dpp_move(double old, double v) {
 
 __device__ __forceinline__ unsigned long long ballot64(bool p) { return __ballot(p); }
 
-// Pointers taken from the descriptors are generic; marking them global lets the
-// compiler use global (not flat) memory instructions, which do not count
-// against the LDS wait counter.
-#define GAS __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ GAS T* gp(T* p) {
-  return (GAS T*)p;
-}
-template <typename T>
-__device__ __forceinline__ const GAS T* gp(const T* p) {
-  return (const GAS T*)p;
-}
 // HIP's vector types cannot bind address-space references: load pairs through
 // clang vector types
 typedef int iv2_t __attribute__((ext_vector_type(2)));
@@ -89,20 +78,6 @@ __device__ __forceinline__ double2 ld2(const GAS double2* p) {
   const dv2_t v = *(const GAS dv2_t*)p;
   return make_double2(v.x, v.y);
 }
-// Read-only tables (job list, instance records, group constants, the status
-// written by the previous kernel) read at uniform addresses through the
-// constant address space: scalar loads into SGPRs, so everything derived from
-// them stays uniform.
-#ifdef __HIP_DEVICE_COMPILE__
-#define CAS __attribute__((address_space(4)))
-#else
-#define CAS  // the host pass only parses the kernels
-#endif
-template <typename T>
-__device__ __forceinline__ const CAS T* cp(const T* p) {
-  return (const CAS T*)p;
-}
-
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
@@ -110,6 +85,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 enum { M_PLAIN = 0, M_STORE = 1, M_TAUGRAD = 2 };
 
 constexpr int kD = 8;    // prefetch distance (steps) of the per-step inputs
+static_assert(kD <= kPad2, "the schedule padding must cover the prefetch distance");
 constexpr int kEPL = 4;  // in-stream entries per lane per chunk (e_max <= 256)
 
 // ============================================================================
@@ -189,16 +165,26 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const int o = jd.oct;
     const int T_steps = I.T;
     const int nch = T_steps / C;
-    const long long slot_base = (long long)o * I.pos_per_oct + (long long)r * T_steps * 64;
+    // per-slot schedule rows are padded (pos_per_oct = R * (T + kPad2) * 64),
+    // so the prefetch of step tau + kD needs no condition
+    const long long Tp = I.pos_per_oct / ((long long)R * 64);
+    const long long slot_base = (long long)o * I.pos_per_oct + (long long)r * Tp * 64;
     const GAS int2* SCH = gp(I.sched + slot_base);
     const GAS T2* XQ = gp(reinterpret_cast<const T2*>(I.xq[iter & 1]) + slot_base);
     const GAS T2* XF = MODE == M_TAUGRAD ? gp(reinterpret_cast<const T2*>(I.xf) + slot_base) : nullptr;
     const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
     const GAS int* ISLOT = gp(I.in_slot);
-    const GAS int* ich = gp(I.in_chunk + (size_t)(o * R + r) * (nch + 1));
+    const CAS int* ich = cp(I.in_chunk) + (size_t)(o * R + r) * (nch + 1);
+    // buffer views of the chunk loop's global data (sizes in bytes): masked
+    // lanes get an offset past the end instead of a branch
+    const rsrc_t UBR = mkrsrc(UBF, (unsigned)I.n_bface * (unsigned)sizeof(T));
+    const rsrc_t ISR = mkrsrc(ISLOT, (unsigned)ich[nch] * 4u);
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[o * R + r]);
     const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
     GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
+    rsrc_t PRS[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
     const int zmask = L3 ? I.ring - 1 : 0;
     const int zlag = L3 ? I.lag : 0;
 
@@ -274,14 +260,16 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
       // the end of the chunk
       T inval[kEPL];
 #pragma unroll
-      for (int m = 0; m < kEPL; ++m) inval[m] = slot_n[m] >= 0 ? UBF[slot_n[m]] : T(0);
+      for (int m = 0; m < kEPL; ++m) inval[m] = bld<T>(UBR, slot_n[m] * (int)sizeof(T));  // slot -1: 0
       {
-        const int b2 = ch + 2 < nch ? ich[ch + 2] : 0;
-        const int e2 = ch + 2 < nch ? ich[ch + 3] : 0;
+        const bool more = ch + 2 < nch;
+        const int b2 = more ? ich[min(ch + 2, nch)] : 0;
+        const int e2 = more ? ich[min(ch + 3, nch)] : 0;
 #pragma unroll
         for (int m = 0; m < kEPL; ++m) {
           const int idx = b2 + lane + 64 * m;
-          slot_n[m] = idx < e2 ? ISLOT[idx] : -1;
+          const int sv = bld<int>(ISR, idx < e2 ? idx * 4 : kOOB);
+          slot_n[m] = idx < e2 ? sv : -1;
         }
       }
       const T* inbuf = my_inb + (ch & 1) * A.e_max;
@@ -302,14 +290,20 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 #pragma unroll
             for (int g = 0; g < G; ++g) zg[g] = rzg[u][g];
           }
-          if (tau + kD < T_steps) {
+          {
             const int tn = tau + kD;
             rcf[u] = ld2(SCH + tn * 64 + lane);
             rxq[u] = ld2(XQ + tn * 64 + lane);
             if (MODE == M_TAUGRAD) rxf[u] = ld2(XF + tn * 64 + lane);
-            if (L3 && kl == 0 && tn >= zlag) {
+            if (L3) {
+              // every lane loads (the ring index wraps in bounds); the z-entry
+              // lanes keep the value once the ring holds data
+              const bool zk = kl == 0 && tn >= zlag;
 #pragma unroll
-              for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
+              for (int g = 0; g < G; ++g) {
+                const T zv = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
+                rzg[u][g] = zk ? zv : T(0);
+              }
             }
           }
           const int cid = cf.x;
@@ -489,13 +483,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           const int e = m * (P * 64) + t;
           const int lp = e / C, cc = e - lp * C;
           const int cid = my_scid[cc * 65 + lp];
-          if (cid >= 0) {
 #pragma unroll
-            for (int a = 0; a < NACC; ++a) {
-              T v = T(0);
-              for (int q = 0; q < P; ++q) v += stage[((size_t)(q * R + r) * NACC * C + a * C + cc) * 65 + lp];
-              PARTJ[a * part_plane + cid] = v;
-            }
+          for (int a = 0; a < NACC; ++a) {
+            T v = T(0);
+            for (int q = 0; q < P; ++q) v += stage[((size_t)(q * R + r) * NACC * C + a * C + cc) * 65 + lp];
+            bst(v, PRS[a], cid >= 0 ? cid * (int)sizeof(T) : kOOB);
           }
         }
       }

@@ -114,7 +114,8 @@ int main(int argc, char** argv) {
             if (tau_ % Cc == 0) in_cur[r] = 0;
             std::vector<double> fold = f[r], fnew(64 * G), xu(64 * G), yu(64 * G), zu(64 * G);
             std::vector<int2> ent(64);
-            for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)o * R + r) * T * 64 + (size_t)tau_ * 64 + l];
+            const size_t Tp3 = (size_t)(S.pos_per_oct / (64 * R));  // padded steps per slot
+            for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)o * R + r) * Tp3 * 64 + (size_t)tau_ * 64 + l];
             for (int l = 0; l < 64; ++l) {
               const int jl = L3 ? (l & 7) : 0, kl = L3 ? (l >> 3) : l;
               const unsigned fl = (unsigned)ent[l].y;

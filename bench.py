@@ -49,7 +49,7 @@ def cpu_baseline(p, iters: int, m_swept: int):
                        f"sweeps all {p.M} directions, counted as the {m_swept} swept projections per band)")
 
 
-SWEEP_SOURCES = ("bte_sweep2d.hip", "bte_sweep2d_launch.h")
+SWEEP_SOURCES = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_kutil.h")
 
 
 def sweep_source_hash() -> str:

@@ -20,6 +20,11 @@
  *              diffuse: incoming e = sum_{out} w (s.n) e / sum_{in} w |s.n|
  *              (Eq. 6 with the discrete half-range normalisation), lagged one
  *              iteration.
+ *              specular: incoming e along s equals the outgoing e along the
+ *              mirror direction s' = s - 2 n (s.n) at the same boundary cell
+ *              (Eq. 7); s' must be one of the quadrature's directions. Lagged
+ *              one iteration like the diffuse walls, and starting, like them,
+ *              from the adjacent cell's equilibrium.
  *   FVM        first-order upwind face values (the face gradient term of the
  *              paper's second-order face reconstruction dropped), uniform
  *              Cartesian cells: S_ij/V_i = 1/h_d for a face normal to axis d.
@@ -31,7 +36,7 @@
  *                 is exact because first-order upwind A is triangular in that
  *                 order), then e += Delta e;
  *              3. update T_L and e0 (Eq. updatee0_t), and the lagged diffuse
- *                 wall values;
+ *                 and specular wall values;
  *              4. repeat until eps_T and eps_q (Eq. 22) fall below the targets.
  *   Heat flux  q = sum_l sum_a w_a v_l s_a e_{a,l}   (Eq. 4, grid axes only)
  *   Residuals  eps_T = RMS_i(T^{n+1} - T^n) / max_i |T^{n+1} - T_ref|,
@@ -58,6 +63,7 @@
 
 #define BC_ISOTHERMAL 0
 #define BC_DIFFUSE 1
+#define BC_SPECULAR 2
 #define NO_BC 255
 
 static const double PI = 3.14159265358979323846;
@@ -141,9 +147,10 @@ static double s_dot_n(const double* s, int f) {
  * e_la: this ordinate's energies (updated in place); eb: boundary face values
  * of band l (absolute energy on incoming faces); T: current T_L.
  */
-static void solve_ordinate(const grid_t* g, const bfaces_t* bf, double v, double tau, double C,
-                           double Csum, const double* s, const double* Q, const double* T,
-                           const double* eb_l, double* e_la, double* rhs, double* de) {
+static void solve_ordinate(const grid_t* g, const bfaces_t* bf, const int* bc_kind, double v,
+                           double tau, double C, double Csum, const double* s, const double* Q,
+                           const double* T, const double* eb_l, const double* es_la, double* e_la,
+                           double* rhs, double* de) {
   const long ncell = g->ncell;
   /* b^n (Eq. rhs_b with first-order faces): minus the net upwind face flux of
      e^n, minus (e^n - e0^n)/tau, plus the band's source share. */
@@ -159,7 +166,12 @@ static void solve_ordinate(const grid_t* g, const bfaces_t* bf, double v, double
         e_face = e_la[c];                  /* upwind cell is the cell itself */
       } else {
         long nb = neighbour(g, c, f);
-        e_face = nb >= 0 ? e_la[nb] : eb_l[bf->slot[c * 6 + f]];
+        if (nb >= 0) {
+          e_face = e_la[nb];
+        } else {
+          long k = bf->slot[c * 6 + f];
+          e_face = bc_kind[bf->bc[k]] == BC_SPECULAR ? es_la[k] : eb_l[k];
+        }
       }
       flux += vn / g->h[d] * e_face;       /* (1/V) v.n S e_face */
     }
@@ -244,6 +256,32 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
   for (long f = 0; f < bf.n; ++f)
     if (bf.bc[f] < 0 || bf.bc[f] >= n_bc) { free_bfaces(&bf); return OR_INVALID; }
 
+  /* mirror directions for specular faces (Eq. 7): for a face normal to grid
+     axis d, s' = s with its d component negated; it must be a quadrature
+     direction. mir[d*M + a] = index of s', or -1. */
+  int has_spec = 0;
+  for (long f = 0; f < bf.n; ++f)
+    if (bc_kind[bf.bc[f]] == BC_SPECULAR) has_spec = 1;
+  int* mir = (int*)malloc(sizeof(int) * 3 * M);
+  if (!mir) { free_bfaces(&bf); return OR_INVALID; }
+  for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < M; ++a) {
+      mir[d * M + a] = -1;
+      for (int m = 0; m < M; ++m) {
+        int same = 1;
+        for (int k = 0; k < 3; ++k) {
+          double want = (k == d) ? -s[3 * a + k] : s[3 * a + k];
+          if (fabs(s[3 * m + k] - want) > 1e-12) same = 0;
+        }
+        if (same) { mir[d * M + a] = m; break; }
+      }
+    }
+  for (long f = 0; f < bf.n; ++f) {
+    if (bc_kind[bf.bc[f]] != BC_SPECULAR) continue;
+    for (int a = 0; a < M; ++a)
+      if (mir[(bf.face[f] / 2) * M + a] < 0) { free(mir); free_bfaces(&bf); return OR_INVALID; }
+  }
+
   double Csum = 0.0, D = 0.0;
   for (int l = 0; l < B; ++l) { Csum += C[l]; D += C[l] / tau[l]; }
 
@@ -254,8 +292,11 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
   double* e = (double*)malloc(sizeof(double) * (size_t)B * M * ncell);
   double* eb = (double*)calloc((size_t)B * (bf.n ? bf.n : 1), sizeof(double));
   double* inv_half = (double*)calloc(bf.n ? bf.n : 1, sizeof(double));
-  if (!T || !Tn || !q || !qn || !e || !eb || !inv_half) {
-    free(T); free(Tn); free(q); free(qn); free(e); free(eb); free(inv_half); free_bfaces(&bf);
+  /* specular wall values per (band, direction, face) */
+  double* es = has_spec ? (double*)calloc((size_t)B * M * bf.n, sizeof(double)) : NULL;
+  if (!T || !Tn || !q || !qn || !e || !eb || !inv_half || (has_spec && !es)) {
+    free(T); free(Tn); free(q); free(qn); free(e); free(eb); free(inv_half); free(es); free(mir);
+    free_bfaces(&bf);
     return OR_INVALID;
   }
 
@@ -277,6 +318,8 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
     for (int l = 0; l < B; ++l) {
       double Tw = (kind == BC_ISOTHERMAL) ? bc_T[bf.bc[f]] : T[bf.cell[f]];
       eb[(size_t)l * bf.n + f] = C[l] * Tw / (4.0 * PI);
+      if (kind == BC_SPECULAR)
+        for (int a = 0; a < M; ++a) es[((size_t)l * M + a) * bf.n + f] = C[l] * Tw / (4.0 * PI);
     }
   }
 
@@ -292,8 +335,9 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
 #pragma omp for schedule(dynamic, 1)
       for (int la = 0; la < B * M; ++la) {
         int l = la / M, a = la % M;
-        solve_ordinate(&g, &bf, v[l], tau[l], C[l], Csum, &s[3 * a], Qp, T,
-                       &eb[(size_t)l * bf.n], &e[(size_t)la * ncell], rhs, de);
+        solve_ordinate(&g, &bf, bc_kind, v[l], tau[l], C[l], Csum, &s[3 * a], Qp, T,
+                       &eb[(size_t)l * bf.n], es ? &es[(size_t)la * bf.n] : NULL,
+                       &e[(size_t)la * ncell], rhs, de);
       }
       free(rhs);
       free(de);
@@ -328,6 +372,20 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
           if (sn > 0.0) out += w[a] * sn * e[((size_t)l * M + a) * ncell + c];
         }
         eb[(size_t)l * bf.n + f] = out * inv_half[f];
+      }
+    }
+    /* lagged specular wall values: the new outgoing energy along the mirror
+       direction at the same cell (Eq. 7) */
+    if (has_spec) {
+#pragma omp parallel for schedule(static)
+      for (long f = 0; f < bf.n; ++f) {
+        if (bc_kind[bf.bc[f]] != BC_SPECULAR) continue;
+        long c = bf.cell[f];
+        int d = bf.face[f] / 2;
+        for (int l = 0; l < B; ++l)
+          for (int a = 0; a < M; ++a)
+            if (s_dot_n(&s[3 * a], bf.face[f]) < 0.0)
+              es[((size_t)l * M + a) * bf.n + f] = e[((size_t)l * M + mir[d * M + a]) * ncell + c];
       }
     }
     ++it;
@@ -370,7 +428,7 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
     info[2] = epsq;
     info[3] = (double)bf.n;
   }
-  free(T); free(Tn); free(q); free(qn); free(e); free(eb); free(inv_half);
+  free(T); free(Tn); free(q); free(qn); free(e); free(eb); free(inv_half); free(es); free(mir);
   free_bfaces(&bf);
   return status;
 }

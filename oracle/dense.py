@@ -9,8 +9,10 @@ source iteration satisfies, and solves it directly:
         sum_faces v_b (s_a . n_f)/h_d e_face = -(e - C_b T_c/(4 pi))/tau_b
                                                + Q_c C_b / (4 pi sum_b C_b)
     where e_face is e_c on outflow faces, the upwind neighbour's e on interior
-    inflow faces, C_b T_w/(4 pi) on isothermal inflow faces (Eq. 5) and the
-    unknown wall value eb_{b,f} on diffuse inflow faces;
+    inflow faces, C_b T_w/(4 pi) on isothermal inflow faces (Eq. 5), the
+    unknown wall value eb_{b,f} on diffuse inflow faces, and on specular
+    inflow faces the same cell's e along the mirror direction
+    s' = s - 2 n (s.n) (Eq. 7);
   * for every active cell, the lattice-temperature definition (Eq. updatee0_t)
         (sum_b C_b/tau_b) T_c = sum_b sum_a w_a e_{b,a,c} / tau_b ;
   * for every diffuse face f and band b, the diffuse-reflection condition
@@ -47,6 +49,16 @@ def _neighbour(p, c, f):
         return -1
     nb = idx[0] + n0 * (idx[1] + n1 * idx[2])
     return nb if p.mask[nb] else -1
+
+
+def _mirror(p, a, d):
+    # index of the direction equal to s_a with its axis-d component negated
+    want = np.array(p.s[a], dtype=np.float64)
+    want[d] = -want[d]
+    hit = np.flatnonzero(np.all(np.abs(np.asarray(p.s) - want) <= 1e-12, axis=1))
+    if hit.size == 0:
+        raise ValueError("quadrature has no mirror of direction %d across axis %d" % (a, d))
+    return int(hit[0])
 
 
 def solve_dense(p, tau=None, Q=None, return_all=False):
@@ -111,6 +123,8 @@ def solve_dense(p, tau=None, Q=None, return_all=False):
                             bc = faces[k][2]
                             if p.bc_kind[bc] == 0:
                                 rhs[r] -= coef * p.C[b] * p.bc_T[bc] / FOUR_PI
+                            elif p.bc_kind[bc] == 2:
+                                A[r, ie(b, _mirror(p, a, d), ci)] += coef
                             else:
                                 A[r, iD(b, k)] += coef
     for ci in range(Na):

@@ -189,12 +189,25 @@ def _face_flux_divergence(p, r):
             for b in range(p.B):
                 if nb >= 0:
                     eface = np.where(sn > 0, e[b, :, c], e[b, :, nb])
+                elif p.bc_kind[p.face_bc[c, f]] == 2:
+                    # specular: incoming along s carries the outgoing e along its mirror
+                    eface = np.where(sn > 0, e[b, :, c], e[b, _mirror_index(p, d), c])
                 else:
                     eface = np.where(sn > 0, e[b, :, c], eb[b, slot[(c, f)]])
                 flux += p.v[b] * float((p.w * sn * eface).sum())
             tot += flux / p.h[d]
         div[c] = tot
     return div
+
+
+def _mirror_index(p, d):
+    """mir[a] = index of the direction s_a with its axis-d component negated,
+    found by a nearest-vector search."""
+    r = p.s.copy()
+    r[:, d] *= -1
+    mir = np.array([int(np.argmin(np.linalg.norm(p.s - r[a], axis=1))) for a in range(p.M)])
+    assert np.abs(p.s[mir] - r).max() < 1e-14
+    return mir
 
 
 def _nb(p, c, f):
@@ -295,3 +308,138 @@ def test_thread_count_does_not_change_result():
     a = oracle.solve(p, tol=0.0, max_iters=7, threads=1)
     b = oracle.solve(p, tol=0.0, max_iters=7, threads=4)
     assert np.array_equal(a["T"], b["T"]) and np.array_equal(a["q"], b["q"])
+
+
+# ------------------------------------------------------ P13 specular walls
+def _wall_box(dim, n, rule, mask, Q, n_bands=3, seed_quad=None):
+    """Box problem with bc 0 isothermal at 305 K, bc 1 diffuse, bc 2 specular
+    (Eq. 7); cell size 2 nm."""
+    v, tau, C = bi.band_table_synthetic(n_bands)
+    if dim == 1:
+        s, w = bi.quad_gl_mu(8)
+    elif dim == 2:
+        s, w = bi.quad_octant_gl(2, 1, polar_axis=2)
+    else:
+        s, w = bi.quad_octant_gl(1, 1, polar_axis=0)
+    fbc = bi.face_bc_from_mask(n, dim, mask, rule)
+    return bi.Problem("wall_box", dim, tuple(n), (2e-9, 2e-9, 2e-9), mask, fbc,
+                      np.array([bi.BC_ISOTHERMAL, bi.BC_DIFFUSE, bi.BC_SPECULAR], dtype=np.int32),
+                      np.array([305.0, 300.0, 300.0]), v, tau, C, s, w, Q * mask, 300.0)
+
+
+def _mirror_pair(dim, n, d, b, seed):
+    """Problem A: a box whose -b edge is isothermal, whose +d edge is a specular
+    wall and whose other boundary faces (holes included) are diffuse. Problem B:
+    A and its mirror image across the +d edge, side by side, with no specular
+    face at all. By symmetry, B's fixed point restricted to A's half solves A's
+    discrete equations, with the mirror plane in the role of A's specular wall
+    (method of images)."""
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    m = np.ones(shape, dtype=np.uint8)
+    if dim >= 2:
+        hole = [int(rng.integers(1, n[a] - 1)) if n[a] > 2 else 0 for a in range(3)]
+        m[hole[2], hole[1], hole[0]] = 0
+    Q = 1e18 * rng.uniform(0.0, 1.0, size=shape)
+    ax = 2 - d
+    mB = np.concatenate([m, np.flip(m, ax)], axis=ax)
+    QB = np.concatenate([Q, np.flip(Q, ax)], axis=ax)
+    nB = list(n)
+    nB[d] *= 2
+
+    def rule_a(i, j, k, f):
+        ijk = (i, j, k)
+        if f == 2 * b and ijk[b] == 0:
+            return 0
+        if f == 2 * d + 1 and ijk[d] == n[d] - 1:
+            return 2
+        return 1
+
+    def rule_b(i, j, k, f):
+        ijk = (i, j, k)
+        if f == 2 * b and ijk[b] == 0:
+            return 0
+        if b == d and f == 2 * b + 1 and ijk[b] == nB[b] - 1:
+            return 0
+        return 1
+
+    pa = _wall_box(dim, n, rule_a, m.reshape(-1), Q.reshape(-1))
+    pb = _wall_box(dim, nB, rule_b, mB.reshape(-1), QB.reshape(-1))
+    return pa, pb, ax
+
+
+@pytest.mark.parametrize("dim,n,d,b", [(1, (10, 1, 1), 0, 0), (2, (6, 5, 1), 0, 1),
+                                       (2, (5, 6, 1), 1, 0), (3, (4, 3, 3), 2, 0)])
+def test_specular_wall_is_a_mirror_plane(dim, n, d, b):
+    pa, pb, ax = _mirror_pair(dim, n, d, b, seed=11 + d)
+    assert np.all(pb.face_bc[pb.face_bc != bi.NO_BC] != 2)
+    ra = oracle.solve(pa, tol=0.0, max_iters=6000)
+    rb = oracle.solve(pb, tol=0.0, max_iters=6000)
+    shape = (n[2], n[1], n[0])
+    Ta = ra["T"].reshape(shape)
+    Tb = np.take(rb["T"].reshape(pb.n[2], pb.n[1], pb.n[0]), np.arange(n[d]), axis=ax)
+    act = pa.mask.reshape(shape) > 0
+    scale = np.abs(Ta[act] - 300.0).max()
+    assert scale > 1e-3
+    assert np.abs(Ta[act] - Tb[act]).max() < 1e-9 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_specular_fixed_point_matches_dense(dim):
+    if dim == 2:
+        p = bi.random_box_2d(5, 4, seed=7, n_bands=3, n_theta=1, n_phi=1, kinds=(0, 2))
+    else:
+        p = bi.random_box_3d(3, 3, 4, seed=8, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2))
+    Td = dense.solve_dense(p)
+    r = oracle.solve(p, tol=0.0, max_iters=6000)
+    act = p.mask > 0
+    scale = np.abs(Td[act] - p.T_ref).max()
+    assert scale > 1e-6
+    assert np.abs(r["T"][act] - Td[act]).max() < 1e-10 * scale
+
+
+def test_energy_balance_per_cell_with_specular_walls():
+    """With the incoming face value of a specular face taken as the outgoing e
+    along the mirror direction, the fixed point balances energy in every cell,
+    and the heat generated leaves through the isothermal faces only."""
+    p = bi.random_box_2d(6, 5, seed=9, n_bands=3, n_theta=2, n_phi=1, kinds=(0, 2))
+    r = oracle.solve(p, tol=0.0, max_iters=6000, want_e=True, want_eb=True)
+    div = _face_flux_divergence(p, r)
+    act = p.mask > 0
+    Qmax = np.abs(p.Q).max()
+    assert np.abs(div[act] - p.Q[act]).max() < 1e-9 * Qmax
+
+
+def test_specular_side_walls_reduce_to_the_film():
+    """A 2D strip with isothermal -x / +x walls, specular -y / +y walls and a
+    source that varies in x only has the 1D film's solution (same bands and
+    directions, only s_x transporting) in every row: the mirror directions carry
+    the same s_x, so the y fluxes cancel at the walls."""
+    nx, ny = 12, 3
+    v, tau, C = bi.band_table_synthetic(3)
+    s, w = bi.quad_octant_gl(2, 2, polar_axis=2)
+    qx = 1e18 * np.linspace(0.2, 1.0, nx)
+    m2 = np.ones(nx * ny, dtype=np.uint8)
+    fbc2 = bi.face_bc_from_mask((nx, ny, 1), 2, m2, lambda i, j, k, f: {0: 0, 1: 1}.get(f, 2))
+    p2 = bi.Problem("strip", 2, (nx, ny, 1), (2e-9, 2e-9, 2e-9), m2, fbc2,
+                    np.array([0, 0, 2], dtype=np.int32), np.array([305.0, 300.0, 300.0]),
+                    v, tau, C, s, w, np.tile(qx, ny), 300.0)
+    m1 = np.ones(nx, dtype=np.uint8)
+    fbc1 = bi.face_bc_from_mask((nx, 1, 1), 1, m1, lambda i, j, k, f: f)
+    p1 = bi.Problem("film", 1, (nx, 1, 1), (2e-9, 2e-9, 2e-9), m1, fbc1,
+                    np.array([0, 0], dtype=np.int32), np.array([305.0, 300.0]),
+                    v, tau, C, s, w, qx, 300.0)
+    r2 = oracle.solve(p2, tol=0.0, max_iters=6000)
+    r1 = oracle.solve(p1, tol=0.0, max_iters=6000)
+    T2 = r2["T"].reshape(ny, nx)
+    scale = np.abs(r1["T"] - 300.0).max()
+    for j in range(ny):
+        assert np.abs(T2[j] - r1["T"]).max() < 1e-10 * scale
+
+
+def test_specular_needs_mirror_directions():
+    p = bi.random_box_2d(5, 4, seed=7, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2))
+    a = 0.1
+    rot = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    with pytest.raises(ValueError):
+        oracle.solve(p.replace(s=p.s @ rot.T), tol=0.0, max_iters=2)

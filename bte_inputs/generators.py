@@ -32,7 +32,7 @@ FOUR_PI = 4.0 * math.pi
 __all__ = [
     "BC_ISOTHERMAL", "BC_DIFFUSE", "BC_SPECULAR", "NO_BC", "Problem",
     "band_table_synthetic", "band_table_gray", "quad_gl_mu", "quad_octant_gl",
-    "face_bc_from_mask", "gaussian_source", "film_1d", "square_2d", "finfet_3d",
+    "face_bc_from_mask", "gaussian_source", "film_1d", "square_2d", "finfet_3d", "finfet_3d_mixed",
     "adjoint_case", "batch_instances", "scattering_mfp", "random_box_2d", "random_box_3d", "multi_hole_2d",
 ]
 
@@ -359,6 +359,32 @@ def finfet_3d(scale=1, seed=2, n_bands=15, n_theta=4, n_phi=4, Q0=1e19, T_ref=30
                    np.array([BC_ISOTHERMAL, BC_DIFFUSE], dtype=np.int32),
                    np.array([300.0, 300.0]), np.asarray(v, float), np.asarray(tau, float),
                    np.asarray(C, float), np.asarray(s, float), np.asarray(w, float), Q, T_ref)
+
+
+def finfet_3d_mixed(scale=1, **kw):
+    """finfet_3d with the wall mix of the paper's short-base FinFET case
+    (Results, FinFET with specular and diffuse walls): isothermal 300 K at the
+    substrate bottom (bc 0) and on the top face of the fin (bc 3), diffusely
+    reflecting fin side walls (bc 1), specularly reflecting base surfaces
+    (bc 2: the substrate's sides and its top around the fin)."""
+    p = finfet_3d(scale=scale, **kw)
+    nz = p.n[2]
+    sub = 92 // scale
+    fh = 28 // scale
+    fin_top = sub + fh - 1
+
+    def rule(i, j, k, f):
+        if f == 4 and k == 0:
+            return 0
+        if f == 5 and k == fin_top:
+            return 3
+        return 1 if k >= sub else 2
+
+    assert fin_top < nz
+    fbc = face_bc_from_mask(p.n, 3, p.mask, rule)
+    return p.replace(name="finfet_3d_mixed", face_bc=fbc,
+                     bc_kind=np.array([BC_ISOTHERMAL, BC_DIFFUSE, BC_SPECULAR, BC_ISOTHERMAL], dtype=np.int32),
+                     bc_T=np.array([300.0, 300.0, 300.0, 300.0]))
 
 
 def adjoint_case(base: Problem, seed_truth=3, seed_probe=4, seed_fd=5, n_probes=64, rim=4,

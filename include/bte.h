@@ -54,7 +54,10 @@ typedef enum {
 enum {
   BTE_BC_ISOTHERMAL = 0, /* thermalizing wall at bc_T (Eq. 5) */
   BTE_BC_DIFFUSE = 1,    /* diffusely reflecting adiabatic wall (Eq. 6) */
-  BTE_BC_SPECULAR = 2    /* specular wall (Eq. 7): rejected with BTE_ERR_INVALID */
+  BTE_BC_SPECULAR = 2    /* specularly reflecting adiabatic wall (Eq. 7): an incoming
+                            ordinate takes the outgoing value of its mirror direction
+                            at the same cell, lagged one iteration like the diffuse
+                            walls. Needs plans with G = 1; no adjoint. */
 };
 
 /* Arithmetic of the sweeps. FP64: everything in double. FP32: the transport
@@ -89,7 +92,8 @@ typedef struct {
 } bte_quadrature;
 
 /* Kernel shape of the sweep (chosen by bte_autotune, or set by hand).
-   G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D: 1, 2 or 4).
+   G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D: 1, 2 or 4;
+      1 whenever a specular wall is present).
    R: 1D/2D only, waves per workgroup that pipeline successive strips of
       64*NR rows (R*P <= 4); 3D: always 1.
    P: waves per workgroup that sweep different ordinate groups of one octant
@@ -129,7 +133,7 @@ const char* bte_last_error(void);
 /* Host-only validation of a problem (no device call). Returns BTE_OK or
    BTE_ERR_INVALID for: dim not in 1..3; n < 1 or h <= 0 on a used axis, or
    n != 1 on an unused axis; no active cell; n_bc out of range, a bc kind other
-   than isothermal/diffuse, a face_bc entry >= n_bc on a boundary face;
+   than isothermal/diffuse/specular, a face_bc entry >= n_bc on a boundary face;
    no isothermal boundary face (no unique steady state: the T_L update
    conserves energy, so heat can leave only through isothermal walls);
    B < 1, any v, tau or C <= 0 or non-finite; M < 1, |s| != 1 (1e-12),

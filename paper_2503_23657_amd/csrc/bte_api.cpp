@@ -104,7 +104,9 @@ struct Inst {
   double* d_bc_T = nullptr;
   int* d_dface = nullptr;
   double* d_inv_half = nullptr;
-  void* d_ubf = nullptr;        // forward inflow table
+  int* d_sface = nullptr;       // specular faces: slot and face direction
+  int* d_sface_dir = nullptr;
+  void* d_ubf = nullptr;        // forward inflow table [B][rows][n_bface]
   void* d_ubf0 = nullptr;       // zeros (adjoint)
   // plan-dependent device data (owned by the plan pool)
   int2* d_sched = nullptr;
@@ -142,6 +144,10 @@ struct bte_ctx {
   bool plan_set = false;
   std::vector<Inst> inst;
   bool has_diffuse = false;
+  bool has_specular = false;
+  int ubf_rows = 1;                    // inflow-table rows per band: 1, or the ordinate count (specular)
+  int2* d_spec_src = nullptr;          // [6][M] mirror of each ordinate (octant, member), or -1
+  double* d_spec_iwq = nullptr;        // [6][M] 1 / (w_a' |s_a'.n|)
   int n_cu = 256;
   DevPool pool;                        // plan-independent
   std::unique_ptr<DevPool> ppool;      // plan-dependent
@@ -209,6 +215,12 @@ double total_D(const bte_ctx* h) {
 bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   Plan pl = pl_in;
   const bool L3 = h->dim == 3;
+  if (h->has_specular && pl.G != 1) {
+    // a specular inflow belongs to one ordinate, and the out-stream entry of a
+    // group must hold one ordinate's value
+    set_err("specular walls need plans with G = 1");
+    return BTE_ERR_INVALID;
+  }
   if (L3) {
     pl.R = 1;
     pl.NR = 1;
@@ -269,6 +281,21 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       return BTE_ERR_INVALID;
     }
     const Schedule& S = I.sch;
+    if (h->has_specular) {
+      // every mirror ordinate must find its outflow entry at each specular face
+      const int nbf = (int)I.hi.bf_cell.size();
+      for (int sf : I.hi.sface) {
+        const int fd = I.hi.bf_face[sf], d = fd / 2;
+        for (const auto& oa : h->ords) {
+          const double sn = (fd & 1) ? oa.s[d] : -oa.s[d];
+          if (!(sn > 0.0)) continue;
+          if (S.ofk[(size_t)oa.oct * nbf + sf] < 0) {
+            set_err("internal: specular face %d has no outflow entry in octant %d", sf, oa.oct);
+            return BTE_ERR_INVALID;
+          }
+        }
+      }
+    }
     W_max = std::max(W_max, S.W);
     e_max = std::max(e_max, S.e_max);
     o_max = std::max(o_max, S.o_max);
@@ -284,8 +311,13 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     gtf.insert(gtf.end(), cf.begin(), cf.end());
     gta.insert(gta.end(), ca.begin(), ca.end());
     for (int g = 0; g < n_grp_inst; ++g) {
-      gif.push_back(make_int4(gs.band[g], gs.oct[g], g, 0));
-      gia.push_back(make_int4(gs.band[g], gs.oct[g] ^ (n_oct - 1), g, 0));
+      // forward inflow-table row: the band, or (band, ordinate) with specular
+      // walls (G = 1; padding groups read ordinate 0's row, their weights are 0)
+      int row = gs.band[g];
+      if (h->has_specular) row = gs.band[g] * h->ubf_rows + std::max(0, gs.ords[(size_t)g * pl.G]);
+      gif.push_back(make_int4(gs.band[g], gs.oct[g], g, row));
+      // the adjoint reads a table of zeros
+      gia.push_back(make_int4(gs.band[g], gs.oct[g] ^ (n_oct - 1), g, gs.band[g]));
     }
     // device arrays of the schedule
     HIPCHK(pp.upload(&I.d_sched, S.sched));
@@ -519,6 +551,46 @@ bte_status build_static(bte_ctx* h) {
   std::vector<int> nbi;
   h->fin_f.resize(n);
   h->fin_a.resize(n);
+  // specular walls (Eq. 7): the inflow of an ordinate is its mirror's outflow,
+  // so the inflow table gets one row per (band, ordinate)
+  h->has_specular = false;
+  for (const auto& I : h->inst)
+    if (!I.hi.sface.empty()) h->has_specular = true;
+  const int M = (int)h->ords.size();
+  h->ubf_rows = h->has_specular ? M : 1;
+  if (h->has_specular) {
+    std::vector<int> member(M, 0);
+    {
+      std::vector<int> cnt(8, 0);
+      for (int a = 0; a < M; ++a) member[a] = cnt[h->ords[a].oct]++;
+    }
+    std::vector<int2> src((size_t)6 * M, make_int2(-1, -1));
+    std::vector<double> iwq((size_t)6 * M, 0.0);
+    for (int fd = 0; fd < 2 * h->dim; ++fd) {
+      const int d = fd / 2;
+      for (int a = 0; a < M; ++a) {
+        const double sn = (fd & 1) ? h->ords[a].s[d] : -h->ords[a].s[d];
+        if (!(sn < 0.0)) continue;
+        int m = -1;
+        for (int c = 0; c < M && m < 0; ++c) {
+          bool same = true;
+          for (int e = 0; e < h->dim; ++e) {
+            const double want = e == d ? -h->ords[a].s[e] : h->ords[a].s[e];
+            same = same && std::fabs(h->ords[c].s[e] - want) < 1e-12;
+          }
+          if (same) m = c;
+        }
+        if (m < 0) {
+          set_err("quadrature not closed under reflection of axis %d", d);
+          return BTE_ERR_INVALID;
+        }
+        src[(size_t)fd * M + a] = make_int2(h->ords[m].oct, member[m]);
+        iwq[(size_t)fd * M + a] = 1.0 / (h->ords[m].w * std::fabs(h->ords[m].s[d]));
+      }
+    }
+    HIPCHK(pp.upload(&h->d_spec_src, src));
+    HIPCHK(pp.upload(&h->d_spec_iwq, iwq));
+  }
   for (int k = 0; k < n; ++k) {
     Inst& I = h->inst[k];
     const HostInst& hi = I.hi;
@@ -545,7 +617,11 @@ bte_status build_static(bte_ctx* h) {
       ih[i] = 1.0 / half_range(h->ords, f / 2);
     }
     HIPCHK(pp.upload(&I.d_inv_half, ih));
-    const size_t nu = (size_t)h->B * std::max<size_t>(hi.bf_cell.size(), 1);
+    std::vector<int> sdir(hi.sface.size());
+    for (size_t i = 0; i < hi.sface.size(); ++i) sdir[i] = hi.bf_face[hi.sface[i]];
+    HIPCHK(pp.upload(&I.d_sface, hi.sface));
+    HIPCHK(pp.upload(&I.d_sface_dir, sdir));
+    const size_t nu = (size_t)h->B * h->ubf_rows * std::max<size_t>(hi.bf_cell.size(), 1);
     char* u1;
     char* u0;
     HIPCHK(pp.alloc(&u1, nu * es));
@@ -629,7 +705,7 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   if (s != BTE_OK) return s;
   Plan pl;
   if (h->dim == 3) {
-    pl.G = 2;
+    pl.G = h->has_specular ? 1 : 2;
     pl.R = 1;
     pl.P = 4;
     pl.C = 8;
@@ -709,7 +785,29 @@ bte_status enqueue_walls(bte_ctx* h, hipStream_t st) {
     w.ofk = I.d_ofk;
     w.grp_ob = I.d_grp_ob;
     w.B = h->B;
+    w.rows = h->ubf_rows;
     HIPCHK(launch_wall_update(h->precision, w, st));
+  }
+  return BTE_OK;
+}
+
+bte_status enqueue_specular(bte_ctx* h, hipStream_t st) {
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    if (I.hi.sface.empty()) continue;
+    SpecArgs a;
+    a.inst = h->d_inst_f;
+    a.inst_id = (int)k;
+    a.n_sface = (int)I.hi.sface.size();
+    a.sface_slot = I.d_sface;
+    a.sface_dir = I.d_sface_dir;
+    a.src = h->d_spec_src;
+    a.inv_wq = h->d_spec_iwq;
+    a.ofk = I.d_ofk;
+    a.grp_ob = I.d_grp_ob;
+    a.B = h->B;
+    a.M = h->ubf_rows;
+    HIPCHK(launch_spec_update(h->precision, a, st));
   }
   return BTE_OK;
 }
@@ -729,6 +827,10 @@ bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStre
     if (s != BTE_OK) return s;
     if (!adj && h->has_diffuse) {
       s = enqueue_walls(h, st);
+      if (s != BTE_OK) return s;
+    }
+    if (!adj && h->has_specular) {
+      s = enqueue_specular(h, st);
       if (s != BTE_OK) return s;
     }
   }
@@ -840,7 +942,7 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   UbfInitArgs u;
   u.ubf = I.d_ubf;
   u.n_bface = (int)I.hi.bf_cell.size();
-  u.B = h->B;
+  u.B = h->B * h->ubf_rows;
   u.bf_bc = I.d_bf_bc;
   u.bf_cell = I.d_bf_cell;
   u.bc_kind = I.d_bc_kind;
@@ -1140,7 +1242,7 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
     set_err("null handle or dJ/dT");
     return BTE_ERR_INVALID;
   }
-  if (h->has_diffuse) {
+  if (h->has_diffuse || h->has_specular) {
     set_err("the adjoint supports isothermal walls only");
     return BTE_ERR_INVALID;
   }

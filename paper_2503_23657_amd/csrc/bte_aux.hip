@@ -261,7 +261,35 @@ __global__ void __launch_bounds__(256) wall_update_kernel(WallArgs A) {
     for (int g = 0; g < gr.y; ++g) s += (double)outv[(size_t)(gr.x + g) * I.n_out_stride + k];
   }
   T* ubf = const_cast<T*>(reinterpret_cast<const T*>(I.ubf));
-  ubf[(size_t)b * I.n_bface + slot] = (T)(s * A.inv_half[df]);
+  // a diffuse wall's inflow is the same for every ordinate of the band
+  const T u = (T)(s * A.inv_half[df]);
+  for (int r = 0; r < A.rows; ++r) ubf[((size_t)b * A.rows + r) * I.n_bface + slot] = u;
+}
+
+// Lagged specular walls (Eq. 7): one thread per (ordinate, specular face), over
+// all bands; ordinates that leave through the face keep their (unused) entries.
+template <typename T>
+__global__ void __launch_bounds__(256) spec_update_kernel(SpecArgs A) {
+  const InstDev& I = A.inst[A.inst_id];
+  const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+  if (st->done) return;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)A.n_sface * A.M) return;
+  const int i = (int)(t % A.n_sface);
+  const int a = (int)(t / A.n_sface);
+  const int fd = A.sface_dir[i];
+  const int2 src = A.src[fd * A.M + a];
+  if (src.x < 0) return;
+  const int slot = A.sface_slot[i];
+  const int k = A.ofk[(size_t)src.x * I.n_bface + slot];
+  const double iwq = A.inv_wq[fd * A.M + a];
+  const T* outv = reinterpret_cast<const T*>(I.outv);
+  T* ubf = const_cast<T*>(reinterpret_cast<const T*>(I.ubf));
+  for (int b = 0; b < A.B; ++b) {
+    const int g = A.grp_ob[src.x * A.B + b].x + src.y;
+    const double v = (double)outv[(size_t)g * I.n_out_stride + k];
+    ubf[((size_t)b * A.M + a) * I.n_bface + slot] = (T)(v * iwq);
+  }
 }
 
 template <typename T>
@@ -342,6 +370,8 @@ template __global__ void finalize_kernel<float>(FinArgs, const FinInst*);
 template __global__ void finalize_kernel<double>(FinArgs, const FinInst*);
 template __global__ void wall_update_kernel<float>(WallArgs);
 template __global__ void wall_update_kernel<double>(WallArgs);
+template __global__ void spec_update_kernel<float>(SpecArgs);
+template __global__ void spec_update_kernel<double>(SpecArgs);
 template __global__ void init_state_kernel<float>(InitArgs);
 template __global__ void init_state_kernel<double>(InitArgs);
 
@@ -384,6 +414,16 @@ hipError_t launch_output(const double* X, const unsigned char* active, int n, do
 
 hipError_t launch_status_reset(StatusDev* stt, double n_active, hipStream_t st) {
   hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(1), 0, st, stt, n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_update(int prec, const SpecArgs& a, hipStream_t st) {
+  const long long n = (long long)a.n_sface * a.M;
+  if (n == 0) return hipSuccess;
+  if (prec == BTE_PREC_FP32)
+    hipLaunchKernelGGL(spec_update_kernel<float>, dim3(nblk(n)), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(spec_update_kernel<double>, dim3(nblk(n)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

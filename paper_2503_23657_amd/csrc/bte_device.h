@@ -41,7 +41,7 @@ constexpr uint32_t F_ACTIVE = 1u << 0;
 constexpr uint32_t F_IN_X = 1u << 1;   // upwind face on axis x is a boundary: consume one inflow entry
 constexpr uint32_t F_IN_Y = 1u << 2;
 constexpr uint32_t F_IN_Z = 1u << 3;
-constexpr uint32_t F_OUT_X = 1u << 4;  // downwind face on axis x is a diffuse wall: emit one outflow entry
+constexpr uint32_t F_OUT_X = 1u << 4;  // downwind face on axis x is a diffuse or specular wall: emit one outflow entry
 constexpr uint32_t F_OUT_Y = 1u << 5;
 constexpr uint32_t F_OUT_Z = 1u << 6;
 // bits 7..22 of the flags: i index of the position's cell in sweep orientation
@@ -156,7 +156,7 @@ struct SweepArgs {
   const JobDev* jobs;
   int n_jobs;
   int* counters;        // [2]: job ticket, exit ticket (self-resetting)
-  const int4* grp_i;    // [n_grp_total] (band, octant, instance-local group, 0)
+  const int4* grp_i;    // [n_grp_total] (band, octant, instance-local group, inflow-table row)
   const void* grp_t;    // [n_grp_total][grp_stride(G)]
   int B;
   int R, P, C;
@@ -211,6 +211,24 @@ struct WallArgs {
   const int* ofk;            // [n_oct][n_bface] index of the face in octant o's out-stream, or -1
   const int2* grp_ob;        // [n_oct][B] (first instance-local group, count)
   int B;
+  int rows;                  // inflow-table rows per band (1, or the ordinate count with specular walls)
+};
+
+// Lagged specular-wall values (Eq. 7): the inflow of ordinate a at a specular
+// face is the outgoing value of its mirror ordinate a' at the same cell, read
+// from the sweep's out-stream (w_a' |s_a'.n| u for one ordinate per group).
+struct SpecArgs {
+  const InstDev* inst;
+  int inst_id;
+  int n_sface;
+  const int* sface_slot;     // [n_sface] boundary-face slot of each specular face
+  const int* sface_dir;      // [n_sface] face direction 0..5 (-x, +x, -y, +y, -z, +z)
+  const int2* src;           // [6][M] (octant, member index) of the mirror of a, or (-1, -1) when a
+                             //        does not enter through that face direction
+  const double* inv_wq;      // [6][M] 1 / (w_a' |s_a'.n|)
+  const int* ofk;            // [n_oct][n_bface] index of the face in octant o's out-stream, or -1
+  const int2* grp_ob;        // [n_oct][B] (first instance-local group, count)
+  int B, M;
 };
 
 struct InitArgs {
@@ -225,8 +243,8 @@ struct InitArgs {
 };
 
 struct UbfInitArgs {
-  void* ubf;                 // [B][n_bface]
-  int n_bface, B;
+  void* ubf;                 // [B][rows][n_bface]
+  int n_bface, B;            // B: bands x rows
   const int* bf_bc;          // [n_bface]
   const int* bf_cell;        // [n_bface]
   const int* bc_kind;        // [n_bc]

@@ -26,6 +26,7 @@ int sweep2d_blocks_per_cu(int prec, int G, int NR, int P, int nacc, int mode, in
 
 hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st);
 hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st);
+hipError_t launch_spec_update(int prec, const SpecArgs& a, hipStream_t st);
 hipError_t launch_init_state(int prec, const InitArgs& a, int ncell, hipStream_t st);
 hipError_t launch_output(const double* X, const unsigned char* active, int n, double T_ref,
                          double add_ref, double* out, hipStream_t st);

@@ -32,8 +32,8 @@ std::string validate_problem(const bte_geometry* g, const bte_bands* b, const bt
   if (g->n_bc < 1 || g->n_bc > 255) return "n_bc must be in 1..255";
   if (!g->h_bc_kind || !g->h_bc_T) return "bc tables missing";
   for (int k = 0; k < g->n_bc; ++k) {
-    if (g->h_bc_kind[k] == BTE_BC_SPECULAR) return "specular walls are not supported";
-    if (g->h_bc_kind[k] != BTE_BC_ISOTHERMAL && g->h_bc_kind[k] != BTE_BC_DIFFUSE)
+    if (g->h_bc_kind[k] != BTE_BC_ISOTHERMAL && g->h_bc_kind[k] != BTE_BC_DIFFUSE &&
+        g->h_bc_kind[k] != BTE_BC_SPECULAR)
       return fmt("unknown bc kind %g", g->h_bc_kind[k]);
     if (!std::isfinite(g->h_bc_T[k])) return "non-finite wall temperature";
   }
@@ -115,6 +115,7 @@ void build_instance(const bte_geometry* g, HostInst& hi) {
   hi.bf_face.clear();
   hi.bf_bc.clear();
   hi.dface.clear();
+  hi.sface.clear();
   hi.has_iso = false;
   const int n0 = hi.n[0], n1 = hi.n[1];
   for (int c = 0; c < hi.ncell; ++c) {
@@ -134,6 +135,7 @@ void build_instance(const bte_geometry* g, HostInst& hi) {
       hi.bf_face.push_back(f);
       hi.bf_bc.push_back(bc);
       if (hi.bc_kind[bc] == BTE_BC_DIFFUSE) hi.dface.push_back(slot);
+      else if (hi.bc_kind[bc] == BTE_BC_SPECULAR) hi.sface.push_back(slot);
       else hi.has_iso = true;
     }
   }
@@ -273,6 +275,9 @@ void group_coefficients(const GroupSet& gs, const std::vector<Ordinate>& ords, c
     }
   }
 }
+
+// walls whose inflow is computed from the sweep's outflow (Eqs. 6 and 7)
+static bool reflecting(int kind) { return kind == BTE_BC_DIFFUSE || kind == BTE_BC_SPECULAR; }
 
 static int next_pow2(int x) {
   int p = 1;
@@ -418,7 +423,7 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
             }
             for (int d = 0; d < dim; ++d) {
               const int sd = hi.bslot[(size_t)cell * 6 + dn[d]];
-              if (sd >= 0 && hi.bc_kind[hi.bf_bc[sd]] == BTE_BC_DIFFUSE) {
+              if (sd >= 0 && reflecting(hi.bc_kind[hi.bf_bc[sd]])) {
                 fl |= (F2_OUTX << d) << sh;
                 out_face[(k * 2 + d) * 64 + l] = sd;
               }
@@ -646,7 +651,7 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
             }
             for (int d = 0; d < hi.dim; ++d) {
               const int sd = hi.bslot[(size_t)cell * 6 + dn[d]];
-              if (sd >= 0 && hi.bc_kind[hi.bf_bc[sd]] == BTE_BC_DIFFUSE) {
+              if (sd >= 0 && reflecting(hi.bc_kind[hi.bf_bc[sd]])) {
                 fl |= F_OUT_X << d;
                 s.ofk[(size_t)o * nbf + sd] = out_count + out_k;
                 ++out_k;

@@ -37,6 +37,7 @@ struct HostInst {
   std::vector<int> bc_kind;          // copy of the bc table
   std::vector<double> bc_T;
   std::vector<int> dface;            // slots of diffuse faces
+  std::vector<int> sface;            // slots of specular faces
   bool has_iso = false;
 };
 

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     // ---- this wave's group: band constants and per-ordinate coefficients
     const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
     const int4 gi = cp(A.grp_i)[g_glob];
-    const int band = gi.x;
+    const int ubf_row = gi.w;  // row of the inflow table: the band, or (band, ordinate) with specular walls
     const int g_loc = gi.z;
     const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
     const T kS = gt[0], cQ = gt[1];
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const GAS int2* SCH = gp(I.sched + slot_base);
     const GAS T2* XQ = gp(reinterpret_cast<const T2*>(I.xq[iter & 1]) + slot_base);
     const GAS T2* XF = MODE == M_TAUGRAD ? gp(reinterpret_cast<const T2*>(I.xf) + slot_base) : nullptr;
-    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
+    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)ubf_row * I.n_bface);
     const GAS int* ISLOT = gp(I.in_slot);
     const CAS int* ich = cp(I.in_chunk) + (size_t)(o * R + r) * (nch + 1);
     // buffer views of the chunk loop's global data (sizes in bytes): masked

@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     // ---- this wave's group: band constants and per-ordinate coefficients
     const int g_glob = __builtin_amdgcn_readfirstlane(jd.grp + p);
     const int4 gi = cp(A.grp_i)[g_glob];
-    const int band = gi.x;
+    const int ubf_row = gi.w;  // row of the inflow table: the band, or (band, ordinate) with specular walls
     const int g_loc = gi.z;
     const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
     T kS = gt[0], cQ = gt[1];
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const GAS int2* REC = gp(I.sched + slot * Tp * 64);
     const GAS VX* XQ = gp(reinterpret_cast<const VX*>(I.xq[iter & 1]) + slot * Tp * 64);
     const GAS VX* XF = MODE == M2_TAUGRAD ? gp(reinterpret_cast<const VX*>(I.xf) + slot * Tp * 64) : nullptr;
-    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)band * I.n_bface);
+    const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)ubf_row * I.n_bface);
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[slot]);

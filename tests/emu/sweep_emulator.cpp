@@ -72,10 +72,21 @@ int main(int argc, char** argv) {
   const int nbf = (int)hi.bf_cell.size();
   // state
   std::vector<double> X(ncell, 0.0);
-  std::vector<double> ubf((size_t)B * std::max(nbf, 1), 0.0);
+  // inflow table: one row per band, or per (band, ordinate) with specular walls
+  const bool has_spec = !hi.sface.empty();
+  const int Mf = (int)ords.size();
+  const int rows = has_spec ? Mf : 1;
+  if (has_spec && G != 1) { printf("specular walls need G = 1\n"); return 1; }
+  std::vector<double> ubf((size_t)B * rows * std::max(nbf, 1), 0.0);
   for (int f = 0; f < nbf; ++f) {
     const int bc = hi.bf_bc[f];
-    for (int b = 0; b < B; ++b) ubf[(size_t)b * nbf + f] = hi.bc_kind[bc] == 0 ? hi.bc_T[bc] - Tref : 0.0;
+    for (int br = 0; br < B * rows; ++br) ubf[(size_t)br * nbf + f] = hi.bc_kind[bc] == 0 ? hi.bc_T[bc] - Tref : 0.0;
+  }
+  // position of each ordinate among the members of its octant
+  std::vector<int> member(Mf, 0);
+  {
+    std::vector<int> cnt(8, 0);
+    for (int a = 0; a < Mf; ++a) member[a] = cnt[ords[a].oct]++;
   }
   const int n_oct = S.n_oct, T = S.T, W = S.W;
   const int nch = T / Cc;
@@ -94,6 +105,7 @@ int main(int argc, char** argv) {
         const int grp = gs.bundle_first[bu] + p;
         const double* gt = cf.data() + (size_t)grp * GS;
         const int band = gs.band[grp];
+        const int urow = has_spec ? band * Mf + std::max(0, gs.ords[(size_t)grp * G]) : band;
         const double kS = gt[0], cQ = gt[1];
         std::vector<std::vector<double>> f(R, std::vector<double>(64 * G, 0.0));
         std::vector<std::vector<double>> zring(R, std::vector<double>((size_t)W * G, 0.0));
@@ -103,7 +115,7 @@ int main(int argc, char** argv) {
         if (!L3)
           for (int c = 0; c < W; ++c) {
             const int sl = S.pre_slot[(size_t)o * W + c];
-            const double u = sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0;
+            const double u = sl >= 0 ? ub[(size_t)urow * nbf + sl] : 0.0;
             for (int gg = 0; gg < G; ++gg) zring[R - 1][c * G + gg] = u * gt[go_den(G) + gg];
           }
         for (int tau_ = 0; tau_ < T; ++tau_) {
@@ -139,7 +151,7 @@ int main(int argc, char** argv) {
               const unsigned fl = (unsigned)ent[l].y;
               for (int d = 0; d < 3; ++d)
                 if (fl & (F_IN_X << d)) {
-                  const double u = ub[(size_t)band * nbf + S.in_slot[k++]];
+                  const double u = ub[(size_t)urow * nbf + S.in_slot[k++]];
                   in_cur[r]++;
                   for (int gg = 0; gg < G; ++gg) {
                     const double val = u * gt[go_den(G) + gg];
@@ -223,12 +235,13 @@ int main(int argc, char** argv) {
         const int grp = gs.bundle_first[bu] + p;
         const double* gt = cf.data() + (size_t)grp * GS;
         const int band = gs.band[grp];
+        const int urow = has_spec ? band * Mf + std::max(0, gs.ords[(size_t)grp * G]) : band;
         const double kS = gt[0], cQ = gt[1];
         std::vector<std::vector<double>> f(R, std::vector<double>((size_t)64 * NR * G, 0.0));
         std::vector<std::vector<double>> ring(R, std::vector<double>((size_t)(W + 1) * G, 0.0));
         for (int c = 0; c < W; ++c) {
           const int sl = S.pre_slot[(size_t)o * W + c];
-          const double u = sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0;
+          const double u = sl >= 0 ? ub[(size_t)urow * nbf + sl] : 0.0;
           for (int gg = 0; gg < G; ++gg) ring[R - 1][c * G + gg] = u * gt[go_den(G) + gg];
         }
         std::vector<int> out_cnt(R, 0);
@@ -298,7 +311,7 @@ int main(int argc, char** argv) {
                 for (int k = 0; k < NR; ++k)
                   for (int gg = 0; gg < G; ++gg) {
                     const int sl = itab[e0 + k];
-                    xst[(size_t)k * G + gg] = (sl >= 0 ? ub[(size_t)band * nbf + sl] : 0.0) * gt[go_den(G) + gg];
+                    xst[(size_t)k * G + gg] = (sl >= 0 ? ub[(size_t)urow * nbf + sl] : 0.0) * gt[go_den(G) + gg];
                   }
               }
               for (int k = 0; k < NR; ++k) {
@@ -312,10 +325,10 @@ int main(int argc, char** argv) {
                 double a0s = 0.0, a1s = 0.0;
                 for (int gg = 0; gg < G; ++gg) {
                   const double den = gt[go_den(G) + gg];
-                  const double xu = (b & F2_INX) ? ub[(size_t)band * nbf + itab[ex]] * den
+                  const double xu = (b & F2_INX) ? ub[(size_t)urow * nbf + itab[ex]] * den
                                     : !xst.empty() ? xst[(size_t)k * G + gg]
                                                    : fold[((size_t)l * NR + k) * G + gg];
-                  const double zu = (b & F2_INY) ? ub[(size_t)band * nbf + itab[ey]] * den : zc[gg];
+                  const double zu = (b & F2_INY) ? ub[(size_t)urow * nbf + itab[ey]] * den : zc[gg];
                   const double fn = gt[go_a(G, 1) + gg] * zu + gt[go_a(G, 0) + gg] * xu + S_;
                   fnew[((size_t)l * NR + k) * G + gg] = fn;
                   zc[gg] = fn;
@@ -368,7 +381,29 @@ int main(int argc, char** argv) {
           for (int gg = 0; gg < gs.ob_count[o * B + b]; ++gg)
             sacc += outv[(size_t)(gs.ob_first[o * B + b] + gg) * S.n_out_stride + k];
         }
-        ubf[(size_t)b * nbf + df] = sacc / half_range(ords, hi.bf_face[df] / 2);
+        for (int r = 0; r < rows; ++r)
+          ubf[((size_t)b * rows + r) * nbf + df] = sacc / half_range(ords, hi.bf_face[df] / 2);
+      }
+    }
+    // specular faces: the incoming ordinate takes its mirror's outflow entry
+    for (int sf : hi.sface) {
+      const int fd = hi.bf_face[sf], d = fd / 2;
+      for (int a = 0; a < Mf; ++a) {
+        const double sn = (fd & 1) ? ords[a].s[d] : -ords[a].s[d];
+        if (!(sn < 0.0)) continue;
+        int m = -1;
+        for (int c = 0; c < Mf && m < 0; ++c) {
+          bool same = true;
+          for (int e2 = 0; e2 < dim; ++e2)
+            same = same && std::fabs(ords[c].s[e2] - (e2 == d ? -ords[a].s[e2] : ords[a].s[e2])) < 1e-12;
+          if (same) m = c;
+        }
+        const int om = ords[m].oct;
+        const int k = S.ofk[(size_t)om * nbf + sf];
+        for (int b = 0; b < B; ++b) {
+          const double vv = outv[(size_t)(gs.ob_first[om * B + b] + member[m]) * S.n_out_stride + k];
+          ubf[((size_t)b * Mf + a) * nbf + sf] = vv / (ords[m].w * std::fabs(ords[m].s[d]));
+        }
       }
     }
     X = acc0;

@@ -65,7 +65,21 @@ CASES = [
     ("box3d_diffuse", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4,
      (2, 1, 1, 8, 1)),
     ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
+    # specular walls (every boundary but the isothermal bottom, hole faces included)
+    ("film_specular", lambda: _film_specular(), 6, (1, 1, 1, 8, 1)),
+    ("box_specular", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)), 5,
+     (1, 1, 2, 8, 1)),
+    ("holes_specular_nr4_r2", lambda: bi.multi_hole_2d(50, 300, seed=4, n_bands=2, n_theta=1, n_phi=1,
+                                                        kinds=(0, 2)), 3, (1, 2, 2, 8, 4)),
+    ("box3d_specular", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)), 4,
+     (1, 1, 2, 8, 1)),
 ]
+
+
+def _film_specular():
+    """Film with a hot isothermal -x wall and a specular +x wall, with a source."""
+    p = bi.film_1d(n_cells=40, n_mu=8, Q=np.linspace(0.0, 1e18, 40))
+    return p.replace(bc_kind=np.array([bi.BC_ISOTHERMAL, bi.BC_SPECULAR], dtype=np.int32))
 
 
 @pytest.mark.parametrize("name,make,iters,plan", CASES, ids=[c[0] for c in CASES])

@@ -57,7 +57,7 @@ enum {
   BTE_BC_SPECULAR = 2    /* specularly reflecting adiabatic wall (Eq. 7): an incoming
                             ordinate takes the outgoing value of its mirror direction
                             at the same cell, lagged one iteration like the diffuse
-                            walls. Needs plans with G = 1; no adjoint. */
+                            walls. Needs plans with G = 1. */
 };
 
 /* Arithmetic of the sweeps. FP64: everything in double. FP32: the transport
@@ -188,9 +188,11 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
                      double* d_q, const bte_opts* opts, void* hip_stream, bte_report* h_rep);
 
 /* Adjoint of the converged source-iteration fixed point (needs a previous
-   bte_solve on h with opts->store_state = 1; isothermal walls only).
+   bte_solve on h with opts->store_state = 1).
    Given d_dJdT = dJ/dT [ncell], iterates lambda = dJ/dT + sum_b k_b sum_a psi
-   with psi = transpose sweeps (direction -s_a, zero inflow) of lambda, then
+   with psi = transpose sweeps (direction -s_a) of lambda. Isothermal walls give
+   the transposed sweeps zero inflow; diffuse and specular walls give them the
+   adjoint of the lagged reflection (Eqs. 6, 7), iterated with lambda. Then
    writes h_dJdtau [B] (host) and d_dJdQ [ncell] (device); either may be NULL. */
 bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, double* d_dJdQ,
                        const bte_opts* opts, void* hip_stream, bte_report* h_rep);

@@ -106,6 +106,8 @@ struct Inst {
   double* d_inv_half = nullptr;
   int* d_sface = nullptr;       // specular faces: slot and face direction
   int* d_sface_dir = nullptr;
+  int* d_dface_axis = nullptr;  // grid axis of each diffuse face
+  double* d_adj_scale = nullptr;  // [B][3] wall-value factor of the transposed sweeps
   void* d_ubf = nullptr;        // forward inflow table [B][rows][n_bface]
   void* d_ubf0 = nullptr;       // zeros (adjoint)
   // plan-dependent device data (owned by the plan pool)
@@ -146,8 +148,9 @@ struct bte_ctx {
   bool has_diffuse = false;
   bool has_specular = false;
   int ubf_rows = 1;                    // inflow-table rows per band: 1, or the ordinate count (specular)
-  int2* d_spec_src = nullptr;          // [6][M] mirror of each ordinate (octant, member), or -1
-  double* d_spec_iwq = nullptr;        // [6][M] 1 / (w_a' |s_a'.n|)
+  int2* d_spec_src = nullptr;          // [6][M] mirror of each incoming ordinate (octant, member), or -1
+  int2* d_spec_src_a = nullptr;        // [6][M] mirror of each outgoing ordinate (transposed sweeps)
+  double* d_spec_iwq = nullptr;        // [6][M] 1 / (w_a' |s_a'.n|) of the mirror a'
   int n_cu = 256;
   DevPool pool;                        // plan-independent
   std::unique_ptr<DevPool> ppool;      // plan-dependent
@@ -287,10 +290,13 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       for (int sf : I.hi.sface) {
         const int fd = I.hi.bf_face[sf], d = fd / 2;
         for (const auto& oa : h->ords) {
+          // forward: the outgoing ordinates' octants; transposed sweeps: the
+          // flipped octants of the incoming ones
           const double sn = (fd & 1) ? oa.s[d] : -oa.s[d];
-          if (!(sn > 0.0)) continue;
-          if (S.ofk[(size_t)oa.oct * nbf + sf] < 0) {
-            set_err("internal: specular face %d has no outflow entry in octant %d", sf, oa.oct);
+          if (sn == 0.0) continue;
+          const int os = sn > 0.0 ? oa.oct : oa.oct ^ (n_oct - 1);
+          if (S.ofk[(size_t)os * nbf + sf] < 0) {
+            set_err("internal: specular face %d has no outflow entry in octant %d", sf, os);
             return BTE_ERR_INVALID;
           }
         }
@@ -316,8 +322,8 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       int row = gs.band[g];
       if (h->has_specular) row = gs.band[g] * h->ubf_rows + std::max(0, gs.ords[(size_t)g * pl.G]);
       gif.push_back(make_int4(gs.band[g], gs.oct[g], g, row));
-      // the adjoint reads a table of zeros
-      gia.push_back(make_int4(gs.band[g], gs.oct[g] ^ (n_oct - 1), g, gs.band[g]));
+      // the adjoint has its own table (zero on isothermal faces), same rows
+      gia.push_back(make_int4(gs.band[g], gs.oct[g] ^ (n_oct - 1), g, row));
     }
     // device arrays of the schedule
     HIPCHK(pp.upload(&I.d_sched, S.sched));
@@ -564,13 +570,13 @@ bte_status build_static(bte_ctx* h) {
       std::vector<int> cnt(8, 0);
       for (int a = 0; a < M; ++a) member[a] = cnt[h->ords[a].oct]++;
     }
-    std::vector<int2> src((size_t)6 * M, make_int2(-1, -1));
+    std::vector<int2> src((size_t)6 * M, make_int2(-1, -1)), src_a((size_t)6 * M, make_int2(-1, -1));
     std::vector<double> iwq((size_t)6 * M, 0.0);
     for (int fd = 0; fd < 2 * h->dim; ++fd) {
       const int d = fd / 2;
       for (int a = 0; a < M; ++a) {
         const double sn = (fd & 1) ? h->ords[a].s[d] : -h->ords[a].s[d];
-        if (!(sn < 0.0)) continue;
+        if (sn == 0.0) continue;
         int m = -1;
         for (int c = 0; c < M && m < 0; ++c) {
           bool same = true;
@@ -584,11 +590,14 @@ bte_status build_static(bte_ctx* h) {
           set_err("quadrature not closed under reflection of axis %d", d);
           return BTE_ERR_INVALID;
         }
-        src[(size_t)fd * M + a] = make_int2(h->ords[m].oct, member[m]);
+        // incoming ordinates read their mirror in the forward iteration,
+        // outgoing ones in the transposed iteration
+        (sn < 0.0 ? src : src_a)[(size_t)fd * M + a] = make_int2(h->ords[m].oct, member[m]);
         iwq[(size_t)fd * M + a] = 1.0 / (h->ords[m].w * std::fabs(h->ords[m].s[d]));
       }
     }
     HIPCHK(pp.upload(&h->d_spec_src, src));
+    HIPCHK(pp.upload(&h->d_spec_src_a, src_a));
     HIPCHK(pp.upload(&h->d_spec_iwq, iwq));
   }
   for (int k = 0; k < n; ++k) {
@@ -621,6 +630,10 @@ bte_status build_static(bte_ctx* h) {
     for (size_t i = 0; i < hi.sface.size(); ++i) sdir[i] = hi.bf_face[hi.sface[i]];
     HIPCHK(pp.upload(&I.d_sface, hi.sface));
     HIPCHK(pp.upload(&I.d_sface_dir, sdir));
+    std::vector<int> dax(hi.dface.size());
+    for (size_t i = 0; i < hi.dface.size(); ++i) dax[i] = hi.bf_face[hi.dface[i]] / 2;
+    HIPCHK(pp.upload(&I.d_dface_axis, dax));
+    HIPCHK(pp.alloc(&I.d_adj_scale, (size_t)h->B * 3));
     const size_t nu = (size_t)h->B * h->ubf_rows * std::max<size_t>(hi.bf_cell.size(), 1);
     char* u1;
     char* u0;
@@ -772,12 +785,12 @@ bte_status enqueue_finalize(bte_ctx* h, bool adj, int flags, const bte_opts& o, 
   return BTE_OK;
 }
 
-bte_status enqueue_walls(bte_ctx* h, hipStream_t st) {
+bte_status enqueue_walls(bte_ctx* h, bool adj, hipStream_t st) {
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
     if (I.hi.dface.empty()) continue;
     WallArgs w;
-    w.inst = h->d_inst_f;
+    w.inst = adj ? h->d_inst_a : h->d_inst_f;
     w.inst_id = (int)k;
     w.n_dface = (int)I.hi.dface.size();
     w.dface_slot = I.d_dface;
@@ -786,27 +799,32 @@ bte_status enqueue_walls(bte_ctx* h, hipStream_t st) {
     w.grp_ob = I.d_grp_ob;
     w.B = h->B;
     w.rows = h->ubf_rows;
+    w.dface_axis = I.d_dface_axis;
+    w.oct_xor = adj ? (1 << h->dim) - 1 : 0;
+    w.scale = adj ? I.d_adj_scale : nullptr;
     HIPCHK(launch_wall_update(h->precision, w, st));
   }
   return BTE_OK;
 }
 
-bte_status enqueue_specular(bte_ctx* h, hipStream_t st) {
+bte_status enqueue_specular(bte_ctx* h, bool adj, hipStream_t st) {
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
     if (I.hi.sface.empty()) continue;
     SpecArgs a;
-    a.inst = h->d_inst_f;
+    a.inst = adj ? h->d_inst_a : h->d_inst_f;
     a.inst_id = (int)k;
     a.n_sface = (int)I.hi.sface.size();
     a.sface_slot = I.d_sface;
     a.sface_dir = I.d_sface_dir;
-    a.src = h->d_spec_src;
+    a.src = adj ? h->d_spec_src_a : h->d_spec_src;
     a.inv_wq = h->d_spec_iwq;
     a.ofk = I.d_ofk;
     a.grp_ob = I.d_grp_ob;
     a.B = h->B;
     a.M = h->ubf_rows;
+    a.oct_xor = adj ? (1 << h->dim) - 1 : 0;
+    a.scale = adj ? I.d_adj_scale : nullptr;
     HIPCHK(launch_spec_update(h->precision, a, st));
   }
   return BTE_OK;
@@ -825,12 +843,12 @@ bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStre
     if (last) fl |= FIN_CHECK | FIN_QPREV;
     s = enqueue_finalize(h, adj, fl, o, st);
     if (s != BTE_OK) return s;
-    if (!adj && h->has_diffuse) {
-      s = enqueue_walls(h, st);
+    if (h->has_diffuse) {
+      s = enqueue_walls(h, adj, st);
       if (s != BTE_OK) return s;
     }
-    if (!adj && h->has_specular) {
-      s = enqueue_specular(h, st);
+    if (h->has_specular) {
+      s = enqueue_specular(h, adj, st);
       if (s != BTE_OK) return s;
     }
   }
@@ -1242,10 +1260,6 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
     set_err("null handle or dJ/dT");
     return BTE_ERR_INVALID;
   }
-  if (h->has_diffuse || h->has_specular) {
-    set_err("the adjoint supports isothermal walls only");
-    return BTE_ERR_INVALID;
-  }
   for (auto& I : h->inst)
     if (!I.stored) {
       set_err("bte_adjoint needs a previous solve with store_state = 1");
@@ -1268,6 +1282,24 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
   }
   HIPCHK(hipMemcpyAsync(h->d_inst_a, ida.data(), n * sizeof(InstDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_fin_a, h->fin_a.data(), n * sizeof(FinInst), hipMemcpyHostToDevice, st));
+  // reflecting walls: the wall-value adjoint mu (the transpose of the lagged
+  // reflection) starts at zero; the transposed sweeps take mu back as inflow
+  // through the factor 4 pi tau_b D h_d / (C_b t0 v_b) per band and face axis
+  const double Dtot = total_D(h);
+  std::vector<std::vector<double>> adj_scale(n);
+  for (size_t k = 0; k < n; ++k) {
+    Inst& I = h->inst[k];
+    if (I.hi.dface.empty() && I.hi.sface.empty()) continue;
+    adj_scale[k].assign((size_t)h->B * 3, 0.0);
+    for (int b = 0; b < h->B; ++b)
+      for (int d = 0; d < I.hi.dim; ++d)
+        adj_scale[k][(size_t)b * 3 + d] =
+            4.0 * kPi * h->tau[b] * Dtot * I.hi.h[d] / (h->C[b] * h->t0 * h->v[b]);
+    HIPCHK(hipMemcpyAsync(I.d_adj_scale, adj_scale[k].data(), adj_scale[k].size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    const size_t nu = (size_t)h->B * h->ubf_rows * std::max<size_t>(I.hi.bf_cell.size(), 1);
+    HIPCHK(launch_zero(I.d_ubf0, nu * elem(h->precision), st));
+  }
   for (size_t k = 0; k < n; ++k) {
     Inst& I = h->inst[k];
     InitArgs a;

@@ -255,14 +255,17 @@ __global__ void __launch_bounds__(256) wall_update_kernel(WallArgs A) {
   const T* outv = reinterpret_cast<const T*>(I.outv);
   double s = 0.0;
   for (int o = 0; o < I.n_oct; ++o) {
+    // o: the octant whose schedule emitted the entries; its groups belong to
+    // octant o ^ oct_xor (the transposed sweeps run the flipped schedule)
     const int k = A.ofk[(size_t)o * I.n_bface + slot];
     if (k < 0) continue;
-    const int2 gr = A.grp_ob[o * A.B + b];
+    const int2 gr = A.grp_ob[(o ^ A.oct_xor) * A.B + b];
     for (int g = 0; g < gr.y; ++g) s += (double)outv[(size_t)(gr.x + g) * I.n_out_stride + k];
   }
   T* ubf = const_cast<T*>(reinterpret_cast<const T*>(I.ubf));
   // a diffuse wall's inflow is the same for every ordinate of the band
-  const T u = (T)(s * A.inv_half[df]);
+  const double sc = A.scale ? A.scale[b * 3 + A.dface_axis[df]] : 1.0;
+  const T u = (T)(s * A.inv_half[df] * sc);
   for (int r = 0; r < A.rows; ++r) ubf[((size_t)b * A.rows + r) * I.n_bface + slot] = u;
 }
 
@@ -281,14 +284,16 @@ __global__ void __launch_bounds__(256) spec_update_kernel(SpecArgs A) {
   const int2 src = A.src[fd * A.M + a];
   if (src.x < 0) return;
   const int slot = A.sface_slot[i];
-  const int k = A.ofk[(size_t)src.x * I.n_bface + slot];
+  // the mirror's group sweeps the schedule of octant src.x ^ oct_xor
+  const int k = A.ofk[(size_t)(src.x ^ A.oct_xor) * I.n_bface + slot];
   const double iwq = A.inv_wq[fd * A.M + a];
   const T* outv = reinterpret_cast<const T*>(I.outv);
   T* ubf = const_cast<T*>(reinterpret_cast<const T*>(I.ubf));
   for (int b = 0; b < A.B; ++b) {
     const int g = A.grp_ob[src.x * A.B + b].x + src.y;
     const double v = (double)outv[(size_t)g * I.n_out_stride + k];
-    ubf[((size_t)b * A.M + a) * I.n_bface + slot] = (T)(v * iwq);
+    const double sc = A.scale ? A.scale[b * 3 + fd / 2] : 1.0;
+    ubf[((size_t)b * A.M + a) * I.n_bface + slot] = (T)(v * iwq * sc);
   }
 }
 

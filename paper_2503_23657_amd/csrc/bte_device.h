@@ -212,11 +212,16 @@ struct WallArgs {
   const int2* grp_ob;        // [n_oct][B] (first instance-local group, count)
   int B;
   int rows;                  // inflow-table rows per band (1, or the ordinate count with specular walls)
+  const int* dface_axis;     // [n_dface] grid axis of each diffuse face
+  int oct_xor;               // 0: forward; n_oct - 1: transposed sweeps (groups sweep the flipped octant)
+  const double* scale;       // [B][3] factor per band and face axis (transposed sweeps), or NULL
 };
 
 // Lagged specular-wall values (Eq. 7): the inflow of ordinate a at a specular
 // face is the outgoing value of its mirror ordinate a' at the same cell, read
 // from the sweep's out-stream (w_a' |s_a'.n| u for one ordinate per group).
+// The transposed sweeps use the same kernel with the roles of incoming and
+// outgoing ordinates exchanged (the src table of the other side).
 struct SpecArgs {
   const InstDev* inst;
   int inst_id;
@@ -229,6 +234,8 @@ struct SpecArgs {
   const int* ofk;            // [n_oct][n_bface] index of the face in octant o's out-stream, or -1
   const int2* grp_ob;        // [n_oct][B] (first instance-local group, count)
   int B, M;
+  int oct_xor;               // 0: forward; n_oct - 1: transposed sweeps
+  const double* scale;       // [B][3] factor per band and face axis (transposed sweeps), or NULL
 };
 
 struct InitArgs {

@@ -271,6 +271,9 @@ void group_coefficients(const GroupSet& gs, const std::vector<Ordinate>& ords, c
         r[go_wacc(G, 1) + g] = gamma * omega * inv;
         r[go_wt(G, 0) + g] = omega * inv;
         r[go_wt(G, 1) + g] = omega;
+        // outflow entries of the transposed sweep at reflecting walls: the
+        // wall-value adjoint beta_d psi with psi = omega * inv * (sweep value)
+        for (int d = 0; d < hi.dim; ++d) r[go_wo(G, d) + g] = beta[d] * omega * inv;
       }
     }
   }

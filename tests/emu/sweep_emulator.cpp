@@ -369,28 +369,38 @@ int main(int argc, char** argv) {
     if (dim < 3) sweep2d(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
     else sweep(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
   };
-  std::vector<double> acc0, acc1;
-  for (int it = 0; it < iters; ++it) {
-    run_sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+  // lagged wall values from the last sweep's outflow entries. Forward: the
+  // diffuse and specular inflows. Transposed sweeps (adj): the wall-value
+  // adjoint, read from the entries of the flipped schedules and scaled by
+  // 4 pi tau_b D h_d / (C_b t0 v_b).
+  double Dsum = 0.0;
+  for (int b = 0; b < B; ++b) Dsum += C[b] / tau[b];
+  auto wall_scale = [&](bool adj, int b, int d) {
+    return adj ? 4.0 * M_PI * tau[b] * Dsum * hi.h[d] / (C[b] * t0 * v[b]) : 1.0;
+  };
+  auto update_walls = [&](bool adj, std::vector<double>& tab) {
+    const int ox = adj ? n_oct - 1 : 0;
     for (int df : hi.dface) {
       for (int b = 0; b < B; ++b) {
         double sacc = 0.0;
         for (int o = 0; o < n_oct; ++o) {
           const int k = S.ofk[(size_t)o * nbf + df];
           if (k < 0) continue;
-          for (int gg = 0; gg < gs.ob_count[o * B + b]; ++gg)
-            sacc += outv[(size_t)(gs.ob_first[o * B + b] + gg) * S.n_out_stride + k];
+          const int og = o ^ ox;
+          for (int gg = 0; gg < gs.ob_count[og * B + b]; ++gg)
+            sacc += outv[(size_t)(gs.ob_first[og * B + b] + gg) * S.n_out_stride + k];
         }
-        for (int r = 0; r < rows; ++r)
-          ubf[((size_t)b * rows + r) * nbf + df] = sacc / half_range(ords, hi.bf_face[df] / 2);
+        const double val = sacc / half_range(ords, hi.bf_face[df] / 2) * wall_scale(adj, b, hi.bf_face[df] / 2);
+        for (int r = 0; r < rows; ++r) tab[((size_t)b * rows + r) * nbf + df] = val;
       }
     }
-    // specular faces: the incoming ordinate takes its mirror's outflow entry
+    // specular faces: forward, an incoming ordinate takes its mirror's entry;
+    // transposed, an outgoing one does
     for (int sf : hi.sface) {
       const int fd = hi.bf_face[sf], d = fd / 2;
       for (int a = 0; a < Mf; ++a) {
         const double sn = (fd & 1) ? ords[a].s[d] : -ords[a].s[d];
-        if (!(sn < 0.0)) continue;
+        if (adj ? !(sn > 0.0) : !(sn < 0.0)) continue;
         int m = -1;
         for (int c = 0; c < Mf && m < 0; ++c) {
           bool same = true;
@@ -399,13 +409,18 @@ int main(int argc, char** argv) {
           if (same) m = c;
         }
         const int om = ords[m].oct;
-        const int k = S.ofk[(size_t)om * nbf + sf];
+        const int k = S.ofk[(size_t)(om ^ ox) * nbf + sf];
         for (int b = 0; b < B; ++b) {
           const double vv = outv[(size_t)(gs.ob_first[om * B + b] + member[m]) * S.n_out_stride + k];
-          ubf[((size_t)b * Mf + a) * nbf + sf] = vv / (ords[m].w * std::fabs(ords[m].s[d]));
+          tab[((size_t)b * Mf + a) * nbf + sf] = vv / (ords[m].w * std::fabs(ords[m].s[d])) * wall_scale(adj, b, d);
         }
       }
     }
+  };
+  std::vector<double> acc0, acc1;
+  for (int it = 0; it < iters; ++it) {
+    run_sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+    update_walls(false, ubf);
     X = acc0;
   }
   if (argc > 2) {
@@ -418,13 +433,14 @@ int main(int argc, char** argv) {
     run_sweep(X, Q, coef, false, ubf, acc0, acc1, &store, nullptr, nullptr, nullptr);
     std::vector<double> ca;
     group_coefficients(gs, ords, hi, v, tau, C, t0, true, ca);
-    std::vector<double> zero(ubf.size(), 0.0), lam = g, dumQ(ncell, 0.0);
+    std::vector<double> ubfa(ubf.size(), 0.0), lam = g, dumQ(ncell, 0.0);
     for (int it = 0; it < iters; ++it) {
-      run_sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+      run_sweep(lam, dumQ, ca, true, ubfa, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
+      update_walls(true, ubfa);
       for (int c = 0; c < ncell; ++c) lam[c] = hi.active[c] ? g[c] + acc0[c] : 0.0;
     }
     std::vector<double> tg(2 * gs.band.size(), 0.0);
-    run_sweep(lam, dumQ, ca, true, zero, acc0, acc1, nullptr, &store, &X, &tg);
+    run_sweep(lam, dumQ, ca, true, ubfa, acc0, acc1, nullptr, &store, &X, &tg);
     double D = 0.0;
     for (int b = 0; b < B; ++b) D += C[b] / tau[b];
     double L = 0.0;

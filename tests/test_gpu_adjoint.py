@@ -25,8 +25,8 @@ def _loss_parts(p, probes, target):
     return loss_t
 
 
-def _gpu_grads(bte, p, loss_t, precision="fp64", tol=1e-13):
-    s = bte.Solver(p, precision=precision)
+def _gpu_grads(bte, p, loss_t, precision="fp64", tol=1e-13, plan=None):
+    s = bte.Solver(p, precision=precision, plan=plan)
     Q = torch.tensor(p.Q, dtype=torch.float64, device="cuda")
     T, _, rep = s.solve(Q, tol=tol, check_every=4, store_state=True)
     Tl = T.detach().clone().requires_grad_(True)
@@ -136,12 +136,97 @@ def test_adjoint_requires_stored_state(hip_lib):
     s.close()
 
 
-def test_adjoint_rejects_diffuse_walls(hip_lib):
-    p = bi.random_box_2d(9, 7, seed=0, kinds=(0, 1))
-    s = hip_lib.Solver(p, precision="fp64")
-    Q = torch.tensor(p.Q, device="cuda")
-    s.solve(Q, tol=1e-8, store_state=True)
-    with pytest.raises(hip_lib.BTEError) as ei:
-        s.adjoint(torch.zeros(p.ncell, dtype=torch.float64, device="cuda"))
-    assert ei.value.status == hip_lib.BTE_ERR_INVALID
+@pytest.mark.parametrize("kind,plan", [(1, None), (1, dict(G=2, R=1, P=1, NR=1)), (2, None),
+                                       (2, dict(G=1, R=2, P=1, NR=1))])
+def test_adjoint_with_reflecting_walls_matches_complex_step(hip_lib, kind, plan):
+    """Diffuse (kind 1) or specular (kind 2) walls on every face but the
+    isothermal bottom, hole faces included: the transposed sweeps carry the
+    adjoint of the lagged wall values."""
+    p = bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
+    probes = np.flatnonzero(p.mask)[[2, 9, 17, 23]]
+    T0 = dense.solve_dense(p)
+    target = T0[probes] + 0.05
+    loss_t = _loss_parts(p, probes, target)
+    dtau, dQ, T, rep, rep_a = _gpu_grads(hip_lib, p, loss_t, plan=plan)
+    assert rep["status"] == "ok" and rep_a["status"] == "ok"
+
+    def loss(TT):
+        return ((TT[probes] - target) ** 2).mean()
+
+    act = np.flatnonzero(p.mask)
+    gt = dense.complex_step_grad(p, loss, "tau")
+    gq = dense.complex_step_grad(p, loss, "Q", idx=list(act))
+    assert np.abs(dtau - gt).max() < 1e-8 * np.abs(gt).max()
+    assert np.abs(dQ[act] - gq).max() < 1e-8 * np.abs(gq).max()
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_adjoint_3d_reflecting_walls_matches_complex_step(hip_lib, kind):
+    p = bi.random_box_3d(4, 3, 5, seed=5, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
+    probes = np.flatnonzero(p.mask)[[1, 7, 20, 33, 41]]
+    T0 = dense.solve_dense(p)
+    target = T0[probes] - 0.03
+    loss_t = _loss_parts(p, probes, target)
+    dtau, dQ, T, rep, rep_a = _gpu_grads(hip_lib, p, loss_t)
+
+    def loss(TT):
+        return ((TT[probes] - target) ** 2).mean()
+
+    act = np.flatnonzero(p.mask)
+    gt = dense.complex_step_grad(p, loss, "tau")
+    gq = dense.complex_step_grad(p, loss, "Q", idx=list(act))
+    assert np.abs(dtau - gt).max() < 1e-8 * np.abs(gt).max()
+    assert np.abs(dQ[act] - gq).max() < 1e-8 * np.abs(gq).max()
+
+
+def _fd_check(bte, p, probes, target, fd_tau, fd_Q, rtol=1e-5):
+    s = bte.Solver(p, precision="fp64")
+    pr = torch.tensor(probes, device="cuda")
+    tg = torch.tensor(target, device="cuda")
+
+    def J_of(tau, Q):
+        s.set_tau(tau)
+        T, _, _ = s.solve(torch.tensor(Q, device="cuda"), tol=1e-13, check_every=8)
+        return float(((T[pr] - tg) ** 2).mean())
+
+    s.set_tau(p.tau)
+    T, _, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=1e-13, check_every=8, store_state=True)
+    Tl = T.detach().clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(((Tl[pr] - tg) ** 2).mean(), Tl)
+    dtau, dQ, _ = s.adjoint(g.contiguous(), tol=1e-13, check_every=8)
+    dQ = dQ.cpu().numpy()
+    for b in fd_tau:
+        hstep = 1e-4 * p.tau[b]
+        tp, tm = p.tau.copy(), p.tau.copy()
+        tp[b] += hstep
+        tm[b] -= hstep
+        fd = (J_of(tp, p.Q) - J_of(tm, p.Q)) / (2 * hstep)
+        assert abs(fd - dtau[b]) < rtol * abs(dtau).max(), (b, fd, dtau[b])
+    for c in fd_Q:
+        hstep = 1e-3 * p.Q.max()
+        qp, qm = p.Q.copy(), p.Q.copy()
+        qp[c] += hstep
+        qm[c] -= hstep
+        fd = (J_of(p.tau, qp) - J_of(p.tau, qm)) / (2 * hstep)
+        assert abs(fd - dQ[c]) < rtol * np.abs(dQ).max(), (c, fd, dQ[c])
     s.close()
+
+
+def test_adjoint_vs_central_differences_specular_square(hip_lib):
+    """The paper's 2D inverse setting: isothermal bottom, specular walls on the
+    other sides; FD of the GPU FP64 forward on tau and Q entries."""
+    p = bi.random_box_2d(40, 40, seed=7, n_bands=15, n_theta=2, n_phi=2, hole=False, kinds=(0, 2), Q0=1e19)
+    rng = np.random.default_rng(8)
+    act = np.flatnonzero(p.mask)
+    probes = np.sort(rng.choice(act, 20, replace=False))
+    target = 300.0 + rng.uniform(0.0, 2.0, size=20)
+    _fd_check(hip_lib, p, probes, target, fd_tau=[0, 7, 14], fd_Q=list(rng.choice(act, 4, replace=False)))
+
+
+def test_adjoint_vs_central_differences_finfet_mixed(hip_lib):
+    p = bi.finfet_3d_mixed(scale=8, n_bands=3, n_theta=2, n_phi=2)
+    rng = np.random.default_rng(9)
+    act = np.flatnonzero(p.mask)
+    probes = np.sort(rng.choice(act, 12, replace=False))
+    target = 300.0 + rng.uniform(0.0, 1.0, size=12)
+    _fd_check(hip_lib, p, probes, target, fd_tau=[0, 2], fd_Q=list(rng.choice(act[p.Q[act] > 0], 3, replace=False)))

@@ -111,7 +111,6 @@ def test_specular_plans_need_one_ordinate_per_group(hip_lib):
         best = s.autotune(Q, n_iters=2)
         assert best["G"] == 1
         T, _, rep = s.solve(Q, tol=0.0, max_iters=4, check_every=4, store_state=True)
-        with pytest.raises(hip_lib.BTEError, match="isothermal walls only"):
-            s.adjoint(torch.zeros(p.ncell, dtype=torch.float64, device="cuda"))
+        assert rep["iters"] == 4
     finally:
         s.close()

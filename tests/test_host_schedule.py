@@ -117,3 +117,34 @@ def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
     dQ = np.array([float(l.split()[1]) for l in out if l.startswith("dQ")])
     assert np.abs(dtau - gt).max() < 1e-8 * np.abs(gt).max()
     assert np.abs(dQ - gq).max() < 1e-10 * np.abs(gq).max()
+
+
+@pytest.mark.parametrize("kind,plan", [(1, (2, 1, 1, 8, 1)), (1, (1, 1, 2, 8, 2)), (2, (1, 1, 1, 8, 1)),
+                                       (2, (1, 2, 1, 8, 1))])
+def test_emulated_adjoint_with_walls_matches_dense(emu, tmp_path, kind, plan):
+    """Transposed sweeps with the wall-value adjoint (the transpose of the
+    lagged diffuse or specular reflection) against complex-step derivatives of
+    the dense discrete fixed point."""
+    from oracle import dense
+    p = bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
+    iters = 1500
+    probes = np.flatnonzero(p.mask)[[2, 9, 17, 23]]
+    T0 = dense.solve_dense(p)
+    target = T0[probes] + 0.05
+
+    def loss(T):
+        return ((T[probes] - target) ** 2).mean()
+
+    gt = dense.complex_step_grad(p, loss, wrt="tau")
+    gq = dense.complex_step_grad(p, loss, wrt="Q", idx=list(np.flatnonzero(p.mask)))
+    gT = np.zeros(p.ncell)
+    gT[probes] = 2.0 * (T0[probes] - target) / probes.size
+    gpath = str(tmp_path / "g.bin")
+    gT.astype(np.float64).tofile(gpath)
+    path = str(tmp_path / "in.bin")
+    _write(p, iters, plan, path)
+    out = subprocess.run([emu, path, gpath], capture_output=True, text=True, check=True).stdout.split("\n")
+    dtau = np.array([float(l.split()[1]) for l in out if l.startswith("dtau")])
+    dQ = np.array([float(l.split()[1]) for l in out if l.startswith("dQ")])[np.flatnonzero(p.mask)]
+    assert np.abs(dtau - gt).max() < 1e-8 * np.abs(gt).max()
+    assert np.abs(dQ - gq).max() < 1e-8 * np.abs(gq).max()

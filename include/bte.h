@@ -197,6 +197,16 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
 bte_status bte_adjoint(bte_handle h, const double* d_dJdT, double* h_dJdtau, double* d_dJdQ,
                        const bte_opts* opts, void* hip_stream, bte_report* h_rep);
 
+/* Derivative of the adjoint's objective with respect to a common factor s on
+   every cell size h_d (s = 1: the geometry as created), i.e. L dJ/dL when all
+   lengths scale with L (Results, "1D inverse problem for system size": the
+   film-thickness gradient). Every beta_d = v|s_d|/h_d scales as 1/s, so by the forward
+   equation dJ/ds = -sum_b (1/tau_b) sum_{a,c} psi (u - dT) + sum_c Q_c dJ/dQ_c
+   with the adjoint field psi of the last bte_adjoint / bte_batch_adjoint on h.
+   h_dJds: [n_inst] host output. BTE_ERR_STATE when no adjoint has run since the
+   last solve. */
+bte_status bte_adjoint_dscale(bte_handle h, double* h_dJds);
+
 /* Average device time (ms) of one launch of the forward sweep kernel on the
    current state, measured with HIP events around n_launches back-to-back
    launches on hip_stream; also returns the number of cell x ordinate x band

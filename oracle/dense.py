@@ -66,7 +66,7 @@ def solve_dense(p, tau=None, Q=None, return_all=False):
     (absolute; 0 on inactive cells), or (T, e, eb, faces) with return_all."""
     tau = np.asarray(p.tau if tau is None else tau)
     Q = np.asarray(p.Q if Q is None else Q)
-    dtype = np.result_type(tau.dtype, Q.dtype, np.float64)
+    dtype = np.result_type(tau.dtype, Q.dtype, np.asarray(p.h).dtype, np.float64)
     B, M, dim = p.B, p.M, p.dim
     act, index = _geometry(p)
     Na = act.size
@@ -168,3 +168,11 @@ def complex_step_grad(p, loss, wrt="tau", idx=None, hstep=1e-30):
         T = solve_dense(p, tau=th) if wrt == "tau" else solve_dense(p, Q=th)
         out.append(loss(T).imag / hstep)
     return np.array(out)
+
+
+def complex_step_dscale(p, loss, hstep=1e-30):
+    """d loss(T) / d s for a common factor s on every cell size (all lengths of
+    the geometry scaled, s = 1), by the complex step on the cell sizes."""
+    h = tuple(complex(hd) * (1.0 + 1j * hstep) for hd in p.h)
+    T = solve_dense(p.replace(h=h))
+    return loss(T).imag / hstep

@@ -101,6 +101,7 @@ bte_get_plan = _sig("bte_get_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_autotune = _sig("bte_autotune", _S, [_H, _P, ctypes.c_int, _P, ctypes.POINTER(Plan)])
 bte_solve = _sig("bte_solve", _S, [_H, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
 bte_adjoint = _sig("bte_adjoint", _S, [_H, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
+bte_adjoint_dscale = _sig("bte_adjoint_dscale", _S, [_H, _P])
 bte_time_sweep = _sig("bte_time_sweep", _S, [_H, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double)])
 bte_batch_solve = _sig("bte_batch_solve", _S, [_H, _P, _P, _P, ctypes.POINTER(Opts), _P, _P])
@@ -109,7 +110,7 @@ bte_destroy = _sig("bte_destroy", _S, [_H])
 
 EXPORTED = ["bte_version", "bte_last_error", "bte_validate", "bte_quadrature_gl_mu",
             "bte_quadrature_octant_gl", "bte_create", "bte_set_tau", "bte_set_plan", "bte_get_plan",
-            "bte_autotune", "bte_solve", "bte_adjoint", "bte_time_sweep", "bte_batch_create",
+            "bte_autotune", "bte_solve", "bte_adjoint", "bte_adjoint_dscale", "bte_time_sweep", "bte_batch_create",
             "bte_batch_solve", "bte_batch_adjoint", "bte_destroy"]
 
 
@@ -286,6 +287,13 @@ class Solver:
         _check(st, allow)
         return dtau, dq, rep.as_dict()
 
+    def adjoint_dscale(self) -> float:
+        """dJ/ds of the last adjoint for a common factor s on every cell size
+        (L dJ/dL when all lengths scale with L)."""
+        out = np.zeros(1)
+        _check(bte_adjoint_dscale(self._h, out.ctypes.data))
+        return float(out[0])
+
     def time_sweep(self, n_launches=20, stream=None):
         ms = ctypes.c_double()
         upd = ctypes.c_double()
@@ -355,6 +363,13 @@ class BatchSolver:
         st = bte_batch_adjoint(self._h, ag, dtau.ctypes.data, aq, ctypes.byref(o), _stream(stream), reps)
         _check(st, (BTE_ERR_NOT_CONVERGED,))
         return dtau.reshape(n, B), dqs, [r.as_dict() for r in reps]
+
+    def adjoint_dscale(self) -> np.ndarray:
+        """dJ/ds of the last batched adjoint, per instance (common factor s on
+        every cell size of that instance)."""
+        out = np.zeros(len(self.problems))
+        _check(bte_adjoint_dscale(self._h, out.ctypes.data))
+        return out
 
 
 from .autograd import BTESolve  # noqa: E402,F401

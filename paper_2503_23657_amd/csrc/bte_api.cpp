@@ -107,6 +107,9 @@ struct Inst {
   int* d_sface = nullptr;       // specular faces: slot and face direction
   int* d_sface_dir = nullptr;
   int* d_dface_axis = nullptr;  // grid axis of each diffuse face
+  double* d_Qs = nullptr;       // heat source of the stored forward state
+  double dJds = 0.0;            // dJ/ds of the last adjoint (s: common factor on the cell sizes)
+  bool have_dJds = false;
   double* d_adj_scale = nullptr;  // [B][3] wall-value factor of the transposed sweeps
   void* d_ubf = nullptr;        // forward inflow table [B][rows][n_bface]
   void* d_ubf0 = nullptr;       // zeros (adjoint)
@@ -358,6 +361,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     I.d_part = pt;
     I.d_store = nullptr;
     I.stored = false;
+    I.have_dJds = false;
     HIPCHK(pp.alloc(&I.d_tgrad, (size_t)n_grp_inst * 2));
     // descriptors
     for (int adj = 0; adj < 2; ++adj) {
@@ -633,6 +637,7 @@ bte_status build_static(bte_ctx* h) {
     std::vector<int> dax(hi.dface.size());
     for (size_t i = 0; i < hi.dface.size(); ++i) dax[i] = hi.bf_face[hi.dface[i]] / 2;
     HIPCHK(pp.upload(&I.d_dface_axis, dax));
+    HIPCHK(pp.alloc(&I.d_Qs, hi.ncell));
     HIPCHK(pp.alloc(&I.d_adj_scale, (size_t)h->B * 3));
     const size_t nu = (size_t)h->B * h->ubf_rows * std::max<size_t>(hi.bf_cell.size(), 1);
     char* u1;
@@ -971,6 +976,7 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   HIPCHK(launch_ubf_init(h->precision, u, st));
   HIPCHK(launch_status_reset(h->d_st_f + k, (double)I.hi.n_active, st));
   I.stored = false;
+    I.have_dJds = false;
   return BTE_OK;
 }
 
@@ -1203,6 +1209,8 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
   if (o.store_state) {
     s = store_state(h, st);
     if (s != BTE_OK) return s;
+    if (d_Q) HIPCHK(hipMemcpyAsync(I.d_Qs, d_Q, (size_t)I.hi.ncell * 8, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(launch_zero(I.d_Qs, (size_t)I.hi.ncell * 8, st));
   }
   HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, h->T_ref, 1.0, d_T, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1239,6 +1247,11 @@ bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const
   if (o.store_state) {
     s = store_state(h, st);
     if (s != BTE_OK) return s;
+    for (size_t k = 0; k < h->inst.size(); ++k) {
+      Inst& I = h->inst[k];
+      if (d_Q[k]) HIPCHK(hipMemcpyAsync(I.d_Qs, d_Q[k], (size_t)I.hi.ncell * 8, hipMemcpyDeviceToDevice, st));
+      else HIPCHK(launch_zero(I.d_Qs, (size_t)I.hi.ncell * 8, st));
+    }
   }
   bte_status worst = BTE_OK;
   for (size_t k = 0; k < h->inst.size(); ++k) {
@@ -1344,16 +1357,30 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
     double L = 0.0;
     for (int c = 0; c < nc; ++c)
       if (I.hi.active[c]) L += lam[c] * dT[c];
+    std::vector<double> T1(h->B, 0.0), T2(h->B, 0.0);
+    for (int g = 0; g < I.n_grp; ++g) {
+      T1[I.grp_band[g]] += tg[2 * g];
+      T2[I.grp_band[g]] += tg[2 * g + 1];
+    }
     if (h_dJdtau) {
-      std::vector<double> T1(h->B, 0.0), T2(h->B, 0.0);
-      for (int g = 0; g < I.n_grp; ++g) {
-        T1[I.grp_band[g]] += tg[2 * g];
-        T2[I.grp_band[g]] += tg[2 * g + 1];
-      }
       for (int b = 0; b < h->B; ++b) {
         const double tb = h->tau[b];
         h_dJdtau[k * h->B + b] = (1.0 / tb) * ((h->t0 / tb) * T1[b] - T2[b] + h->C[b] / (tb * D) * L);
       }
+    }
+    // dJ/ds for a common factor s on every cell size: every beta_d scales as
+    // 1/s, and by the forward equation sum_d beta_d (u - u_up) equals
+    // rho' (dT - u) + gamma' Q, so dJ/ds = -sum_b rho'_b T1_b + sum_c Q_c dJ/dQ_c
+    {
+      std::vector<double> dq(nc), Qs(nc);
+      HIPCHK(hipMemcpy(dq.data(), h->fin_a[k].q, nc * 8, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(Qs.data(), I.d_Qs, nc * 8, hipMemcpyDeviceToHost));
+      double ds = 0.0;
+      for (int c = 0; c < nc; ++c)
+        if (I.hi.active[c]) ds += Qs[c] * dq[c];
+      for (int b = 0; b < h->B; ++b) ds -= (h->t0 / h->tau[b]) * T1[b];
+      I.dJds = ds;
+      I.have_dJds = true;
     }
     h->h_st[k] = sa[k];
     h->h_st[k].done = conv[k];
@@ -1380,6 +1407,21 @@ bte_status bte_batch_adjoint(bte_handle h, const double* const* d_dJdT, double* 
                              bte_report* h_reps) {
   ErrClear clear_on_exit;
   return adjoint_common(h, d_dJdT, h_dJdtau, d_dJdQ, opts, hip_stream, h_reps);
+}
+
+bte_status bte_adjoint_dscale(bte_handle h, double* h_dJds) {
+  ErrClear clear_on_exit;
+  if (!h || !h_dJds) {
+    set_err("null handle or output");
+    return BTE_ERR_INVALID;
+  }
+  for (auto& I : h->inst)
+    if (!I.have_dJds) {
+      set_err("bte_adjoint_dscale needs a previous bte_adjoint or bte_batch_adjoint");
+      return BTE_ERR_STATE;
+    }
+  for (size_t k = 0; k < h->inst.size(); ++k) h_dJds[k] = h->inst[k].dJds;
+  return BTE_OK;
 }
 
 bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double* h_ms, double* h_updates) {

@@ -230,3 +230,62 @@ def test_adjoint_vs_central_differences_finfet_mixed(hip_lib):
     probes = np.sort(rng.choice(act, 12, replace=False))
     target = 300.0 + rng.uniform(0.0, 1.0, size=12)
     _fd_check(hip_lib, p, probes, target, fd_tau=[0, 2], fd_Q=list(rng.choice(act[p.Q[act] > 0], 3, replace=False)))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: bi.film_1d(n_cells=12, L=24e-9, n_mu=6, Q=np.linspace(0, 1e18, 12)),
+    lambda: bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 1)),
+    lambda: bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)),
+    lambda: bi.random_box_3d(4, 3, 5, seed=5, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 1)),
+])
+def test_length_scale_gradient_matches_complex_step(hip_lib, make):
+    """dJ/ds for a common factor s on every cell size (L dJ/dL) against the
+    complex step on the cell sizes of the dense fixed point."""
+    p = make()
+    act = np.flatnonzero(p.mask)
+    probes = act[[1, 4, 7]]
+    T0 = dense.solve_dense(p)
+    target = T0[probes] + 0.02
+    s = hip_lib.Solver(p, precision="fp64")
+    T, _, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=1e-13, check_every=4, store_state=True)
+    g = torch.zeros(p.ncell, dtype=torch.float64, device="cuda")
+    g[torch.tensor(probes, device="cuda")] = 2.0 * (T[torch.tensor(probes, device="cuda")]
+                                                    - torch.tensor(target, device="cuda")) / probes.size
+    s.adjoint(g, tol=1e-13, check_every=4)
+    ds = s.adjoint_dscale()
+    s.close()
+    cs = dense.complex_step_dscale(p, lambda TT: ((TT[probes] - target) ** 2).mean())
+    assert abs(ds - cs) < 1e-8 * abs(cs)
+
+
+def test_film_thickness_inverse(hip_lib):
+    """Results, "1D inverse problem for system size": a gray silicon-like film
+    (200 cells, 32 directions, tau of Kn = 1 at 100 nm) observed at 20 evenly
+    spaced cells; starting from 50 nm, 25 steps of a normalised gradient descent
+    on log L with an exponentially decaying step recover the 100 nm film."""
+    n, L_true = 200, 100e-9
+    base = bi.film_1d(n_cells=n, L=L_true, Kn=1.0)
+    obs = torch.tensor(np.linspace(0, n - 1, 20).round().astype(int), device="cuda")
+    s = hip_lib.Solver(base, precision="fp64")
+    Q = torch.tensor(base.Q, device="cuda")
+
+    def run(L, grad):
+        s.close()
+        s.__init__(base.replace(h=(L / n,) * 3), precision="fp64")
+        T, _, _ = s.solve(Q, tol=1e-12, check_every=8, store_state=grad)
+        return T
+
+    T_obs = run(L_true, False)[obs].clone()
+    L0 = 50e-9
+    x, v = 0.0, 0.0
+    for k in range(25):
+        L = L0 * np.exp(x)
+        T = run(L, True)
+        g = torch.zeros(n, dtype=torch.float64, device="cuda")
+        g[obs] = 2.0 * (T[obs] - T_obs)
+        s.adjoint(g, tol=1e-12, check_every=8)
+        dJdx = s.adjoint_dscale()  # = L dJ/dL = dJ/d(log L)
+        v = 0.999 * v + 0.001 * dJdx * dJdx
+        x -= 0.25 * 0.85 ** k * dJdx / np.sqrt(v / (1 - 0.999 ** (k + 1)))
+    s.close()
+    assert abs(L0 * np.exp(x) / L_true - 1.0) < 0.01

@@ -95,3 +95,30 @@ def test_transpose_sweep_identity(a):
     lhs = u @ np.linalg.solve(A, v)
     rhs = np.linalg.solve(Ar, u) @ v
     assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: bi.film_1d(n_cells=12, L=24e-9, n_mu=6, Q=np.linspace(0, 1e18, 12)),
+    lambda: bi.random_box_2d(5, 4, seed=2, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 1)),
+    lambda: bi.random_box_2d(5, 4, seed=2, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)),
+])
+def test_length_scale_complex_step_matches_c_oracle_differences(make):
+    """The complex-step derivative of the dense fixed point with respect to a
+    common factor on every cell size against central differences of the C
+    oracle's converged solve with scaled cell sizes."""
+    p = make()
+    r = oracle.solve(p, tol=1e-14, max_iters=20000)
+    act = np.flatnonzero(p.mask)
+    probes = act[[1, 4, 7]]
+    target = r["T"][probes] + 0.02
+
+    def loss(T):
+        return ((T[probes] - target) ** 2).mean()
+
+    cs = dense.complex_step_dscale(p, loss)
+    eps = 1e-5
+    Jp = loss(oracle.solve(p.replace(h=tuple(hd * (1 + eps) for hd in p.h)), tol=1e-14, max_iters=20000)["T"])
+    Jm = loss(oracle.solve(p.replace(h=tuple(hd * (1 - eps) for hd in p.h)), tol=1e-14, max_iters=20000)["T"])
+    fd = (Jp - Jm) / (2 * eps)
+    assert abs(cs) > 0
+    assert abs(fd - cs) < 1e-6 * abs(cs)

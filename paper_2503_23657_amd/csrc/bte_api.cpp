@@ -489,7 +489,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   sa.lds_zring = (int)off;
   off += al(L3 ? 0 : (size_t)P * R * W_max * G * es);
   sa.lds_yring = (int)off;
-  off += al(L3 ? (size_t)P * 8 * W_max * G * es : 0);
+  off += al(L3 ? (size_t)P * (8 * W_max + 64) * G * es : 0);  // + one dummy entry per lane
   sa.lds_xb = (int)off;
   off += al(L3 ? (size_t)P * 72 * G * es : 0);
   sa.lds_cid = (int)off;
@@ -497,7 +497,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   sa.lds_in = (int)off;
   off += al((size_t)P * R * 2 * e_max * es);
   sa.lds_out = (int)off;
-  off += al((size_t)P * R * o_max * es);
+  off += al((size_t)P * R * (o_max + 64) * es);
   // the partial-sum staging goes last: its size depends on the number of
   // accumulator planes of the launched variant
   sa.lds_stage = (int)off;
@@ -723,9 +723,11 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   if (s != BTE_OK) return s;
   Plan pl;
   if (h->dim == 3) {
-    pl.G = h->has_specular ? 1 : 2;
+    // one ordinate per lane, eight waves of one octant per workgroup (fewer
+    // when the LDS of the shape does not fit)
+    pl.G = 1;
     pl.R = 1;
-    pl.P = 4;
+    pl.P = 8;
     pl.C = 8;
     pl.NR = 1;
   } else {
@@ -739,9 +741,8 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
     pl.C = kC2;
   }
   s = build_plan(h.get(), pl);
-  if (s != BTE_OK && h->dim == 3 && pl.C > 8) {
-    // boundary-rich geometries need shorter chunks for the inflow stream buffer
-    pl.C = 8;
+  while (s != BTE_OK && h->dim == 3 && pl.P > 1) {
+    pl.P /= 2;
     s = build_plan(h.get(), pl);
   }
   if (s != BTE_OK && h->dim < 3 && pl.P > 1) {

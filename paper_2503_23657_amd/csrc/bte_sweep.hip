@@ -113,21 +113,21 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 
   // LDS carve-up (byte offsets computed on the host)
   T* zring = reinterpret_cast<T*>(lds + A.lds_zring);  // 2D: [P][R][W_max][G]
-  T* yring = reinterpret_cast<T*>(lds + A.lds_yring);  // 3D: [P][LK][W_max][G]
-  T* xb = reinterpret_cast<T*>(lds + A.lds_xb);        // 3D: [P][72][G]
+  T* yring = reinterpret_cast<T*>(lds + A.lds_yring);  // 3D: [P][LK * W_max + 64][G] (64 dummy entries)
+  T* xb = reinterpret_cast<T*>(lds + A.lds_xb);        // 3D: [P][72][G] (entries 8.. hold lane - 8's value)
   T* stage = reinterpret_cast<T*>(lds + A.lds_stage);  // [P*R][NACC][C][65]
   int* scid = reinterpret_cast<int*>(lds + A.lds_cid); // [R][C][65]
   T* inb = reinterpret_cast<T*>(lds + A.lds_in);       // [P*R][2][e_max]
-  T* outb = reinterpret_cast<T*>(lds + A.lds_out);     // [P*R][o_max]
+  T* outb = reinterpret_cast<T*>(lds + A.lds_out);     // [P*R][o_max + 64] (64 dummy entries)
   const int W_max = A.W_max;
   T* my_zring = zring + (size_t)(p * R + r) * W_max * G;
   const T* prev_zring = zring + (size_t)(p * R + rprev) * W_max * G;
-  T* my_yring = yring + (size_t)p * LK * W_max * G;
+  T* my_yring = yring + (size_t)p * (LK * W_max + 64) * G;
   T* my_xb = xb + (size_t)p * 72 * G;
   T* my_stage = stage + (size_t)(p * R + r) * NACC * C * 65;
   int* my_scid = scid + (size_t)r * C * 65;
   T* my_inb = inb + (size_t)(p * R + r) * 2 * A.e_max;
-  T* my_outb = outb + (size_t)(p * R + r) * A.o_max;
+  T* my_outb = outb + (size_t)(p * R + r) * (A.o_max + 64);
   GAS T* my_zg = L3 ? gp(reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride) : nullptr;
 
   for (;;) {
@@ -187,6 +187,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
     const int zmask = L3 ? I.ring - 1 : 0;
     const int zlag = L3 ? I.lag : 0;
+    // buffer view of this wave's global z ring (I.ring steps x 8 lanes x G)
+    const rsrc_t ZGR = mkrsrc(my_zg, L3 ? (unsigned)(I.ring * LJ * G) * (unsigned)sizeof(T) : 0u);
 
     // ---- clear the exchange buffers; prefill the first strip's ghosts (2D)
     if (!L3) {
@@ -335,51 +337,43 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
             }
           } else {
             // j-neighbour (y): lane - 1 inside each 8-lane group; jl == 0 takes
-            // the previous J-block's value from the y-ring
-            T gh[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) gh[g] = T(0);
-            if (jl == 0) {
-#pragma unroll
-              for (int g = 0; g < G; ++g) gh[g] = my_yring[(kl * W_max + col) * G + g];
-            }
+            // the previous J-block's value from the y-ring (every lane reads its
+            // ring row, col being valid on every lane, and selects)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
+              const T gv = my_yring[(kl * W_max + col) * G + g];
               const T d = dpp_move<0x111>(T(0), f[g]);
-              yu[g] = jl == 0 ? gh[g] : d;
+              yu[g] = jl == 0 ? gv : d;
             }
-            // k-neighbour (z): entry lane of the exchange block; the ghost row
-            // (entries 0..7) holds the previous strip's values for kl == 0
-            if (kl == 0) {
+            // k-neighbour (z): lane - 8 through the exchange block; the entry
+            // row (kl == 0) takes the previous strip's value from its own
+            // prefetched ring register
 #pragma unroll
-              for (int g = 0; g < G; ++g) my_xb[jl * G + g] = zg[g];
+            for (int g = 0; g < G; ++g) {
+              const T xv = my_xb[lane * G + g];
+              zu[g] = kl == 0 ? zg[g] : xv;
             }
-#pragma unroll
-            for (int g = 0; g < G; ++g) zu[g] = my_xb[lane * G + g];
           }
 
           // ---- boundary inflows from the stream
           if (ballot64(fl & (F_IN_X | F_IN_Y | F_IN_Z)) != 0ull) {
             const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = L3 && (fl & F_IN_Z);
             const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = L3 ? ballot64(bz) : 0ull;
-            int k = in_cur + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
-            if (bx) {
-              const T uin = inbuf[k++];
+            // a lane's entries are consecutive (x, y, z); every lane reads three
+            // in-range entries and keeps those it owns
+            const int kx = in_cur + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const int ky = kx + (bx ? 1 : 0), kz = ky + (by ? 1 : 0);
+            const int kmax = A.e_max - 1;
+            const T ux = inbuf[min(kx, kmax)], uy = inbuf[min(ky, kmax)], uz = inbuf[min(kz, kmax)];
 #pragma unroll
-              for (int g = 0; g < G; ++g) xu[g] = uin * den[g];
-            }
-            if (by) {
-              const T uin = inbuf[k++];
-#pragma unroll
-              for (int g = 0; g < G; ++g) {
-                if (L3) yu[g] = uin * den[g];
-                else zu[g] = uin * den[g];
+            for (int g = 0; g < G; ++g) {
+              xu[g] = bx ? ux * den[g] : xu[g];
+              if (L3) {
+                yu[g] = by ? uy * den[g] : yu[g];
+                zu[g] = bz ? uz * den[g] : zu[g];
+              } else {
+                zu[g] = by ? uy * den[g] : zu[g];
               }
-            }
-            if (L3 && bz) {
-              const T uin = inbuf[k++];
-#pragma unroll
-              for (int g = 0; g < G; ++g) zu[g] = uin * den[g];
             }
             in_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
@@ -403,13 +397,19 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           if (L3) {
 #pragma unroll
             for (int g = 0; g < G; ++g) my_xb[(lane + 8) * G + g] = f[g];
-            if (jl == LJ - 1 && cid >= 0) {
+            {
+              // the last lane of each 8-lane group publishes its value to the
+              // y-ring; the others write a dummy entry of their own
+              const int ye = (jl == LJ - 1 && cid >= 0) ? kl * W_max + col : LK * W_max + lane;
 #pragma unroll
-              for (int g = 0; g < G; ++g) my_yring[(kl * W_max + col) * G + g] = f[g];
+              for (int g = 0; g < G; ++g) my_yring[ye * G + g] = f[g];
             }
-            if (kl == LK - 1) {
+            {
+              // the top row of the block publishes to the global z ring; the
+              // other lanes' stores fall outside the buffer view
+              const int zo = kl == LK - 1 ? (((tau & zmask) * LJ + jl) * G) * (int)sizeof(T) : (int)kOOB;
 #pragma unroll
-              for (int g = 0; g < G; ++g) my_zg[(size_t)((tau & zmask) * LJ + jl) * G + g] = f[g];
+              for (int g = 0; g < G; ++g) bst(f[g], ZGR, kl == LK - 1 ? zo + g * (int)sizeof(T) : (int)kOOB);
             }
           } else {
             if (lane == 63 && cid >= 0) {
@@ -422,26 +422,21 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           if (ballot64(fl & (F_OUT_X | F_OUT_Y | F_OUT_Z)) != 0ull) {
             const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = L3 && (fl & F_OUT_Z);
             const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = L3 ? ballot64(oz) : 0ull;
-            int k = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const int kx = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const int ky = kx + (ox ? 1 : 0), kz = ky + (oy ? 1 : 0);
             const CAS T* wo = gt + go_wo(G, 0);
-            if (ox) {
-              T v = T(0);
+            T vx = T(0), vy = T(0), vz = T(0);
 #pragma unroll
-              for (int g = 0; g < G; ++g) v = fma(wo[g], f[g], v);
-              my_outb[k++] = v;
+            for (int g = 0; g < G; ++g) {
+              vx = fma(wo[g], f[g], vx);
+              vy = fma(wo[G + g], f[g], vy);
+              if (L3) vz = fma(wo[2 * G + g], f[g], vz);
             }
-            if (oy) {
-              T v = T(0);
-#pragma unroll
-              for (int g = 0; g < G; ++g) v = fma(wo[G + g], f[g], v);
-              my_outb[k++] = v;
-            }
-            if (L3 && oz) {
-              T v = T(0);
-#pragma unroll
-              for (int g = 0; g < G; ++g) v = fma(wo[2 * G + g], f[g], v);
-              my_outb[k++] = v;
-            }
+            // entries a lane does not own go to its dummy slot
+            const int dmy = A.o_max + lane;
+            my_outb[ox ? kx : dmy] = vx;
+            my_outb[oy ? ky : dmy] = vy;
+            if (L3) my_outb[oz ? kz : dmy] = vz;
             out_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
 

@@ -8,23 +8,23 @@
 // and Eq. 4 (heat flux) are accumulated, plus the outgoing partial currents of
 // the diffuse walls (Eq. 6).
 //
-// Work decomposition (see bte_device.h for the terms):
-//   * a lane owns one cell of the (j, k) cross-section and sweeps it along i;
-//     its G register slots hold G ordinates of one band and one octant;
-//   * the upwind neighbour in i is the lane's own previous value; the neighbour
-//     in j or k is a neighbouring lane's previous value, moved with a DPP lane
-//     shift (wave_shr:1 for k in 2D, row_shr:1 for j in 3D) or, for k in 3D,
-//     through a per-wave LDS exchange block with a ghost row;
-//   * 2D: the R waves of a workgroup pipeline successive 64-row strips, the top
-//     row of one strip reaching the next wave through an LDS ring, with one
-//     workgroup barrier every C steps;
-//     3D: one wave streams all 8x8 pencil blocks; the j-link between blocks goes
+// Work decomposition, 3D problems (1D/2D ones have their own rows-per-lane
+// kernel; see bte_device.h for the terms):
+//   * the 64 lanes of a wave own an 8 x 8 block of the (j, k) cross-section and
+//     sweep it along i, skewed by j + k; a lane's G register slots hold G
+//     ordinates of one band and one octant;
+//   * the upwind neighbour in i is the lane's own previous value; the one in j
+//     is lane - 1 of its 8-lane group, moved with DPP row_shr:1; the one in k is
+//     lane - 8, through a per-wave LDS exchange block;
+//   * one wave streams all pencil blocks; the j-link between blocks goes
 //     through an LDS ring, the k-link between strips through a global ring whose
 //     values are prefetched D steps ahead;
 //   * every per-step input comes from the precomputed skewed schedule, so each
 //     wave reads 64 contiguous entries per step, prefetched D steps ahead;
 //   * boundary inflows are consumed as an ordered stream per wave, staged into
-//     LDS one chunk ahead, so no lane waits on a dependent load;
+//     LDS one chunk ahead, so no lane waits on a dependent load; no step has a
+//     lane-divergent branch (unowned entries are read in range and discarded,
+//     unowned writes go to dummy entries or past the buffer view);
 //   * per-cell partial sums of the P waves of a workgroup are staged in LDS,
 //     added, and written back as contiguous row segments.
 #include <hip/hip_runtime.h>
@@ -89,14 +89,15 @@ static_assert(kD <= kPad2, "the schedule padding must cover the prefetch distanc
 constexpr int kEPL = 4;  // in-stream entries per lane per chunk (e_max <= 256)
 
 // ============================================================================
-// L3 = false: 1D/2D layout (LJ = 1, LK = 64, k = y), R strip waves per slot;
-// L3 = true : 3D layout (LJ = 8, LK = 8, j = y, k = z), R = 1.
+// 3D layout (LJ = 8, LK = 8, j = y, k = z), R = 1; 1D/2D problems have a
+// kernel of their own (bte_sweep2d.hip). L3 is always true.
 // ============================================================================
 template <typename T, int G, int NACC, int MODE, bool L3>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
+  static_assert(L3, "the pencil-block kernel sweeps 3D problems only");
   using T2 = typename V2<T>::t;
-  constexpr int LJ = L3 ? 8 : 1;
-  constexpr int LK = L3 ? 8 : 64;
+  constexpr int LJ = 8;
+  constexpr int LK = 8;
   constexpr int GS = grp_stride(G);
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_job;
@@ -107,12 +108,10 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
   const int R = A.R, P = A.P, C = A.C;
   const int r = wave % R;
   const int p = wave / R;
-  const int rprev = (r + R - 1) % R;
-  const int jl = L3 ? (lane & 7) : 0;
-  const int kl = L3 ? (lane >> 3) : lane;
+  const int jl = lane & 7;
+  const int kl = lane >> 3;
 
   // LDS carve-up (byte offsets computed on the host)
-  T* zring = reinterpret_cast<T*>(lds + A.lds_zring);  // 2D: [P][R][W_max][G]
   T* yring = reinterpret_cast<T*>(lds + A.lds_yring);  // 3D: [P][LK * W_max + 64][G] (64 dummy entries)
   T* xb = reinterpret_cast<T*>(lds + A.lds_xb);        // 3D: [P][72][G] (entries 8.. hold lane - 8's value)
   T* stage = reinterpret_cast<T*>(lds + A.lds_stage);  // [P*R][NACC][C][65]
@@ -120,15 +119,13 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
   T* inb = reinterpret_cast<T*>(lds + A.lds_in);       // [P*R][2][e_max]
   T* outb = reinterpret_cast<T*>(lds + A.lds_out);     // [P*R][o_max + 64] (64 dummy entries)
   const int W_max = A.W_max;
-  T* my_zring = zring + (size_t)(p * R + r) * W_max * G;
-  const T* prev_zring = zring + (size_t)(p * R + rprev) * W_max * G;
   T* my_yring = yring + (size_t)p * (LK * W_max + 64) * G;
   T* my_xb = xb + (size_t)p * 72 * G;
   T* my_stage = stage + (size_t)(p * R + r) * NACC * C * 65;
   int* my_scid = scid + (size_t)r * C * 65;
   T* my_inb = inb + (size_t)(p * R + r) * 2 * A.e_max;
   T* my_outb = outb + (size_t)(p * R + r) * (A.o_max + 64);
-  GAS T* my_zg = L3 ? gp(reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride) : nullptr;
+  GAS T* my_zg = gp(reinterpret_cast<T*>(A.zg) + ((size_t)blockIdx.x * P + p) * A.zg_stride);
 
   for (;;) {
     __syncthreads();
@@ -185,30 +182,15 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     rsrc_t PRS[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
-    const int zmask = L3 ? I.ring - 1 : 0;
-    const int zlag = L3 ? I.lag : 0;
+    const int zmask = I.ring - 1;
+    const int zlag = I.lag;
     // buffer view of this wave's global z ring (I.ring steps x 8 lanes x G)
-    const rsrc_t ZGR = mkrsrc(my_zg, L3 ? (unsigned)(I.ring * LJ * G) * (unsigned)sizeof(T) : 0u);
+    const rsrc_t ZGR = mkrsrc(my_zg, (unsigned)(I.ring * LJ * G) * (unsigned)sizeof(T));
 
-    // ---- clear the exchange buffers; prefill the first strip's ghosts (2D)
-    if (!L3) {
-      for (int e = lane; e < W_max * G; e += 64) my_zring[e] = T(0);
-    } else if (r == 0) {
-      for (int e = lane; e < LK * W_max * G; e += 64) my_yring[e] = T(0);
-      for (int e = lane; e < 72 * G; e += 64) my_xb[e] = T(0);
-    }
+    // ---- clear the exchange buffers
+    for (int e = lane; e < LK * W_max * G; e += 64) my_yring[e] = T(0);
+    for (int e = lane; e < 72 * G; e += 64) my_xb[e] = T(0);
     __syncthreads();
-    if (!L3 && r == 0) {
-      // strip 0, lane 0 reads the ring of "strip -1" = slot R-1, indexed by column
-      T* zr = zring + (size_t)(p * R + (R - 1)) * W_max * G;
-      const GAS int* pre = gp(I.pre_slot + (size_t)o * I.W);
-      for (int c = lane; c < I.W; c += 64) {
-        const int sl = pre[c];
-        const T u = sl >= 0 ? UBF[sl] : T(0);
-#pragma unroll
-        for (int g = 0; g < G; ++g) zr[c * G + g] = u * den[g];
-      }
-    }
 
     // ---- inflow stream pipeline: slots of chunk k+1 wait in registers, the
     //      values of chunk k sit in LDS buffer (k & 1)
@@ -247,13 +229,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
       rcf[u] = ld2(SCH + u * 64 + lane);
       rxq[u] = ld2(XQ + u * 64 + lane);
       if (MODE == M_TAUGRAD) rxf[u] = ld2(XF + u * 64 + lane);
-      if (L3) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) rzg[u][g] = T(0);
-        if (kl == 0 && u >= zlag) {
+      for (int g = 0; g < G; ++g) rzg[u][g] = T(0);
+      if (kl == 0 && u >= zlag) {
 #pragma unroll
-          for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((u - zlag) & zmask) * LJ + jl) * G + g];
-        }
+        for (int g = 0; g < G; ++g) rzg[u][g] = my_zg[(size_t)(((u - zlag) & zmask) * LJ + jl) * G + g];
       }
     }
 
@@ -288,24 +268,20 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           T2 xf;
           if (MODE == M_TAUGRAD) xf = rxf[u];
           T zg[G];
-          if (L3) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) zg[g] = rzg[u][g];
-          }
+          for (int g = 0; g < G; ++g) zg[g] = rzg[u][g];
           {
             const int tn = tau + kD;
             rcf[u] = ld2(SCH + tn * 64 + lane);
             rxq[u] = ld2(XQ + tn * 64 + lane);
             if (MODE == M_TAUGRAD) rxf[u] = ld2(XF + tn * 64 + lane);
-            if (L3) {
-              // every lane loads (the ring index wraps in bounds); the z-entry
-              // lanes keep the value once the ring holds data
-              const bool zk = kl == 0 && tn >= zlag;
+            // every lane loads (the ring index wraps in bounds); the z-entry
+            // lanes keep the value once the ring holds data
+            const bool zk = kl == 0 && tn >= zlag;
 #pragma unroll
-              for (int g = 0; g < G; ++g) {
-                const T zv = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
-                rzg[u][g] = zk ? zv : T(0);
-              }
+            for (int g = 0; g < G; ++g) {
+              const T zv = my_zg[(size_t)(((tn - zlag) & zmask) * LJ + jl) * G + g];
+              rzg[u][g] = zk ? zv : T(0);
             }
           }
           const int cid = cf.x;
@@ -321,21 +297,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           T xu[G], yu[G], zu[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) xu[g] = f[g];
-          if (!L3) {
-            // k-neighbour (y): lane - 1; lane 0 takes the previous strip's value
-            T gh[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) gh[g] = T(0);
-            if (lane == 0) {
-#pragma unroll
-              for (int g = 0; g < G; ++g) gh[g] = prev_zring[col * G + g];
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-              zu[g] = dpp_move<0x138>(gh[g], f[g]);
-              yu[g] = T(0);
-            }
-          } else {
+          {
             // j-neighbour (y): lane - 1 inside each 8-lane group; jl == 0 takes
             // the previous J-block's value from the y-ring (every lane reads its
             // ring row, col being valid on every lane, and selects)
@@ -357,23 +319,19 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 
           // ---- boundary inflows from the stream
           if (ballot64(fl & (F_IN_X | F_IN_Y | F_IN_Z)) != 0ull) {
-            const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = L3 && (fl & F_IN_Z);
-            const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = L3 ? ballot64(bz) : 0ull;
+            const bool bx = fl & F_IN_X, by = fl & F_IN_Y, bz = fl & F_IN_Z;
+            const unsigned long long mx = ballot64(bx), my = ballot64(by), mz = ballot64(bz);
             // a lane's entries are consecutive (x, y, z); every lane reads three
             // in-range entries and keeps those it owns
-            const int kx = in_cur + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const int kx = in_cur + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
             const int ky = kx + (bx ? 1 : 0), kz = ky + (by ? 1 : 0);
             const int kmax = A.e_max - 1;
             const T ux = inbuf[min(kx, kmax)], uy = inbuf[min(ky, kmax)], uz = inbuf[min(kz, kmax)];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               xu[g] = bx ? ux * den[g] : xu[g];
-              if (L3) {
-                yu[g] = by ? uy * den[g] : yu[g];
-                zu[g] = bz ? uz * den[g] : zu[g];
-              } else {
-                zu[g] = by ? uy * den[g] : zu[g];
-              }
+              yu[g] = by ? uy * den[g] : yu[g];
+              zu[g] = bz ? uz * den[g] : zu[g];
             }
             in_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
@@ -384,9 +342,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           for (int a = 0; a < NACC; ++a) acc[a] = T(0);
 #pragma unroll
           for (int g = 0; g < G; ++g) {
-            T fn;
-            if (L3) fn = fma(a2[g], zu[g], fma(a1[g], yu[g], fma(a0[g], xu[g], S)));
-            else fn = fma(a1[g], zu[g], fma(a0[g], xu[g], S));
+            const T fn = fma(a2[g], zu[g], fma(a1[g], yu[g], fma(a0[g], xu[g], S)));
             f[g] = fn;
 #pragma unroll
             for (int a = 0; a < NACC; ++a) acc[a] = fma(wacc[a][g], fn, acc[a]);
@@ -394,7 +350,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 
           // ---- exchange writes for the downstream neighbours
           __builtin_amdgcn_wave_barrier();
-          if (L3) {
+          {
 #pragma unroll
             for (int g = 0; g < G; ++g) my_xb[(lane + 8) * G + g] = f[g];
             {
@@ -411,18 +367,13 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
 #pragma unroll
               for (int g = 0; g < G; ++g) bst(f[g], ZGR, kl == LK - 1 ? zo + g * (int)sizeof(T) : (int)kOOB);
             }
-          } else {
-            if (lane == 63 && cid >= 0) {
-#pragma unroll
-              for (int g = 0; g < G; ++g) my_zring[col * G + g] = f[g];
-            }
           }
 
           // ---- diffuse-wall outflow stream
           if (ballot64(fl & (F_OUT_X | F_OUT_Y | F_OUT_Z)) != 0ull) {
-            const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = L3 && (fl & F_OUT_Z);
-            const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = L3 ? ballot64(oz) : 0ull;
-            const int kx = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + (L3 ? lanes_below(mz) : 0);
+            const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = fl & F_OUT_Z;
+            const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = ballot64(oz);
+            const int kx = out_cur - out_chunk0 + lanes_below(mx) + lanes_below(my) + lanes_below(mz);
             const int ky = kx + (ox ? 1 : 0), kz = ky + (oy ? 1 : 0);
             const CAS T* wo = gt + go_wo(G, 0);
             T vx = T(0), vy = T(0), vz = T(0);
@@ -430,13 +381,13 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
             for (int g = 0; g < G; ++g) {
               vx = fma(wo[g], f[g], vx);
               vy = fma(wo[G + g], f[g], vy);
-              if (L3) vz = fma(wo[2 * G + g], f[g], vz);
+              vz = fma(wo[2 * G + g], f[g], vz);
             }
             // entries a lane does not own go to its dummy slot
             const int dmy = A.o_max + lane;
             my_outb[ox ? kx : dmy] = vx;
             my_outb[oy ? ky : dmy] = vy;
-            if (L3) my_outb[oz ? kz : dmy] = vz;
+            my_outb[oz ? kz : dmy] = vz;
             out_cur += __popcll(mx) + __popcll(my) + __popcll(mz);
           }
 

@@ -126,7 +126,8 @@ def main():
         solver.set_plan(G=G_, R=R_, P=P_, NR=NR_)
         plan = solver.plan()
     else:
-        plan = solver.autotune(Q, n_iters=5)
+        # whole iterations, the flux carried by the last two as in a long solve
+        plan = solver.autotune(Q, n_iters=30)
     log("plan", plan)
     K = max(8, args.steps)
     # warm-up (also captures the graphs)

@@ -148,9 +148,15 @@ def main():
     flop = n_upd * flops_per_update(2, False)
     achieved_tf = flop / (sweep_ms * 1e-3) / 1e12
     kname = f"sweep2d_kernel<float, {plan['G']}, {plan['NR']}, {plan['P']}, 1, 0>"
+    traffic = profiled_traffic(kname)
     roofline = dict(bound="alu", achieved=achieved_tf, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved_tf / FP32_VALU_PEAK_TFLOPS, traffic=profiled_traffic(kname),
+                    frac=achieved_tf / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
                     kernel=kname, kernel_ms=sweep_ms, sweep_updates_per_s=n_upd / (sweep_ms * 1e-3))
+    if traffic is not None:
+        # the measured HBM bytes of one launch over its event-timed duration,
+        # against the published HBM peak
+        gbs = traffic / (sweep_ms * 1e-3) / 1e9
+        roofline.update(hbm_gbs=gbs, hbm_peak_gbs=HBM_PEAK_GBS, hbm_frac=gbs / HBM_PEAK_GBS)
 
     extra = {}
     if not args.no_extra:

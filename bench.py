@@ -35,18 +35,24 @@ def flops_per_update(dim: int, with_q: bool) -> float:
     return 2.0 * (dim + 1 + (dim if with_q else 0))
 
 
-def cpu_baseline(p, iters: int, m_swept: int):
+def cpu_baseline(p, iters: int, m_swept: int, iters_single: int = 2):
     """The FP64 oracle timed on the host over a bounded number of iterations,
-    as a rate in the metric's own counting (swept projections per band)."""
+    as a rate in the metric's own counting (swept projections per band), on
+    all host threads and, over fewer iterations, on one thread."""
     import oracle
     threads = oracle.num_threads()
+    upd = p.n_active * m_swept * p.B
     t0 = time.perf_counter()
     oracle.solve(p, tol=0.0, max_iters=iters, threads=threads)
     dt = time.perf_counter() - t0
-    upd = p.n_active * m_swept * p.B * iters
-    return dict(value=upd / dt, unit="updates/s", cores=threads, kind="oracle",
+    t0 = time.perf_counter()
+    oracle.solve(p, tol=0.0, max_iters=iters_single, threads=1)
+    dt1 = time.perf_counter() - t0
+    return dict(value=upd * iters / dt, unit="updates/s", cores=threads, kind="oracle",
                 sample=f"{iters} source iterations of the full 256x256 problem in FP64 ({dt:.1f} s; the oracle "
-                       f"sweeps all {p.M} directions, counted as the {m_swept} swept projections per band)")
+                       f"sweeps all {p.M} directions, counted as the {m_swept} swept projections per band)",
+                single_thread=dict(value=upd * iters_single / dt1, unit="updates/s", cores=1,
+                                   sample=f"{iters_single} source iterations, same problem ({dt1:.1f} s)"))
 
 
 SWEEP_SOURCES = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_kutil.h")

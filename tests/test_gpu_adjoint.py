@@ -136,6 +136,16 @@ def test_adjoint_requires_stored_state(hip_lib):
     with pytest.raises(hip_lib.BTEError) as ei:
         s.adjoint(torch.zeros(p.ncell, dtype=torch.float64, device="cuda"))
     assert ei.value.status == hip_lib.BTE_ERR_STATE
+    # the length-scale gradient needs an adjoint since the last solve
+    with pytest.raises(hip_lib.BTEError) as ei:
+        s.adjoint_dscale()
+    assert ei.value.status == hip_lib.BTE_ERR_STATE
+    s.solve(Q, tol=1e-10, store_state=True)
+    s.adjoint(torch.zeros(p.ncell, dtype=torch.float64, device="cuda"), tol=1e-10)
+    assert s.adjoint_dscale() == 0.0  # zero objective gradient
+    s.solve(Q, tol=1e-10)
+    with pytest.raises(hip_lib.BTEError):
+        s.adjoint_dscale()
     s.close()
 
 

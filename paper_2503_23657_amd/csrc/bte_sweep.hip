@@ -299,11 +299,14 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           for (int g = 0; g < G; ++g) xu[g] = f[g];
           {
             // j-neighbour (y): lane - 1 inside each 8-lane group; jl == 0 takes
-            // the previous J-block's value from the y-ring (every lane reads its
-            // ring row, col being valid on every lane, and selects)
+            // the previous J-block's value from the y-ring. The other lanes read
+            // their own dummy entry instead: the columns of a step repeat along
+            // the block's anti-diagonals, so their ring reads would fall on few
+            // LDS banks
+            const int yr = jl == 0 ? kl * W_max + col : LK * W_max + lane;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-              const T gv = my_yring[(kl * W_max + col) * G + g];
+              const T gv = my_yring[yr * G + g];
               const T d = dpp_move<0x111>(T(0), f[g]);
               yu[g] = jl == 0 ? gv : d;
             }

@@ -102,6 +102,9 @@ def main():
                     help="fixed kernel plan 'G,R,P,NR' instead of the autotuned one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (calibrates the HBM byte counters)")
+    ap.add_argument("--sweep3d", choices=("finfet", "finfet_mixed"), default=None,
+                    help="only time the 3D sweep on the full FinFET-like domain (diffuse walls, or the paper's "
+                         "specular/diffuse/isothermal mix) and print one JSON line; not the benchmark metric")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -111,6 +114,20 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 4, "copies": 3}))
+        return
+    if args.sweep3d:
+        import torch
+
+        import bte_inputs as bi
+        import paper_2503_23657_amd as bte
+        p = bi.finfet_3d(scale=1) if args.sweep3d == "finfet" else bi.finfet_3d_mixed(scale=1)
+        solver = bte.Solver(p, precision="fp32")
+        Q = torch.tensor(p.Q, dtype=torch.float64, device="cuda")
+        solver.solve(Q, tol=0.0, max_iters=2, check_every=2)
+        ms, upd = solver.time_sweep(n_launches=max(1, args.steps // 60))
+        print(json.dumps({"workload": f"3D {args.sweep3d} 96x96x120 ({p.n_active} cells), 15 bands, 128 directions",
+                          "plan": solver.plan(), "sweep_ms": ms, "updates_per_s": upd / (ms * 1e-3),
+                          "dtype": "f32"}))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)

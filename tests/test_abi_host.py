@@ -55,7 +55,8 @@ def _bad_cases():
     yield "reflection", p.replace(s=p.s[keep], w=w2)
     yield "empty mask", p.replace(mask=np.zeros_like(p.mask))
     yield "adiabatic only", p.replace(bc_kind=np.array([1], dtype=np.int32))
-    yield "specular", p.replace(bc_kind=np.array([2], dtype=np.int32))
+    yield "specular only", p.replace(bc_kind=np.array([2], dtype=np.int32))
+    yield "bc kind", p.replace(bc_kind=np.array([3], dtype=np.int32))
     fb = p.face_bc.copy()
     fb[fb == 0] = 7
     yield "bc id range", p.replace(face_bc=fb)
@@ -74,7 +75,8 @@ def test_validation_rejects(name, p):
 def test_validation_accepts_workloads():
     import paper_2503_23657_amd as bte
     for p in (bi.film_1d(), bi.square_2d(16), bi.finfet_3d(scale=8, n_bands=2),
-              bi.random_box_2d(9, 7, seed=0), bi.random_box_3d(5, 4, 6, seed=0)):
+              bi.random_box_2d(9, 7, seed=0), bi.random_box_3d(5, 4, 6, seed=0),
+              bi.random_box_2d(9, 7, seed=0, kinds=(0, 2)), bi.finfet_3d_mixed(scale=8, n_bands=2)):
         bte.validate(p)
 
 

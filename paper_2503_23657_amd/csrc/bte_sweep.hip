@@ -5,8 +5,8 @@
 // direction) pair the first-order upwind system A e = b (Eqs. Axb, A_matrix with
 // first-order faces) is solved exactly by one pass in upwind order, and in the
 // same pass the band/direction sums of Eq. updatee0_t (new lattice temperature)
-// and Eq. 4 (heat flux) are accumulated, plus the outgoing partial currents of
-// the diffuse walls (Eq. 6).
+// and Eq. 4 (heat flux) are accumulated, plus the outgoing values at the
+// reflecting walls (diffuse, Eq. 6, and specular, Eq. 7).
 //
 // Work decomposition, 3D problems (1D/2D ones have their own rows-per-lane
 // kernel; see bte_device.h for the terms):
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
             }
           }
 
-          // ---- diffuse-wall outflow stream
+          // ---- reflecting-wall outflow stream
           if (ballot64(fl & (F_OUT_X | F_OUT_Y | F_OUT_Z)) != 0ull) {
             const bool ox = fl & F_OUT_X, oy = fl & F_OUT_Y, oz = fl & F_OUT_Z;
             const unsigned long long mx = ballot64(ox), my = ballot64(oy), mz = ballot64(oz);

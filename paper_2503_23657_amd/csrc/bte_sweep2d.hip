@@ -5,8 +5,8 @@
 // direction) pair the first-order upwind system A e = b (Eqs. Axb, A_matrix with
 // first-order faces) is solved exactly by one pass in upwind order, and in the
 // same pass the band/direction sums of Eq. updatee0_t (new lattice temperature)
-// and Eq. 4 (heat flux) are accumulated, plus the outgoing partial currents of
-// the diffuse walls (Eq. 6).
+// and Eq. 4 (heat flux) are accumulated, plus the outgoing values at the
+// reflecting walls (diffuse, Eq. 6, and specular, Eq. 7).
 //
 // Work decomposition:
 //   * lane l of a wave owns NR consecutive rows (64*NR rows per strip) and
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
 
     // ---- one chunk of kC2 steps; IN: 0 no flagged inflow entries in the
     //      chunk, 1 x-inflows and row-0 y-inflows only (folded into the chain
-    //      inputs), 2 any inflow (its own chain with selects); OUT: diffuse-wall
+    //      inputs), 2 any inflow (its own chain with selects); OUT: reflecting-wall
     //      outflow entries present; XS: lanes entering their strip at the x wall
     //      (F2_XSTART), whose x-inflows are read from LDS a step ahead
     auto chunk = [&](auto in_tag, auto out_tag, auto xs_tag, const int ch) {
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           }
         }
 
-        // ---- diffuse-wall outflow stream: rows, then axes, then lanes
+        // ---- reflecting-wall outflow stream: rows, then axes, then lanes
         constexpr unsigned kOutAll = rowmask(F2_OUTX | F2_OUTY, NR);
         if (OUT && __ballot(fl & kOutAll) != 0ull) {
 #pragma unroll

@@ -322,3 +322,45 @@ def test_adjoint_fp32_sweeps_match_fp64(hip_lib, kinds):
     d32, q32, _, _, r32 = _gpu_grads(hip_lib, p, loss_t, precision="fp32", tol=1e-7, max_iters=20000)
     assert np.abs(d32 - d64).max() < 1e-3 * np.abs(d64).max()
     assert np.abs(q32 - q64).max() < 1e-3 * np.abs(q64).max()
+
+
+def test_heat_source_inverse_with_specular_walls(hip_lib):
+    """Results, "2D inverse problem for heat source intensity": a 100 nm square
+    (32 x 32 cells, 15 bands) with an isothermal 300 K bottom and specular walls
+    elsewhere, heated in a 10 nm x 20 nm box near the top; the temperatures of 20
+    evenly spaced bottom-row cells recover the box's intensity (1e19 W/m^3) from
+    half of it with dJ/dQ summed over the box, in 25 normalised gradient steps
+    with an exponentially decaying step."""
+    n, L = 32, 100e-9
+    h = L / n
+    mask = np.ones(n * n, dtype=np.uint8)
+    fbc = bi.face_bc_from_mask((n, n, 1), 2, mask, lambda i, j, k, f: 0 if (f == 2 and j == 0) else 1)
+    v, tau, C = bi.band_table_synthetic(15)
+    s_, w_ = bi.quad_octant_gl(2, 2, polar_axis=2)
+    X, Y = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h, indexing="xy")
+    box = ((np.abs(X - 0.5 * L) <= 5e-9) & (Y >= L - 25e-9) & (Y <= L - 5e-9)).reshape(-1)
+    assert box.sum() > 0
+    p = bi.Problem("source_inverse", 2, (n, n, 1), (h, h, h), mask, fbc,
+                   np.array([bi.BC_ISOTHERMAL, bi.BC_SPECULAR], dtype=np.int32), np.array([300.0, 300.0]),
+                   v, tau, C, s_, w_, 1e19 * box.astype(np.float64), 300.0)
+    obs = torch.tensor(np.linspace(0, n - 1, 20).round().astype(int), device="cuda")  # bottom row j = 0
+    boxt = torch.tensor(box, device="cuda")
+    s = hip_lib.Solver(p, precision="fp64")
+
+    def solve(I, grad):
+        T, _, _ = s.solve(torch.tensor(I * box.astype(np.float64), device="cuda"), tol=1e-12, check_every=8,
+                          store_state=grad)
+        return T
+
+    T_obs = solve(1e19, False)[obs].clone()
+    x, vv = 0.5, 0.0  # intensity in units of 1e19 W/m^3
+    for k in range(25):
+        T = solve(x * 1e19, True)
+        g = torch.zeros(p.ncell, dtype=torch.float64, device="cuda")
+        g[obs] = 2.0 * (T[obs] - T_obs)
+        _, dQ, _ = s.adjoint(g, tol=1e-12, check_every=8)
+        dJdx = float(dQ[boxt].sum()) * 1e19
+        vv = 0.999 * vv + 0.001 * dJdx * dJdx
+        x -= 0.25 * 0.85 ** k * dJdx / np.sqrt(vv / (1 - 0.999 ** (k + 1)))
+    s.close()
+    assert abs(x - 1.0) < 0.01

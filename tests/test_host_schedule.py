@@ -119,14 +119,17 @@ def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
     assert np.abs(dQ - gq).max() < 1e-10 * np.abs(gq).max()
 
 
-@pytest.mark.parametrize("kind,plan", [(1, (2, 1, 1, 8, 1)), (1, (1, 1, 2, 8, 2)), (2, (1, 1, 1, 8, 1)),
-                                       (2, (1, 2, 1, 8, 1))])
-def test_emulated_adjoint_with_walls_matches_dense(emu, tmp_path, kind, plan):
+@pytest.mark.parametrize("dim,kind,plan", [(2, 1, (2, 1, 1, 8, 1)), (2, 1, (1, 1, 2, 8, 2)), (2, 2, (1, 1, 1, 8, 1)),
+                                           (2, 2, (1, 2, 1, 8, 1)), (3, 1, (2, 1, 2, 8, 1)), (3, 2, (1, 1, 2, 8, 1))])
+def test_emulated_adjoint_with_walls_matches_dense(emu, tmp_path, dim, kind, plan):
     """Transposed sweeps with the wall-value adjoint (the transpose of the
     lagged diffuse or specular reflection) against complex-step derivatives of
     the dense discrete fixed point."""
     from oracle import dense
-    p = bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
+    if dim == 2:
+        p = bi.random_box_2d(7, 6, seed=3, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
+    else:
+        p = bi.random_box_3d(4, 3, 5, seed=5, n_bands=2, n_theta=1, n_phi=1, kinds=(0, kind))
     iters = 1500
     probes = np.flatnonzero(p.mask)[[2, 9, 17, 23]]
     T0 = dense.solve_dense(p)

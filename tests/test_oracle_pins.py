@@ -443,3 +443,18 @@ def test_specular_needs_mirror_directions():
     rot = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
     with pytest.raises(ValueError):
         oracle.solve(p.replace(s=p.s @ rot.T), tol=0.0, max_iters=2)
+
+
+# ------------------------------------------------ P14 stored oracle values
+def test_film_matches_stored_values():
+    """The oracle's converged film profile against the values stored by
+    tests/golden/make_golden.py: a change to the oracle's arithmetic shows up
+    here and has to be justified by the passage it follows."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "film_1d_kn1.txt")
+    stored = np.loadtxt(path, comments="#")
+    r = oracle.solve(bi.film_1d(), tol=1e-12, max_iters=100000)
+    assert stored.shape == r["T"].shape
+    assert np.abs(r["T"] - stored).max() < 1e-12
+    # the profile is antisymmetric about 300 K and has temperature jumps at the walls
+    assert abs(stored[0] - 301.0) > 0.1 and abs(stored[-1] - 299.0) > 0.1

@@ -495,3 +495,115 @@ def test_film_matches_gray_slab_integral_equation():
         err[(n, n_mu)] = (np.abs(d).max(), np.sqrt(np.mean(d * d)))
     assert err[(200, 32)][0] < 1e-3
     assert err[(400, 64)][1] < 0.6 * err[(200, 64)][1]
+
+
+# ------------------------------------------ P16 heat flux along y and z (Eq. 4)
+def _film_along(axis_perm, n_cells, v, tau, C, s, w, Qline, T_lo=305.0, T_hi=300.0):
+    """1D film whose transport axis carries the component axis_perm[0] of the
+    given directions: s' = s[:, axis_perm], same weights, isothermal walls."""
+    m1 = np.ones(n_cells, dtype=np.uint8)
+    fbc1 = bi.face_bc_from_mask((n_cells, 1, 1), 1, m1, lambda i, j, k, f: f)
+    return bi.Problem("film", 1, (n_cells, 1, 1), (2e-9, 2e-9, 2e-9), m1, fbc1,
+                      np.array([0, 0], dtype=np.int32), np.array([T_lo, T_hi]),
+                      v, tau, C, np.ascontiguousarray(s[:, list(axis_perm)]), w, Qline, 300.0)
+
+
+def test_flux_along_y_matches_film():
+    """Methods, "Phonon BTE" (Eq. 4): a 2D strip with isothermal -y / +y walls,
+    specular -x / +x walls and a source varying in y only carries the 1D film's
+    solution along y in every column: T equal, q_y equal to the film's q_x
+    (the film transports the y components of the same directions) and q_x zero,
+    since each direction and its x mirror carry the same energy."""
+    nx, ny = 3, 12
+    v, tau, C = bi.band_table_synthetic(3)
+    s, w = bi.quad_octant_gl(2, 2, polar_axis=2)
+    qy = 1e18 * np.linspace(0.2, 1.0, ny)
+    m2 = np.ones(nx * ny, dtype=np.uint8)
+    fbc2 = bi.face_bc_from_mask((nx, ny, 1), 2, m2, lambda i, j, k, f: {2: 0, 3: 1}.get(f, 2))
+    p2 = bi.Problem("strip_y", 2, (nx, ny, 1), (2e-9, 2e-9, 2e-9), m2, fbc2,
+                    np.array([0, 0, 2], dtype=np.int32), np.array([305.0, 300.0, 300.0]),
+                    v, tau, C, s, w, np.repeat(qy, nx), 300.0)
+    p1 = _film_along((1, 0, 2), ny, v, tau, C, s, w, qy)
+    r2 = oracle.solve(p2, tol=0.0, max_iters=6000)
+    r1 = oracle.solve(p1, tol=0.0, max_iters=6000)
+    T2 = r2["T"].reshape(ny, nx)
+    q2 = r2["q"].reshape(ny, nx, 2)
+    tsc = np.abs(r1["T"] - 300.0).max()
+    qsc = np.abs(r1["q"][:, 0]).max()
+    assert qsc > 0
+    for i in range(nx):
+        assert np.abs(T2[:, i] - r1["T"]).max() < 1e-10 * tsc
+        assert np.abs(q2[:, i, 1] - r1["q"][:, 0]).max() < 1e-10 * qsc
+    assert np.abs(q2[:, :, 0]).max() < 1e-12 * qsc
+
+
+def test_flux_along_z_matches_film():
+    """Eq. 4 along z: a 3D column with specular x and y walls, isothermal -z / +z
+    walls and a source varying in z only reduces to the film along z: q_z equals
+    the film's q_x, q_x and q_y vanish."""
+    nx, ny, nz = 2, 3, 10
+    v, tau, C = bi.band_table_synthetic(2)
+    s, w = bi.quad_octant_gl(2, 1, polar_axis=0)
+    qz = 1e18 * np.linspace(1.0, 0.3, nz)
+    m3 = np.ones(nx * ny * nz, dtype=np.uint8)
+    fbc3 = bi.face_bc_from_mask((nx, ny, nz), 3, m3, lambda i, j, k, f: {4: 0, 5: 1}.get(f, 2))
+    p3 = bi.Problem("column_z", 3, (nx, ny, nz), (2e-9, 2e-9, 2e-9), m3, fbc3,
+                    np.array([0, 0, 2], dtype=np.int32), np.array([305.0, 300.0, 300.0]),
+                    v, tau, C, s, w, np.repeat(qz, nx * ny), 300.0)
+    p1 = _film_along((2, 0, 1), nz, v, tau, C, s, w, qz)
+    r3 = oracle.solve(p3, tol=0.0, max_iters=6000)
+    r1 = oracle.solve(p1, tol=0.0, max_iters=6000)
+    T3 = r3["T"].reshape(nz, ny * nx)
+    q3 = r3["q"].reshape(nz, ny * nx, 3)
+    tsc = np.abs(r1["T"] - 300.0).max()
+    qsc = np.abs(r1["q"][:, 0]).max()
+    for c in range(nx * ny):
+        assert np.abs(T3[:, c] - r1["T"]).max() < 1e-10 * tsc
+        assert np.abs(q3[:, c, 2] - r1["q"][:, 0]).max() < 1e-10 * qsc
+    assert np.abs(q3[:, :, :2]).max() < 1e-12 * qsc
+
+
+def test_flux_transposes_on_centred_square():
+    """With the hot spot at the centre and a quadrature closed under x <-> y,
+    the fixed point is symmetric under the transpose of the square, so the flux
+    along y at (i, j) is the flux along x at (j, i) (Eq. 4)."""
+    p = bi.square_2d(16, L=0.2e-6, n_bands=3, n_theta=2, n_phi=2, centered=True)
+    r = oracle.solve(p, tol=1e-13, max_iters=5000)
+    q = r["q"].reshape(16, 16, 2)
+    sc = np.abs(q).max()
+    assert sc > 0
+    assert np.abs(q[:, :, 1] - q[:, :, 0].T).max() < 1e-12 * sc
+    # and the flux points away from the hot spot on either side of it
+    assert q[8, 12, 0] > 0 and q[8, 3, 0] < 0
+
+
+# ------------------------------------------ P17 convergence residuals (Eq. 22)
+@pytest.mark.parametrize("n_it", [1, 5, 12])
+def test_residuals_follow_eq22(n_it):
+    """Methods, "Iterative matrix formulation and solution scheme" (Eq. 22, with
+    the deviational normalisation): the eps_T and eps_q reported after n + 1
+    iterations equal the RMS change of T and of |q| between the fields returned
+    after n and n + 1 iterations, over the active cells, divided by the largest
+    |T - T_ref| and the largest |q| of the newer fields."""
+    p = bi.random_box_2d(7, 6, seed=5, n_bands=3, n_theta=2, n_phi=1, kinds=(0, 1))
+    a = oracle.solve(p, tol=0.0, max_iters=n_it)
+    b = oracle.solve(p, tol=0.0, max_iters=n_it + 1)
+    act = p.mask > 0
+    dT = (b["T"] - a["T"])[act]
+    eT = math.sqrt(float(np.mean(dT * dT))) / float(np.abs(b["T"][act] - p.T_ref).max())
+    qa = np.linalg.norm(a["q"][act], axis=1)
+    qb = np.linalg.norm(b["q"][act], axis=1)
+    eq = math.sqrt(float(np.mean((qb - qa) ** 2))) / float(qb.max())
+    assert b["iters"] == n_it + 1
+    assert abs(b["eps_T"] - eT) <= 1e-12 * eT
+    assert abs(b["eps_q"] - eq) <= 1e-12 * eq
+
+
+def test_residual_stop_rule():
+    """The solve stops at the first iteration whose eps_T and eps_q are both
+    below the target (Eq. 22): one iteration fewer leaves one of them above."""
+    p = bi.random_box_2d(7, 6, seed=5, n_bands=3, n_theta=2, n_phi=1, kinds=(0, 1))
+    r = oracle.solve(p, tol=1e-6, max_iters=5000)
+    assert r["status"] == "converged" and r["eps_T"] < 1e-6 and r["eps_q"] < 1e-6
+    prev = oracle.solve(p, tol=0.0, max_iters=r["iters"] - 1)
+    assert prev["eps_T"] >= 1e-6 or prev["eps_q"] >= 1e-6

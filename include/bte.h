@@ -1,6 +1,13 @@
 /*
  * bte.h -- C ABI of the MI355X phonon-BTE source-iteration library.
  *
+ * Inputs and outputs follow the paper's problem statement (Methods, "Forward
+ * and inverse modeling workflow"): a geometry (here a Cartesian voxel mask with
+ * per-face boundary conditions), the phonon band properties, the angular
+ * quadrature and the heat source go in; the lattice temperature and the heat
+ * flux come out, and for inverse problems the gradients of an objective with
+ * respect to the relaxation times and the heat source.
+ *
  * The library solves the steady, nongray phonon Boltzmann transport equation in
  * the relaxation-time approximation (paper Methods, "Phonon BTE", Eq. 1 with the
  * relaxation sign of Eq. eq:bte-2), discretized by spectral bands (Eqs. 8-13)
@@ -22,8 +29,13 @@
  *   - Pointers named h_* are host pointers; d_* are device pointers on the
  *     device that was current when the handle was created. The caller owns all
  *     memory it passes; the library never frees it and never retains it beyond
- *     the call. The library owns the device memory of a handle (allocated in
- *     bte_create / bte_batch_create, freed by bte_destroy).
+ *     the call, except a workspace bound with bte_bind_workspace, which it uses
+ *     until the handle is destroyed or another workspace is bound.
+ *   - Device memory: bte_create allocates none. With a workspace bound
+ *     (bte_workspace_bytes, bte_bind_workspace) every device array of the
+ *     handle lives in it and the library allocates no device memory. A handle
+ *     used without one makes its own arrays at the first call that needs the
+ *     device and frees them in bte_destroy.
  *   - hip_stream is a hipStream_t (NULL = the null stream). Work is enqueued on
  *     it; calls that report convergence synchronise with it before returning.
  *   - Handles are not thread-safe; use one handle from one thread at a time.
@@ -47,7 +59,8 @@ typedef enum {
   BTE_ERR_HIP = 2,            /* HIP runtime error (message in bte_last_error) */
   BTE_ERR_NOT_CONVERGED = 3,  /* max_iters reached; outputs hold the last iterate */
   BTE_ERR_NONFINITE = 4,      /* a non-finite temperature or flux appeared */
-  BTE_ERR_STATE = 5           /* call order violated (e.g. adjoint before solve) */
+  BTE_ERR_STATE = 5,          /* call order violated (e.g. adjoint before solve) */
+  BTE_ERR_WORKSPACE = 6       /* the bound workspace is too small for the request */
 } bte_status;
 
 /* Boundary-condition kinds (paper Methods, "Boundary conditions"). */
@@ -65,6 +78,10 @@ enum {
    ordinate groups, temperatures and residuals in double. */
 enum { BTE_PREC_FP64 = 0, BTE_PREC_FP32 = 1 };
 
+/* Geometry of one problem: the voxel form of the paper's mesh (Methods,
+   "Spatial discretization": uniform Cartesian cells, V_i = h0 h1 h2 and
+   S_ij / V_i = 1 / h_d for a face normal to axis d) and its boundary conditions
+   (Methods, "Boundary conditions", Eqs. 5-7). */
 typedef struct {
   int dim;                  /* 1, 2 or 3 */
   int n[3];                 /* cells per axis; unused axes must be 1 */
@@ -78,6 +95,8 @@ typedef struct {
   const double* h_bc_T;     /* [n_bc] wall temperature (K), isothermal walls */
 } bte_geometry;
 
+/* Spectral bands (Methods, "Band discretization", Eqs. 8-13): per band the group
+   velocity, relaxation time and heat capacity; C does not depend on T. */
 typedef struct {
   int n_bands;              /* B >= 1 */
   const double* h_v;        /* [B] group velocity (m/s), > 0 */
@@ -85,6 +104,7 @@ typedef struct {
   const double* h_C;        /* [B] volumetric heat capacity (J m^-3 K^-1), > 0 */
 } bte_bands;
 
+/* Discrete ordinates (Methods, "Angle discretization", Eq. 14). */
 typedef struct {
   int n_dirs;               /* M >= 1 */
   const double* h_s;        /* [M*3] unit directions (x, y, z) */
@@ -106,13 +126,23 @@ typedef struct {
    the per-workgroup limit is rejected with BTE_ERR_INVALID. */
 typedef struct { int G, R, P, C, NR; } bte_plan;
 
+/* Options of a solve or adjoint (Methods, "Iterative matrix formulation and
+   solution scheme": the iteration and its stop test, Eq. 22). */
 typedef struct {
   double tol_T;        /* target eps_T (Eq. 22, normalised by max |T - T_ref|); <= 0: run max_iters */
   double tol_q;        /* target eps_q (Eq. 22); <= 0: run max_iters */
   int max_iters;       /* >= 1 */
   int check_every;     /* iterations between convergence checks (>= 1); 0 = default (8) */
+  double T_ref;        /* reference temperature (K) of the deviational variables; <= 0 selects the
+                          mean wall temperature over the instance's isothermal boundary faces.
+                          Exact for any value (the equations are linear in (e, T)); the FP32
+                          sweeps keep more digits of T - T_ref when it is near the solution. */
   int use_graph;       /* 1 = replay a captured hipGraph of check_every iterations */
-  int store_state;     /* bte_solve: keep what bte_adjoint needs (the angular field) */
+  int store_angular;   /* solves: keep what bte_adjoint needs (the angular field) */
+  const char* autotune_cache; /* NULL, or the path of a plan-cache text file: a solve applies the
+                          plan stored for its problem and device, or runs bte_autotune (30
+                          iterations per candidate) and appends the result; lines read
+                          "<key> plan G R P C NR" */
 } bte_opts;
 
 typedef struct {
@@ -154,15 +184,37 @@ bte_status bte_quadrature_gl_mu(int n_mu, double* h_s, double* h_w);
 bte_status bte_quadrature_octant_gl(int n_theta, int n_phi, int polar_axis, double* h_s,
                                     double* h_w);
 
-/* Create a solver for one problem on the current device. Validates as
-   bte_validate, derives the per-band and per-ordinate constants, the boundary
-   face tables and the sweep schedule, and allocates the device state.
-   T_ref: reference temperature of the deviational variables (K). */
+/* Create a solver for one problem on the current device (the per-band,
+   per-ordinate equations of Eq. eq:bte-2 discretized by Eq. eq:fvm-1 with
+   first-order upwind faces; Methods, "Spatial discretization"). Validates as
+   bte_validate, derives the per-band and per-ordinate constants (the diagonal
+   and upwind couplings of Eq. A_matrix), the boundary-face tables and the sweep
+   schedule. Allocates no device memory (see bte_bind_workspace).
+   precision: BTE_PREC_*. *out: the new handle (NULL on failure). */
 bte_status bte_create(const bte_geometry* geom, const bte_bands* bands,
-                      const bte_quadrature* quad, double T_ref, int precision,
-                      bte_handle* out);
+                      const bte_quadrature* quad, int precision, bte_handle* out);
 
-/* Replace the relaxation times (e.g. between optimisation steps). h_tau: [B]. */
+/* Device bytes the handle needs for its current plan: *bytes. with_adjoint = 1
+   adds the angular field that a solve with store_angular keeps for
+   bte_adjoint. A later bte_set_plan or bte_autotune may change the figure. */
+bte_status bte_workspace_bytes(bte_handle h, int with_adjoint, size_t* bytes);
+
+/* Bind caller-owned device memory (e.g. torch.empty(bytes, dtype=torch.uint8)
+   on the handle's device; 256-byte aligned) as the handle's workspace: every
+   device array of the handle is carved from it and the library allocates no
+   device memory from then on. The caller keeps the memory alive and unchanged
+   until the handle is destroyed or rebound; the library never frees it.
+   BTE_ERR_WORKSPACE when bytes is below bte_workspace_bytes(h, 0); with fewer
+   than bte_workspace_bytes(h, 1) bytes a solve with store_angular returns
+   BTE_ERR_WORKSPACE, and so does a plan change that would not fit. d_ws = NULL
+   unbinds (the handle makes its own memory at the next call that needs it).
+   Binding or unbinding drops any solver state (solve again). */
+bte_status bte_bind_workspace(bte_handle h, void* d_ws, size_t bytes);
+
+/* Replace the relaxation times tau_b (Eq. eq:bte-2; e.g. between optimisation
+   steps of an inverse problem, Methods, "Forward and inverse modeling
+   workflow"). h_tau: [B], finite and > 0. A state kept for bte_adjoint is
+   dropped when tau changes. */
 bte_status bte_set_tau(bte_handle h, const double* h_tau);
 
 /* Set / get the sweep kernel shape. */
@@ -174,21 +226,33 @@ bte_status bte_get_plan(bte_handle h, bte_plan* plan);
    (sweep, finalize, diffuse-wall update) after one warm-up iteration, from a
    fresh state; the current shape is kept unless another is at least 3% faster.
    The solver state afterwards is that of a fresh start (solve again).
-   d_Q: [ncell] heat source used for the timing runs (NULL = zero). */
+   d_Q: [ncell] heat source used for the timing runs (NULL = zero); a batch
+   handle takes NULL only (BTE_ERR_STATE otherwise: one array cannot serve
+   instances of different sizes). With a bound workspace, shapes that do not
+   fit in it are skipped. */
 bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_stream,
                         bte_plan* best);
 
-/* Solve. d_Q: [ncell] heat source (W/m^3); d_T_init: [ncell] initial
-   temperature (K) or NULL for T_ref everywhere (a previous result resumes the
-   iteration: warm start); d_T: [ncell] output temperature T_L (K);
-   d_q: [ncell*dim] output heat flux (W/m^2, grid axes) or NULL.
-   Returns BTE_OK when converged, BTE_ERR_NOT_CONVERGED after max_iters (outputs
-   hold the last iterate), BTE_ERR_NONFINITE on a non-finite iterate. */
-bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, double* d_T,
-                     double* d_q, const bte_opts* opts, void* hip_stream, bte_report* h_rep);
+/* Solve by source iteration (Methods, "Iterative matrix formulation and
+   solution scheme": step 1 from the initial temperature, step 2 the exact
+   solve of Eq. Axb for every (band, direction), step 3 the T_L update of
+   Eq. updatee0_t and the lagged wall values of Eqs. 6-7, step 4 the test of
+   Eq. 22). h_tau: [B] relaxation times for this solve, or NULL to keep the
+   current ones (as bte_set_tau). d_Q: [ncell] heat source (W/m^3) or NULL;
+   d_T_init: [ncell] initial temperature (K) or NULL for T_ref everywhere (a
+   previous result resumes the iteration: warm start); d_T: [ncell] output
+   temperature T_L (K); d_q: [ncell*dim] output heat flux (Eq. 4, W/m^2, grid
+   axes) or NULL. Returns BTE_OK when converged, BTE_ERR_NOT_CONVERGED after
+   max_iters (outputs hold the last iterate), BTE_ERR_NONFINITE on a non-finite
+   iterate, BTE_ERR_INVALID (outputs untouched) for bad arguments. */
+bte_status bte_solve(bte_handle h, const double* h_tau, const double* d_Q, const double* d_T_init,
+                     double* d_T, double* d_q, const bte_opts* opts, void* hip_stream,
+                     bte_report* h_rep);
 
-/* Adjoint of the converged source-iteration fixed point (needs a previous
-   bte_solve on h with opts->store_state = 1).
+/* Adjoint of the converged source-iteration fixed point (the gradient
+   workflow of Methods, "Forward and inverse modeling workflow": a discrete
+   adjoint of the implicit solves). Needs a previous bte_solve on h with
+   opts->store_angular = 1 and unchanged tau.
    Given d_dJdT = dJ/dT [ncell], iterates lambda = dJ/dT + sum_b k_b sum_a psi
    with psi = transpose sweeps (direction -s_a) of lambda. Isothermal walls give
    the transposed sweeps zero inflow; diffuse and specular walls give them the
@@ -215,20 +279,24 @@ bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double
                           double* h_updates);
 
 /* Batched solver: n_inst problems of the same dimension, band table and
-   quadrature, swept by one persistent launch per iteration with per-instance
-   convergence and retirement. geoms: [n_inst]. */
+   quadrature (the "parallel forward simulations" of the paper's
+   Introduction), swept by one persistent launch per iteration with
+   per-instance convergence and retirement. geoms: [n_inst]. Allocates no
+   device memory (as bte_create). */
 bte_status bte_batch_create(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
-                            const bte_quadrature* quad, double T_ref, int precision,
-                            bte_handle* out);
+                            const bte_quadrature* quad, int precision, bte_handle* out);
 
-/* d_Q[i], d_T[i], d_q[i]: device arrays of instance i (d_q may be NULL or hold
+/* Solve every instance as bte_solve does (same iteration and stop test, per
+   instance; opts->T_ref <= 0 takes each instance's own default).
+   d_Q[i], d_T[i], d_q[i]: device arrays of instance i (d_q may be NULL or hold
    NULL entries). h_reps: [n_inst] or NULL. Returns BTE_OK when every instance
    converged, else the worst status. */
 bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const* d_T,
                            double* const* d_q, const bte_opts* opts, void* hip_stream,
                            bte_report* h_reps);
 
-/* Batched adjoint (after bte_batch_solve with store_state). h_dJdtau: [n_inst*B]. */
+/* Batched adjoint, per instance as bte_adjoint (after bte_batch_solve with
+   store_angular). h_dJdtau: [n_inst*B]. */
 bte_status bte_batch_adjoint(bte_handle h, const double* const* d_dJdT, double* h_dJdtau,
                              double* const* d_dJdQ, const bte_opts* opts, void* hip_stream,
                              bte_report* h_reps);

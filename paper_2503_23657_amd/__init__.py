@@ -27,8 +27,10 @@ import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-BTE_OK, BTE_ERR_INVALID, BTE_ERR_HIP, BTE_ERR_NOT_CONVERGED, BTE_ERR_NONFINITE, BTE_ERR_STATE = range(6)
-STATUS_NAMES = {0: "ok", 1: "invalid", 2: "hip", 3: "not_converged", 4: "nonfinite", 5: "state"}
+(BTE_OK, BTE_ERR_INVALID, BTE_ERR_HIP, BTE_ERR_NOT_CONVERGED, BTE_ERR_NONFINITE, BTE_ERR_STATE,
+ BTE_ERR_WORKSPACE) = range(7)
+STATUS_NAMES = {0: "ok", 1: "invalid", 2: "hip", 3: "not_converged", 4: "nonfinite", 5: "state",
+                6: "workspace"}
 BC_ISOTHERMAL, BC_DIFFUSE, BC_SPECULAR = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 
@@ -58,7 +60,8 @@ class Plan(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol_T", ctypes.c_double), ("tol_q", ctypes.c_double), ("max_iters", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int), ("store_state", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("T_ref", ctypes.c_double), ("use_graph", ctypes.c_int),
+                ("store_angular", ctypes.c_int), ("autotune_cache", ctypes.c_char_p)]
 
 
 class Report(ctypes.Structure):
@@ -90,16 +93,17 @@ bte_quadrature_gl_mu = _sig("bte_quadrature_gl_mu", _S, [ctypes.c_int, _P, _P])
 bte_quadrature_octant_gl = _sig("bte_quadrature_octant_gl", _S, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                                  _P, _P])
 bte_create = _sig("bte_create", _S, [ctypes.POINTER(Geometry), ctypes.POINTER(Bands),
-                                     ctypes.POINTER(Quadrature), ctypes.c_double, ctypes.c_int,
-                                     ctypes.POINTER(_H)])
+                                     ctypes.POINTER(Quadrature), ctypes.c_int, ctypes.POINTER(_H)])
 bte_batch_create = _sig("bte_batch_create", _S, [ctypes.c_int, ctypes.POINTER(Geometry),
                                                  ctypes.POINTER(Bands), ctypes.POINTER(Quadrature),
-                                                 ctypes.c_double, ctypes.c_int, ctypes.POINTER(_H)])
+                                                 ctypes.c_int, ctypes.POINTER(_H)])
+bte_workspace_bytes = _sig("bte_workspace_bytes", _S, [_H, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
+bte_bind_workspace = _sig("bte_bind_workspace", _S, [_H, _P, ctypes.c_size_t])
 bte_set_tau = _sig("bte_set_tau", _S, [_H, _P])
 bte_set_plan = _sig("bte_set_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_get_plan = _sig("bte_get_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_autotune = _sig("bte_autotune", _S, [_H, _P, ctypes.c_int, _P, ctypes.POINTER(Plan)])
-bte_solve = _sig("bte_solve", _S, [_H, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
+bte_solve = _sig("bte_solve", _S, [_H, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
 bte_adjoint = _sig("bte_adjoint", _S, [_H, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
 bte_adjoint_dscale = _sig("bte_adjoint_dscale", _S, [_H, _P])
 bte_time_sweep = _sig("bte_time_sweep", _S, [_H, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
@@ -109,7 +113,8 @@ bte_batch_adjoint = _sig("bte_batch_adjoint", _S, [_H, _P, _P, _P, ctypes.POINTE
 bte_destroy = _sig("bte_destroy", _S, [_H])
 
 EXPORTED = ["bte_version", "bte_last_error", "bte_validate", "bte_quadrature_gl_mu",
-            "bte_quadrature_octant_gl", "bte_create", "bte_set_tau", "bte_set_plan", "bte_get_plan",
+            "bte_quadrature_octant_gl", "bte_create", "bte_workspace_bytes", "bte_bind_workspace",
+            "bte_set_tau", "bte_set_plan", "bte_get_plan",
             "bte_autotune", "bte_solve", "bte_adjoint", "bte_adjoint_dscale", "bte_time_sweep", "bte_batch_create",
             "bte_batch_solve", "bte_batch_adjoint", "bte_destroy"]
 
@@ -202,28 +207,56 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def make_opts(tol=1e-10, tol_q=None, max_iters=100000, check_every=8, use_graph=True, store_state=False):
+def make_opts(tol=1e-10, tol_q=None, max_iters=100000, check_every=8, use_graph=True, store_state=False,
+              T_ref=0.0, autotune_cache=None):
+    """bte_opts; store_state sets store_angular (keep the angular field for the adjoint)."""
     o = Opts()
     o.tol_T = float(tol)
     o.tol_q = float(tol if tol_q is None else tol_q)
     o.max_iters = int(max_iters)
     o.check_every = int(check_every)
+    o.T_ref = float(T_ref)
     o.use_graph = 1 if use_graph else 0
-    o.store_state = 1 if store_state else 0
+    o.store_angular = 1 if store_state else 0
+    o.autotune_cache = None if autotune_cache is None else os.fsencode(autotune_cache)
     return o
 
 
-class Solver:
-    """One problem on the current HIP device (see bte_create)."""
+class _Workspace:
+    """bte_workspace_bytes / bte_bind_workspace for a handle owner."""
+
+    def workspace_bytes(self, with_adjoint: bool = False) -> int:
+        n = ctypes.c_size_t()
+        _check(bte_workspace_bytes(self._h, 1 if with_adjoint else 0, ctypes.byref(n)))
+        return int(n.value)
+
+    def bind_workspace(self, ws) -> None:
+        """Carve every device array from ws (a uint8 device tensor, kept alive
+        here), or go back to the library's own memory with ws = None."""
+        if ws is None:
+            _check(bte_bind_workspace(self._h, None, 0))
+        else:
+            _check(bte_bind_workspace(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()))
+        self._ws = ws
+
+
+class Solver(_Workspace):
+    """One problem on the current HIP device (see bte_create).
+
+    ``generation`` counts the solves and tau changes made through this object;
+    the autograd binding uses it to tell whether the stored state is still the
+    one its forward pass left."""
 
     def __init__(self, p, precision: str = "fp64", T_ref: Optional[float] = None, plan: Optional[dict] = None):
         self.problem = p
         self._hp = _HostProblem(p)
         self.prec = PREC_FP32 if precision == "fp32" else PREC_FP64
         self.T_ref = float(p.T_ref if T_ref is None else T_ref)
+        self.generation = 0
+        self._ws = None
         h = _H()
         _check(bte_create(ctypes.byref(self._hp.geom), ctypes.byref(self._hp.bands),
-                          ctypes.byref(self._hp.quad), self.T_ref, self.prec, ctypes.byref(h)))
+                          ctypes.byref(self._hp.quad), self.prec, ctypes.byref(h)))
         self._h = h
         if plan:
             self.set_plan(**plan)
@@ -250,6 +283,7 @@ class Solver:
 
     def set_tau(self, tau):
         t = _c(tau, np.float64)
+        self.generation += 1
         _check(bte_set_tau(self._h, t.ctypes.data))
 
     def autotune(self, Q=None, n_iters=5, stream=None) -> dict:
@@ -258,17 +292,21 @@ class Solver:
         return pl.as_dict()
 
     def solve(self, Q, T_init=None, T_out=None, q_out=None, stream=None, allow_not_converged=False,
-              **opt):
-        """Q: float64 device tensor [ncell]. Returns (T, q, report dict)."""
+              tau=None, **opt):
+        """Q: float64 device tensor [ncell]; tau: relaxation times for this solve
+        (None keeps the current ones). Returns (T, q, report dict)."""
         import torch
         p = self.problem
         dev = Q.device
         T = T_out if T_out is not None else torch.empty(p.ncell, dtype=torch.float64, device=dev)
         q = q_out if q_out is not None else torch.empty(p.ncell * p.dim, dtype=torch.float64, device=dev)
+        opt.setdefault("T_ref", self.T_ref)
         o = make_opts(**opt)
         rep = Report()
-        st = bte_solve(self._h, _ptr(Q), _ptr(T_init), _ptr(T), _ptr(q), ctypes.byref(o),
-                       _stream(stream), ctypes.byref(rep))
+        t = None if tau is None else _c(tau, np.float64)
+        self.generation += 1
+        st = bte_solve(self._h, None if t is None else t.ctypes.data, _ptr(Q), _ptr(T_init), _ptr(T), _ptr(q),
+                       ctypes.byref(o), _stream(stream), ctypes.byref(rep))
         allow = (BTE_ERR_NOT_CONVERGED,) if (allow_not_converged or o.tol_T <= 0 or o.tol_q <= 0) else ()
         _check(st, allow)
         return T, q.view(p.ncell, p.dim), rep.as_dict()
@@ -294,6 +332,15 @@ class Solver:
         _check(bte_adjoint_dscale(self._h, out.ctypes.data))
         return float(out[0])
 
+    def sweep_kernel_name(self) -> str:
+        """Name of the forward sweep kernel the current plan launches (as a
+        profiler reports it), for matching counter summaries."""
+        pl = self.plan()
+        t = "float" if self.prec == PREC_FP32 else "double"
+        if self.problem.dim == 3:
+            return f"sweep_kernel<{t}, {pl['G']}, 1, 0, true>"
+        return f"sweep2d_kernel<{t}, {pl['G']}, {pl['NR']}, {pl['P']}, 1, 0>"
+
     def time_sweep(self, n_launches=20, stream=None):
         ms = ctypes.c_double()
         upd = ctypes.c_double()
@@ -301,7 +348,7 @@ class Solver:
         return ms.value, upd.value
 
 
-class BatchSolver:
+class BatchSolver(_Workspace):
     """Many problems of one dimension, band table and quadrature (bte_batch_create)."""
 
     def __init__(self, problems: Sequence, precision: str = "fp32", T_ref: float = 300.0,
@@ -312,9 +359,10 @@ class BatchSolver:
         self._geoms = geoms
         self.prec = PREC_FP32 if precision == "fp32" else PREC_FP64
         self.T_ref = float(T_ref)
+        self._ws = None
         h = _H()
         _check(bte_batch_create(len(self._hps), geoms, ctypes.byref(self._hps[0].bands),
-                                ctypes.byref(self._hps[0].quad), self.T_ref, self.prec, ctypes.byref(h)))
+                                ctypes.byref(self._hps[0].quad), self.prec, ctypes.byref(h)))
         self._h = h
         if plan:
             pl = Plan(plan.get("G", 0), plan.get("R", 0), plan.get("P", 0), plan.get("C", 0), plan.get("NR", 0))
@@ -336,6 +384,12 @@ class BatchSolver:
         _check(bte_get_plan(self._h, ctypes.byref(pl)))
         return pl.as_dict()
 
+    def autotune(self, n_iters=5, stream=None) -> dict:
+        """bte_autotune on the whole batch (zero source in the timing runs)."""
+        pl = Plan()
+        _check(bte_autotune(self._h, None, int(n_iters), _stream(stream), ctypes.byref(pl)))
+        return pl.as_dict()
+
     def solve(self, Qs, stream=None, **opt):
         import torch
         n = len(self.problems)
@@ -345,6 +399,7 @@ class BatchSolver:
         aT = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Ts])
         aq = (ctypes.c_void_p * n)(*[t.data_ptr() for t in qs])
         reps = (Report * n)()
+        opt.setdefault("T_ref", self.T_ref)
         o = make_opts(**opt)
         st = bte_batch_solve(self._h, aQ, aT, aq, ctypes.byref(o), _stream(stream), reps)
         _check(st, (BTE_ERR_NOT_CONVERGED,))

@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/bte.h"
@@ -51,36 +52,53 @@ struct ErrClear {
   ~ErrClear() { (void)hipGetLastError(); }
 };
 
-// Device allocations owned by a handle.
+// Device memory of a handle. Three modes:
+//   OWNED  every array is a hipMalloc of its own, freed with the pool;
+//   ARENA  arrays are carved from a caller-provided workspace (256-byte
+//          aligned offsets); nothing is allocated or freed;
+//   COUNT  nothing is allocated or copied: the pool only adds up the bytes
+//          an ARENA would need (the pointers it returns are never used).
+constexpr size_t kWsAlign = 256;
 struct DevPool {
+  enum Mode { OWNED, ARENA, COUNT };
+  Mode mode = OWNED;
+  char* base = nullptr;  // ARENA
+  size_t cap = 0;        // ARENA capacity (bytes)
+  size_t used = 0;       // bytes requested so far (aligned)
   std::vector<void*> ptrs;
+  DevPool() = default;
+  explicit DevPool(Mode m, char* b = nullptr, size_t c = 0) : mode(m), base(b), cap(c) {}
+  DevPool(const DevPool&) = delete;
+  DevPool& operator=(const DevPool&) = delete;
   ~DevPool() {
     for (void* p : ptrs) (void)hipFree(p);
   }
   template <typename T>
   hipError_t alloc(T** out, size_t count) {
-    void* p = nullptr;
-    const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return e;
-    ptrs.push_back(p);
-    *out = reinterpret_cast<T*>(p);
+    const size_t bytes = (std::max<size_t>(count * sizeof(T), 16) + kWsAlign - 1) / kWsAlign * kWsAlign;
+    if (mode == OWNED) {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) return e;
+      ptrs.push_back(p);
+      *out = reinterpret_cast<T*>(p);
+    } else if (mode == ARENA) {
+      if (used + bytes > cap) return hipErrorOutOfMemory;  // sizes are checked before carving
+      *out = reinterpret_cast<T*>(base + used);
+    } else {
+      *out = reinterpret_cast<T*>(kWsAlign + used);  // placeholder, never dereferenced
+    }
+    used += bytes;
     return hipSuccess;
   }
   template <typename T>
   hipError_t upload(T** out, const std::vector<T>& v) {
     hipError_t e = alloc(out, v.size());
     if (e != hipSuccess) return e;
-    if (!v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (mode != COUNT && !v.empty()) e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
   }
-  void release(void* p) {
-    for (auto& q : ptrs)
-      if (q == p) {
-        (void)hipFree(q);
-        q = nullptr;
-      }
-  }
+  hipError_t memset(void* p, int val, size_t bytes) { return mode == COUNT ? hipSuccess : hipMemset(p, val, bytes); }
 };
 
 struct Inst {
@@ -134,13 +152,14 @@ struct Inst {
   std::vector<int> grp_band;    // instance-local group -> band
   bool stored = false;
   int fwd_parity = 0;           // parity of the converged forward state
+  double T_ref_default = 300.0; // mean temperature of the isothermal walls
+  double T_ref = 300.0;         // reference temperature of the current solve
 };
 
 }  // namespace
 
 struct bte_ctx {
   int precision = BTE_PREC_FP64;
-  double T_ref = 300.0;
   int dim = 0, B = 0;
   std::vector<double> v, tau, C;
   std::vector<Ordinate> ords;
@@ -155,8 +174,19 @@ struct bte_ctx {
   int2* d_spec_src_a = nullptr;        // [6][M] mirror of each outgoing ordinate (transposed sweeps)
   double* d_spec_iwq = nullptr;        // [6][M] 1 / (w_a' |s_a'.n|) of the mirror a'
   int n_cu = 256;
-  DevPool pool;                        // plan-independent
-  std::unique_ptr<DevPool> ppool;      // plan-dependent
+  std::unique_ptr<DevPool> spool;      // plan-independent arrays
+  std::unique_ptr<DevPool> ppool;      // plan-dependent arrays
+  // device memory: COUNT until the first call that needs the device (then
+  // OWNED) or until a workspace is bound (ARENA)
+  DevPool::Mode pool_mode = DevPool::COUNT;
+  char* ws_base = nullptr;             // bound workspace
+  size_t ws_cap = 0;
+  bool ws_store = false;               // the bound workspace holds the adjoint's angular field
+  size_t need_static = 0, need_plan = 0, need_store = 0;  // workspace bytes of the current plan
+  GroupSet gs;                         // ordinate groups of the current plan
+  Plan sched_plan;                     // plan the host schedules were built for
+  bool sched_valid = false;
+  char dev_name[96] = {0};             // device architecture and CU count (autotune-cache key)
   // shared device arrays (plan-dependent)
   InstDev* d_inst_f = nullptr;
   InstDev* d_inst_a = nullptr;
@@ -184,9 +214,12 @@ struct bte_ctx {
   int nacc_max = 1;
   size_t lds_stage_plane = 0;
   hipStream_t cap_stream = nullptr;
-  std::map<long long, hipGraphExec_t> graphs;
-  std::map<long long, hipGraph_t> graph_src;
+  // captured iteration chunks, keyed by (adjoint, iterations, tol_T bits, tol_q bits):
+  // the tolerances are kernel arguments recorded in the graph
+  std::map<std::tuple<int, int, uint64_t, uint64_t>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, uint64_t, uint64_t>, hipGraph_t> graph_src;
   std::vector<FinInst> fin_f, fin_a;   // host copies
+  ~bte_ctx();
 };
 
 namespace {
@@ -199,6 +232,16 @@ void clear_graphs(bte_ctx* h) {
   h->graphs.clear();
   h->graph_src.clear();
 }
+
+}  // namespace
+
+bte_ctx::~bte_ctx() {
+  clear_graphs(this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (h_st) (void)hipHostFree(h_st);
+}
+
+namespace {
 
 std::vector<char> to_prec(const std::vector<double>& x, int prec) {
   std::vector<char> out(x.size() * elem(prec));
@@ -217,8 +260,17 @@ double total_D(const bte_ctx* h) {
   return D;
 }
 
-// (Re)build everything that depends on the plan or on tau.
-bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
+DevPool* new_pool(bte_ctx* h, size_t offset) {
+  if (h->pool_mode == DevPool::ARENA)
+    return new DevPool(DevPool::ARENA, h->ws_base + offset, h->ws_cap > offset ? h->ws_cap - offset : 0);
+  return new DevPool(h->pool_mode);
+}
+
+bte_status finish_plan(bte_ctx* h, const Plan& pl, DevPool& pp);
+
+// (Re)build everything that depends on the plan: schedules, group tables and
+// the plan-dependent arrays.
+bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   Plan pl = pl_in;
   const bool L3 = h->dim == 3;
   if (h->has_specular && pl.G != 1) {
@@ -265,11 +317,16 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     return BTE_ERR_INVALID;
   }
   clear_graphs(h);
-  h->ppool.reset(new DevPool());
+  h->ppool.reset();
+  h->ppool.reset(new_pool(h, h->need_static));
   DevPool& pp = *h->ppool;
   const int prec = h->precision;
   const size_t es = elem(prec);
-  const GroupSet gs = build_groups(h->ords, h->B, h->dim, pl.G, pl.P);
+  const bool reuse_sched = h->sched_valid && h->sched_plan.G == pl.G && h->sched_plan.R == pl.R &&
+                           h->sched_plan.P == pl.P && h->sched_plan.C == pl.C && h->sched_plan.NR == pl.NR;
+  h->sched_valid = false;
+  if (!reuse_sched) h->gs = build_groups(h->ords, h->B, h->dim, pl.G, pl.P);
+  const GroupSet& gs = h->gs;
   const int n_grp_inst = (int)gs.band.size();
   const int n_bund = (int)gs.bundle_first.size();
   const int n_oct = 1 << h->dim;
@@ -282,7 +339,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
     std::string err;
-    if (!build_schedule(I.hi, pl, I.sch, err)) {
+    if (!reuse_sched && !build_schedule(I.hi, pl, I.sch, err)) {
       set_err("%s", err.c_str());
       return BTE_ERR_INVALID;
     }
@@ -347,8 +404,8 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
       char* p2;
       HIPCHK(pp.alloc(&p1, nposb));
       HIPCHK(pp.alloc(&p2, nposb));
-      HIPCHK(hipMemset(p1, 0, nposb));
-      HIPCHK(hipMemset(p2, 0, nposb));
+      HIPCHK(pp.memset(p1, 0, nposb));
+      HIPCHK(pp.memset(p2, 0, nposb));
       I.d_xq[b] = p1;
       I.d_xqa[b] = p2;
     }
@@ -483,8 +540,7 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
                                     sa.lds_stage + 2 * h->lds_stage_plane);
     if (bpc < 1) bpc = 1;
     h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
-    h->plan = pl;
-    return BTE_OK;
+    return finish_plan(h, pl, pp);
   }
   sa.lds_zring = (int)off;
   off += al(L3 ? 0 : (size_t)P * R * W_max * G * es);
@@ -534,29 +590,73 @@ bte_status build_plan(bte_ctx* h, const Plan& pl_in) {
     char* zg;
     const size_t zb = (size_t)h->grid * P * h->zg_stride * es;
     HIPCHK(pp.alloc(&zg, zb));
-    HIPCHK(hipMemset(zg, 0, zb));
+    HIPCHK(pp.memset(zg, 0, zb));
     h->d_zg = zg;
     sa.zg = zg;
     sa.zg_stride = h->zg_stride;
   }
+  return finish_plan(h, pl, pp);
+}
+
+// Plan-dependent arrays whose carving is sized in build_plan: records the
+// plan and its workspace bytes.
+bte_status finish_plan(bte_ctx* h, const Plan& pl, DevPool& pp) {
   h->plan = pl;
-  h->plan.R = R;
+  h->sched_plan = pl;
+  h->sched_valid = true;
+  h->need_plan = pp.used;
+  // the angular field kept for the adjoint: part of a bound workspace when it
+  // was sized for it, else allocated by the first solve that stores it
+  const size_t es = elem(h->precision);
+  size_t st = 0;
+  for (auto& I : h->inst)
+    st += ((size_t)I.n_grp * I.hi.ncell * pl.G * es + kWsAlign - 1) / kWsAlign * kWsAlign;
+  h->need_store = st;
+  if (h->pool_mode == DevPool::ARENA && h->ws_store) {
+    for (auto& I : h->inst) {
+      char* p;
+      HIPCHK(pp.alloc(&p, (size_t)I.n_grp * I.hi.ncell * pl.G * es));
+      I.d_store = p;
+    }
+  }
   return BTE_OK;
+}
+
+// (Re)build the plan-dependent state. With a bound workspace the plan's bytes
+// are counted first, and a plan that does not fit is rejected before any array
+// of the current plan is overwritten.
+bte_status build_plan(bte_ctx* h, const Plan& pl) {
+  if (h->pool_mode == DevPool::ARENA) {
+    h->pool_mode = DevPool::COUNT;
+    bte_status s = build_plan_impl(h, pl);
+    h->pool_mode = DevPool::ARENA;
+    if (s != BTE_OK) return s;
+    const size_t need = h->need_static + h->need_plan + (h->ws_store ? h->need_store : 0);
+    if (need > h->ws_cap) {
+      set_err("plan needs %zu bytes of workspace, %zu bound", need, h->ws_cap);
+      return BTE_ERR_WORKSPACE;
+    }
+    HIPCHK(hipDeviceSynchronize());  // kernels in flight may still read the current plan's arrays
+  }
+  return build_plan_impl(h, pl);
 }
 
 // Plan-independent per-instance device data.
 bte_status build_static(bte_ctx* h) {
-  DevPool& pp = h->pool;
+  clear_graphs(h);
+  h->ppool.reset();
+  h->spool.reset();
+  h->spool.reset(new_pool(h, 0));
+  DevPool& pp = *h->spool;
   const int prec = h->precision;
   const size_t es = elem(prec);
   const int n = (int)h->inst.size();
   HIPCHK(pp.alloc(&h->d_st_f, n));
   HIPCHK(pp.alloc(&h->d_st_a, n));
-  HIPCHK(hipMemset(h->d_st_f, 0, n * sizeof(StatusDev)));
-  HIPCHK(hipMemset(h->d_st_a, 0, n * sizeof(StatusDev)));
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->h_st), sizeof(StatusDev) * 2 * n, hipHostMallocDefault));
+  HIPCHK(pp.memset(h->d_st_f, 0, n * sizeof(StatusDev)));
+  HIPCHK(pp.memset(h->d_st_a, 0, n * sizeof(StatusDev)));
   HIPCHK(pp.alloc(&h->d_counters, 4));
-  HIPCHK(hipMemset(h->d_counters, 0, 16));
+  HIPCHK(pp.memset(h->d_counters, 0, 16));
   std::vector<int2> fb;
   std::vector<int> nbi;
   h->fin_f.resize(n);
@@ -644,8 +744,8 @@ bte_status build_static(bte_ctx* h) {
     char* u0;
     HIPCHK(pp.alloc(&u1, nu * es));
     HIPCHK(pp.alloc(&u0, nu * es));
-    HIPCHK(hipMemset(u1, 0, nu * es));
-    HIPCHK(hipMemset(u0, 0, nu * es));
+    HIPCHK(pp.memset(u1, 0, nu * es));
+    HIPCHK(pp.memset(u0, 0, nu * es));
     I.d_ubf = u1;
     I.d_ubf0 = u0;
     if (!hi.dface.empty()) h->has_diffuse = true;
@@ -668,12 +768,31 @@ bte_status build_static(bte_ctx* h) {
   HIPCHK(pp.upload(&h->d_nblocks, nbi));
   HIPCHK(pp.upload(&h->d_fin_f, h->fin_f));
   HIPCHK(pp.upload(&h->d_fin_a, h->fin_a));
-  HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  h->need_static = pp.used;
+  for (auto& I : h->inst) {
+    I.stored = false;
+    I.have_dJds = false;
+  }
   return BTE_OK;
 }
 
+// Build the device state of a handle whose arrays have only been counted so
+// far, in memory of its own (no workspace bound).
+bte_status ensure_device(bte_ctx* h) {
+  if (h->pool_mode != DevPool::COUNT) return BTE_OK;
+  h->pool_mode = DevPool::OWNED;
+  bte_status s = build_static(h);
+  if (s == BTE_OK) s = build_plan_impl(h, h->plan);
+  if (s != BTE_OK) {
+    h->spool.reset();
+    h->ppool.reset();
+    h->pool_mode = DevPool::COUNT;
+  }
+  return s;
+}
+
 bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
-                         const bte_quadrature* quad, double T_ref, int precision, bte_handle* out) {
+                         const bte_quadrature* quad, int precision, bte_handle* out) {
   if (!out) {
     set_err("null output handle");
     return BTE_ERR_INVALID;
@@ -681,10 +800,6 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   *out = nullptr;
   if (precision != BTE_PREC_FP32 && precision != BTE_PREC_FP64) {
     set_err("precision must be BTE_PREC_FP32 or BTE_PREC_FP64");
-    return BTE_ERR_INVALID;
-  }
-  if (!std::isfinite(T_ref)) {
-    set_err("T_ref must be finite");
     return BTE_ERR_INVALID;
   }
   if (n_inst < 1 || !geoms) {
@@ -704,7 +819,6 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   }
   std::unique_ptr<bte_ctx> h(new bte_ctx());
   h->precision = precision;
-  h->T_ref = T_ref;
   h->dim = geoms[0].dim;
   h->B = bands->n_bands;
   h->v.assign(bands->h_v, bands->h_v + h->B);
@@ -713,12 +827,31 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   h->t0 = *std::min_element(h->tau.begin(), h->tau.end());
   h->ords = fold_ordinates(quad, h->dim);
   h->inst.resize(n_inst);
-  for (int k = 0; k < n_inst; ++k) build_instance(&geoms[k], h->inst[k].hi);
+  for (int k = 0; k < n_inst; ++k) {
+    Inst& I = h->inst[k];
+    build_instance(&geoms[k], I.hi);
+    // default reference temperature: the mean over the isothermal boundary faces
+    double sum = 0.0;
+    long cnt = 0;
+    for (size_t f = 0; f < I.hi.bf_bc.size(); ++f)
+      if (I.hi.bc_kind[I.hi.bf_bc[f]] == BTE_BC_ISOTHERMAL) {
+        sum += I.hi.bc_T[I.hi.bf_bc[f]];
+        ++cnt;
+      }
+    I.T_ref_default = cnt ? sum / cnt : 300.0;
+    I.T_ref = I.T_ref_default;
+  }
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, dev));
   h->n_cu = std::max(1, prop.multiProcessorCount);
+  snprintf(h->dev_name, sizeof(h->dev_name), "%s:%d", prop.gcnArchName, h->n_cu);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->h_st), sizeof(StatusDev) * 2 * n_inst, hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  // device arrays are only counted here; they are built by the first call that
+  // needs them, or in a workspace the caller binds before that
+  h->pool_mode = DevPool::COUNT;
   bte_status s = build_static(h.get());
   if (s != BTE_OK) return s;
   Plan pl;
@@ -863,10 +996,10 @@ bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStre
 
 bte_status launch_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStream_t st) {
   if (!o.use_graph) return enqueue_chunk(h, adj, n, o, st);
-  const long long key = ((long long)adj << 40) | ((long long)n << 8) |
-                        (o.tol_T > 0 ? 1 : 0) | ((o.tol_q > 0 ? 1 : 0) << 1);
-  // tolerances are graph-captured kernel arguments: include their bits in the key
-  long long key2 = key ^ (long long)std::hash<double>()(o.tol_T) ^ ((long long)std::hash<double>()(o.tol_q) << 1);
+  uint64_t bT, bq;
+  memcpy(&bT, &o.tol_T, 8);
+  memcpy(&bq, &o.tol_q, 8);
+  const auto key2 = std::make_tuple((int)adj, n, bT, bq);
   auto it = h->graphs.find(key2);
   if (it == h->graphs.end()) {
     HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -929,6 +1062,10 @@ bte_status check_opts(const bte_opts* o) {
     set_err("check_every must be >= 0");
     return BTE_ERR_INVALID;
   }
+  if (!std::isfinite(o->T_ref)) {
+    set_err("T_ref must be finite");
+    return BTE_ERR_INVALID;
+  }
   return BTE_OK;
 }
 
@@ -955,7 +1092,7 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   a.inst = h->d_inst_f;
   a.inst_id = (int)k;
   a.X0 = d_T_init;
-  a.T_ref = h->T_ref;
+  a.T_ref = I.T_ref;
   a.Q = d_Q;
   a.active = I.d_active;
   a.X[0] = I.d_X[0];
@@ -972,7 +1109,7 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   u.bc_kind = I.d_bc_kind;
   u.bc_T = I.d_bc_T;
   u.T_init = d_T_init;
-  u.T_ref = h->T_ref;
+  u.T_ref = I.T_ref;
   u.zero = 0;
   HIPCHK(launch_ubf_init(h->precision, u, st));
   HIPCHK(launch_status_reset(h->d_st_f + k, (double)I.hi.n_active, st));
@@ -989,6 +1126,10 @@ bte_status store_state(bte_ctx* h, hipStream_t st) {
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
     if (!I.d_store) {
+      if (h->pool_mode == DevPool::ARENA) {
+        set_err("the bound workspace has no room for the angular field: bind bte_workspace_bytes(h, 1) bytes");
+        return BTE_ERR_WORKSPACE;
+      }
       char* p;
       HIPCHK(h->ppool->alloc(&p, (size_t)I.n_grp * I.hi.ncell * h->plan.G * es));
       I.d_store = p;
@@ -1010,6 +1151,119 @@ bte_status default_opts(const bte_opts* o, bte_opts& out) {
   if (s != BTE_OK) return s;
   out = *o;
   if (out.check_every == 0) out.check_every = 8;
+  return BTE_OK;
+}
+
+// Group coefficient tables for the current tau (uploaded when the device
+// state exists; otherwise they are built with it).
+bte_status upload_coefficients(bte_ctx* h) {
+  if (h->pool_mode == DevPool::COUNT) return BTE_OK;
+  std::vector<double> gtf, gta;
+  for (auto& I : h->inst) {
+    std::vector<double> cf, ca;
+    group_coefficients(h->gs, h->ords, I.hi, h->v, h->tau, h->C, h->t0, false, cf);
+    group_coefficients(h->gs, h->ords, I.hi, h->v, h->tau, h->C, h->t0, true, ca);
+    gtf.insert(gtf.end(), cf.begin(), cf.end());
+    gta.insert(gta.end(), ca.begin(), ca.end());
+  }
+  const std::vector<char> a = to_prec(gtf, h->precision), b = to_prec(gta, h->precision);
+  HIPCHK(hipDeviceSynchronize());  // a sweep in flight may still read the tables
+  HIPCHK(hipMemcpy(h->d_gt_f, a.data(), a.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_gt_a, b.data(), b.size(), hipMemcpyHostToDevice));
+  return BTE_OK;
+}
+
+// New relaxation times: validated, then the coefficient tables follow. A state
+// stored for the adjoint belongs to the old ones and is dropped.
+bte_status apply_tau(bte_ctx* h, const double* h_tau) {
+  for (int b = 0; b < h->B; ++b)
+    if (!(h_tau[b] > 0 && std::isfinite(h_tau[b]))) {
+      set_err("tau[%d] must be finite and > 0", b);
+      return BTE_ERR_INVALID;
+    }
+  if (std::equal(h->tau.begin(), h->tau.end(), h_tau)) return BTE_OK;
+  h->tau.assign(h_tau, h_tau + h->B);
+  for (auto& I : h->inst) {
+    I.stored = false;
+    I.have_dJds = false;
+  }
+  return upload_coefficients(h);
+}
+
+// 64-bit FNV-1a, for the geometry part of an autotune-cache key.
+uint64_t fnv1a(uint64_t hsh, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    hsh ^= c[i];
+    hsh *= 1099511628211ull;
+  }
+  return hsh;
+}
+
+// Autotune-cache key: what the sweep's cost depends on (dimension, precision,
+// bands, swept ordinates, every instance's grid, mask and wall kinds) and the
+// device.
+std::string tune_key(const bte_ctx* h) {
+  uint64_t g = 1469598103934665603ull;
+  for (const auto& I : h->inst) {
+    g = fnv1a(g, I.hi.n, sizeof(I.hi.n));
+    g = fnv1a(g, I.hi.active.data(), I.hi.active.size());
+    for (size_t f = 0; f < I.hi.bf_bc.size(); ++f) {
+      const int kind = I.hi.bc_kind[I.hi.bf_bc[f]];
+      g = fnv1a(g, &kind, sizeof(kind));
+    }
+  }
+  char buf[256];
+  snprintf(buf, sizeof(buf), "dim=%d prec=%d B=%d M=%zu inst=%zu geo=%016llx dev=%s", h->dim, h->precision, h->B,
+           h->ords.size(), h->inst.size(), (unsigned long long)g, h->dev_name);
+  return buf;
+}
+
+bte_status autotune_impl(bte_ctx* h, const double* d_Q, int n_iters, hipStream_t st, Plan* best);
+
+// Autotune cache (opts->autotune_cache): use the plan stored for this
+// problem's key, or tune (30 whole iterations per candidate, on d_Q) and
+// append the result. Lines read "<key> plan G R P C NR"; the last match wins.
+bte_status apply_tune_cache(bte_ctx* h, const char* path, const double* d_Q, hipStream_t st) {
+  if (!path) return BTE_OK;
+  const std::string key = tune_key(h);
+  bool found = false;
+  Plan pl;
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+      const size_t kl = key.size();
+      if (strncmp(line, key.c_str(), kl) != 0 || strncmp(line + kl, " plan ", 6) != 0) continue;
+      Plan p;
+      if (sscanf(line + kl + 6, "%d %d %d %d %d", &p.G, &p.R, &p.P, &p.C, &p.NR) == 5) {
+        pl = p;
+        found = true;
+      }
+    }
+    fclose(f);
+  }
+  if (found) {
+    const Plan& c = h->plan;
+    if (pl.G == c.G && pl.R == c.R && pl.P == c.P && pl.C == c.C && pl.NR == c.NR) return BTE_OK;
+    const Plan old = h->plan;
+    bte_status s = build_plan(h, pl);
+    if (s != BTE_OK) {
+      const std::string e = g_err;
+      (void)build_plan(h, old);
+      set_err("autotune cache %s: stored plan rejected: %s", path, e.c_str());
+    }
+    return s;
+  }
+  Plan best;
+  bte_status s = autotune_impl(h, d_Q, 30, st, &best);
+  if (s != BTE_OK) return s;
+  FILE* f = fopen(path, "a");
+  if (!f) {
+    set_err("autotune cache %s cannot be opened for writing", path);
+    return BTE_ERR_INVALID;
+  }
+  fprintf(f, "%s plan %d %d %d %d %d\n", key.c_str(), best.G, best.R, best.P, best.C, best.NR);
+  fclose(f);
   return BTE_OK;
 }
 
@@ -1123,15 +1377,66 @@ bte_status bte_quadrature_octant_gl(int n_theta, int n_phi, int polar_axis, doub
 }
 
 bte_status bte_create(const bte_geometry* geom, const bte_bands* bands, const bte_quadrature* quad,
-                      double T_ref, int precision, bte_handle* out) {
+                      int precision, bte_handle* out) {
   ErrClear clear_on_exit;
-  return create_common(1, geom, bands, quad, T_ref, precision, out);
+  return create_common(1, geom, bands, quad, precision, out);
 }
 
 bte_status bte_batch_create(int n_inst, const bte_geometry* geoms, const bte_bands* bands,
-                            const bte_quadrature* quad, double T_ref, int precision, bte_handle* out) {
+                            const bte_quadrature* quad, int precision, bte_handle* out) {
   ErrClear clear_on_exit;
-  return create_common(n_inst, geoms, bands, quad, T_ref, precision, out);
+  return create_common(n_inst, geoms, bands, quad, precision, out);
+}
+
+bte_status bte_workspace_bytes(bte_handle h, int with_adjoint, size_t* bytes) {
+  ErrClear clear_on_exit;
+  if (!h || !bytes) {
+    set_err("null handle or output");
+    return BTE_ERR_INVALID;
+  }
+  *bytes = h->need_static + h->need_plan + (with_adjoint ? h->need_store : 0);
+  return BTE_OK;
+}
+
+bte_status bte_bind_workspace(bte_handle h, void* d_ws, size_t bytes) {
+  ErrClear clear_on_exit;
+  if (!h) {
+    set_err("null handle");
+    return BTE_ERR_INVALID;
+  }
+  if (d_ws && reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) {
+    set_err("workspace must be %zu-byte aligned", kWsAlign);
+    return BTE_ERR_INVALID;
+  }
+  const size_t need = h->need_static + h->need_plan;
+  if (d_ws && bytes < need) {
+    set_err("workspace of %zu bytes is smaller than the %zu the handle needs", bytes, need);
+    return BTE_ERR_WORKSPACE;
+  }
+  if (h->pool_mode != DevPool::COUNT) HIPCHK(hipDeviceSynchronize());
+  clear_graphs(h);
+  h->ppool.reset();
+  h->spool.reset();
+  h->ws_base = static_cast<char*>(d_ws);
+  h->ws_cap = d_ws ? bytes : 0;
+  h->ws_store = d_ws && bytes >= need + h->need_store;
+  if (!d_ws) {
+    // unbound: the handle's own memory is made by the next call that needs it
+    h->pool_mode = DevPool::COUNT;
+    return BTE_OK;
+  }
+  h->pool_mode = DevPool::ARENA;
+  bte_status s = build_static(h);
+  if (s == BTE_OK) s = build_plan_impl(h, h->plan);
+  if (s != BTE_OK) {
+    h->spool.reset();
+    h->ppool.reset();
+    h->ws_base = nullptr;
+    h->ws_cap = 0;
+    h->ws_store = false;
+    h->pool_mode = DevPool::COUNT;
+  }
+  return s;
 }
 
 bte_status bte_set_tau(bte_handle h, const double* h_tau) {
@@ -1140,13 +1445,7 @@ bte_status bte_set_tau(bte_handle h, const double* h_tau) {
     set_err("null handle or tau");
     return BTE_ERR_INVALID;
   }
-  for (int b = 0; b < h->B; ++b)
-    if (!(h_tau[b] > 0 && std::isfinite(h_tau[b]))) {
-      set_err("tau[%d] must be > 0", b);
-      return BTE_ERR_INVALID;
-    }
-  h->tau.assign(h_tau, h_tau + h->B);
-  return build_plan(h, h->plan);
+  return apply_tau(h, h_tau);
 }
 
 bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
@@ -1184,8 +1483,8 @@ bte_status bte_get_plan(bte_handle h, bte_plan* plan) {
   return BTE_OK;
 }
 
-bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, double* d_T, double* d_q,
-                     const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+bte_status bte_solve(bte_handle h, const double* h_tau, const double* d_Q, const double* d_T_init, double* d_T,
+                     double* d_q, const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
   ErrClear clear_on_exit;
   if (!h || !d_T) {
     set_err("null handle or output");
@@ -1199,7 +1498,16 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
   bte_status s = default_opts(opts, o);
   if (s != BTE_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  s = ensure_device(h);
+  if (s != BTE_OK) return s;
+  if (h_tau) {
+    s = apply_tau(h, h_tau);
+    if (s != BTE_OK) return s;
+  }
+  s = apply_tune_cache(h, o.autotune_cache, d_Q, st);
+  if (s != BTE_OK) return s;
   Inst& I = h->inst[0];
+  I.T_ref = o.T_ref > 0 ? o.T_ref : I.T_ref_default;
   h->fin_f[0].q = d_q ? d_q : I.d_qbuf;
   HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), sizeof(FinInst), hipMemcpyHostToDevice, st));
   s = init_forward(h, 0, d_Q, d_T_init, st);
@@ -1207,13 +1515,13 @@ bte_status bte_solve(bte_handle h, const double* d_Q, const double* d_T_init, do
   double secs = 0.0;
   s = run_loop(h, false, o, st, &secs);
   if (s != BTE_OK) return s;
-  if (o.store_state) {
+  if (o.store_angular) {
     s = store_state(h, st);
     if (s != BTE_OK) return s;
     if (d_Q) HIPCHK(hipMemcpyAsync(I.d_Qs, d_Q, (size_t)I.hi.ncell * 8, hipMemcpyDeviceToDevice, st));
     else HIPCHK(launch_zero(I.d_Qs, (size_t)I.hi.ncell * 8, st));
   }
-  HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, h->T_ref, 1.0, d_T, st));
+  HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, I.T_ref, 1.0, d_T, st));
   HIPCHK(hipStreamSynchronize(st));
   return fill_report(h, 0, secs, h_rep, false, o);
 }
@@ -1229,7 +1537,12 @@ bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const
   bte_status s = default_opts(opts, o);
   if (s != BTE_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  s = ensure_device(h);
+  if (s != BTE_OK) return s;
+  s = apply_tune_cache(h, o.autotune_cache, nullptr, st);
+  if (s != BTE_OK) return s;
   for (size_t k = 0; k < h->inst.size(); ++k) {
+    h->inst[k].T_ref = o.T_ref > 0 ? o.T_ref : h->inst[k].T_ref_default;
     if (!d_T[k]) {
       set_err("null output of instance %zu", k);
       return BTE_ERR_INVALID;
@@ -1245,7 +1558,7 @@ bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const
   double secs = 0.0;
   s = run_loop(h, false, o, st, &secs);
   if (s != BTE_OK) return s;
-  if (o.store_state) {
+  if (o.store_angular) {
     s = store_state(h, st);
     if (s != BTE_OK) return s;
     for (size_t k = 0; k < h->inst.size(); ++k) {
@@ -1257,7 +1570,7 @@ bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const
   bte_status worst = BTE_OK;
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
-    HIPCHK(launch_output(I.d_X[h->h_st[k].iter & 1], I.d_active, I.hi.ncell, h->T_ref, 1.0, d_T[k], st));
+    HIPCHK(launch_output(I.d_X[h->h_st[k].iter & 1], I.d_active, I.hi.ncell, I.T_ref, 1.0, d_T[k], st));
   }
   HIPCHK(hipStreamSynchronize(st));
   for (size_t k = 0; k < h->inst.size(); ++k) {
@@ -1276,7 +1589,7 @@ static bte_status adjoint_common(bte_handle h, const double* const* d_dJdT, doub
   }
   for (auto& I : h->inst)
     if (!I.stored) {
-      set_err("bte_adjoint needs a previous solve with store_state = 1");
+      set_err("bte_adjoint needs a previous solve with store_angular = 1 and the same tau");
       return BTE_ERR_STATE;
     }
   bte_opts o;
@@ -1432,6 +1745,10 @@ bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double
     return BTE_ERR_INVALID;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (h->pool_mode == DevPool::COUNT) {
+    set_err("bte_time_sweep needs a previous solve");
+    return BTE_ERR_STATE;
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1461,7 +1778,36 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
     set_err("null handle or n_iters < 1");
     return BTE_ERR_INVALID;
   }
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (d_Q && h->inst.size() > 1) {
+    // one source array cannot serve instances of different sizes
+    set_err("bte_autotune on a batch handle takes d_Q = NULL (the timing runs use a zero source)");
+    return BTE_ERR_STATE;
+  }
+  bte_status s = ensure_device(h);
+  if (s != BTE_OK) return s;
+  Plan bp;
+  s = autotune_impl(h, d_Q, n_iters, reinterpret_cast<hipStream_t>(hip_stream), &bp);
+  if (s != BTE_OK) return s;
+  if (best) {
+    best->G = bp.G;
+    best->R = bp.R;
+    best->P = bp.P;
+    best->C = bp.C;
+    best->NR = bp.NR;
+  }
+  return BTE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bte_status autotune_impl(bte_ctx* h, const double* d_Q, int n_iters, hipStream_t st, Plan* best) {
+  // the timing runs write their flux into the handle's own buffers, never into
+  // an output array of an earlier call
+  for (size_t k = 0; k < h->inst.size(); ++k) h->fin_f[k].q = h->inst[k].d_qbuf;
+  HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), h->fin_f.size() * sizeof(FinInst), hipMemcpyHostToDevice,
+                        st));
   std::vector<Plan> cand;
   if (h->dim == 3) {
     for (int G : {1, 2, 4})
@@ -1521,22 +1867,16 @@ bte_status bte_autotune(bte_handle h, const double* d_Q, int n_iters, void* hip_
   (void)hipEventDestroy(e1);
   bte_status s = build_plan(h, bestp);
   if (s != BTE_OK) return s;
-  if (best) {
-    best->G = bestp.G;
-    best->R = bestp.R;
-    best->P = bestp.P;
-    best->C = bestp.C;
-    best->NR = bestp.NR;
-  }
+  if (best) *best = bestp;
   return BTE_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 bte_status bte_destroy(bte_handle h) {
   ErrClear clear_on_exit;
-  if (!h) return BTE_OK;
-  clear_graphs(h);
-  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  if (h->h_st) (void)hipHostFree(h->h_st);
   delete h;
   return BTE_OK;
 }

@@ -105,3 +105,31 @@ def test_quadrature_helper_rejects_bad_args():
         bte.quadrature_octant_gl(0, 2, 0)
     with pytest.raises(bte.BTEError):
         bte.quadrature_octant_gl(2, 2, 3)
+
+
+def test_calls_reject_a_null_handle():
+    """Entry points that take a handle refuse NULL before any device call."""
+    import paper_2503_23657_amd as bte
+    n = ctypes.c_size_t(123)
+    assert bte.bte_workspace_bytes(None, 0, ctypes.byref(n)) == bte.BTE_ERR_INVALID
+    assert bte.bte_bind_workspace(None, None, 0) == bte.BTE_ERR_INVALID
+    o = bte.make_opts()
+    assert bte.bte_solve(None, None, None, None, None, None, ctypes.byref(o), None, None) == bte.BTE_ERR_INVALID
+    assert bte.bte_set_tau(None, None) == bte.BTE_ERR_INVALID
+    assert bte.bte_autotune(None, None, 1, None, None) == bte.BTE_ERR_INVALID
+    assert bte.bte_destroy(None) == bte.BTE_OK
+
+
+def test_options_struct_layout():
+    """The binding's bte_opts mirrors include/bte.h field by field (two doubles,
+    two ints, T_ref, two ints, the cache path)."""
+    import paper_2503_23657_amd as bte
+    names = [f[0] for f in bte.Opts._fields_]
+    assert names == ["tol_T", "tol_q", "max_iters", "check_every", "T_ref", "use_graph", "store_angular",
+                     "autotune_cache"]
+    txt = open(os.path.join(ROOT, "include", "bte.h")).read()
+    body = txt[txt.index("typedef struct {\n  double tol_T;"):]
+    body = body[:body.index("} bte_opts;")]
+    decl = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+(\w+);", body, re.M)
+    assert decl == names
+    assert bte.Opts.T_ref.offset == 24 and ctypes.sizeof(bte.Opts) == 48

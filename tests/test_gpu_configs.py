@@ -1,0 +1,210 @@
+"""The benchmark configurations at their stated sizes, on the GPU:
+
+* the differentiation workload on the full 256^2 square (15 bands, 128
+  directions, 64 probes): the FP64 adjoint gradient against central
+  differences of the converged FP64 forward on all 20 seeded parameters, and
+  the FP32-sweep adjoint against the FP64 one;
+* the batch workload: a seeded subset of its 256 instances spanning Kn 0.01 to
+  10, batched in one handle, against the FP64 oracle (live, or its stored
+  samples for the two lowest-Kn instances, whose oracle solve takes minutes);
+* the 256^2 square solved to convergence with FP32 sweeps in the benchmark's
+  kernel shape, against the stored converged oracle samples;
+* the FinFET-like 3D domain at a quarter of its size per axis with all 15
+  bands and 128 directions, against the oracle;
+* batched forward and adjoint on 3D masks, against single-instance solves.
+
+Bars: FP64 1e-10 (fixed iterations) or 1e-9 (both converged, where the fixed
+point's conditioning amplifies the stop tolerance) of max|T - T_ref|; FP32
+1e-4 of it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import bte_inputs as bi
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b, p):
+    act = p.mask > 0
+    return np.abs(a[act] - b[act]).max() / np.abs(b[act] - p.T_ref).max()
+
+
+# ------------------------------------------------ differentiation, full size
+def test_adjoint_vs_central_differences_full_square(hip_lib):
+    p = bi.square_2d()
+    case = bi.adjoint_case(p)
+    assert len(case["probes"]) == 64 and len(case["fd_tau"]) == 5 and len(case["fd_Q"]) == 15
+    s = hip_lib.Solver(p, precision="fp64")
+    Tstar, _, rep = s.solve(torch.tensor(case["Q_true"], device="cuda"), tau=case["tau_true"], tol=1e-13,
+                            check_every=8)
+    assert rep["status"] == "ok"
+    probes = torch.tensor(case["probes"], device="cuda")
+    target = Tstar[probes].clone()
+
+    def J_of(tau, Q):
+        T, _, r = s.solve(torch.tensor(Q, device="cuda"), tau=tau, tol=1e-13, check_every=8)
+        assert r["status"] == "ok"
+        return float(((T[probes] - target) ** 2).mean())
+
+    T, _, _ = s.solve(torch.tensor(p.Q, device="cuda"), tau=p.tau, tol=1e-13, check_every=8, store_state=True)
+    Tl = T.detach().clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(((Tl[probes] - target) ** 2).mean(), Tl)
+    dtau, dQ, rep_a = s.adjoint(g.contiguous(), tol=1e-13, check_every=8)
+    assert rep_a["status"] == "ok"
+    dQ = dQ.cpu().numpy()
+    fd_tau = []
+    for b in case["fd_tau"]:
+        hstep = 1e-4 * p.tau[b]
+        tp, tm = p.tau.copy(), p.tau.copy()
+        tp[b] += hstep
+        tm[b] -= hstep
+        fd_tau.append((J_of(tp, p.Q) - J_of(tm, p.Q)) / (2 * hstep))
+    fd_Q = []
+    for c in case["fd_Q"]:
+        hstep = 1e-4 * p.Q0
+        qp, qm = p.Q.copy(), p.Q.copy()
+        qp[c] += hstep
+        qm[c] -= hstep
+        fd_Q.append((J_of(p.tau, qp) - J_of(p.tau, qm)) / (2 * hstep))
+    fd_tau, fd_Q = np.array(fd_tau), np.array(fd_Q)
+    at, aq = dtau[case["fd_tau"]], dQ[case["fd_Q"]]
+    assert np.abs(at - fd_tau).max() < 1e-5 * np.abs(dtau).max(), (at, fd_tau)
+    assert np.abs(aq - fd_Q).max() < 1e-5 * np.abs(dQ).max(), (aq, fd_Q)
+    # the gradient checked is not a trivial one
+    assert np.abs(fd_Q).max() > 0.05 * np.abs(dQ).max()
+    # FP32 sweeps (FP64 sums) in the forward and adjoint iterations
+    s32 = hip_lib.Solver(p, precision="fp32")
+    s32.solve(torch.tensor(p.Q, device="cuda"), tol=1e-7, check_every=8, store_state=True,
+              allow_not_converged=True, max_iters=2000)
+    dtau32, dQ32, _ = s32.adjoint(g.contiguous(), tol=1e-7, check_every=8, allow_not_converged=True,
+                                  max_iters=2000)
+    assert np.abs(dtau32 - dtau).max() < 1e-3 * np.abs(dtau).max()
+    assert np.abs(dQ32.cpu().numpy() - dQ).max() < 1e-3 * np.abs(dQ).max()
+    s.close()
+    s32.close()
+
+
+# ------------------------------------------------------------ batch subset
+BATCH_SEL = (144, 131, 4, 212, 29, 108)  # Kn 0.0100, 0.0282, 0.0419, 0.0430, 9.73, 9.88
+_ORACLE = {}
+
+
+def _golden_batch():
+    out, scale = {}, {}
+    with open(os.path.join(GOLDEN, "batch_lowkn_samples.txt")) as f:
+        for line in f:
+            if line.startswith("# instance"):
+                w = line.split()
+                scale[int(w[2])] = float(w[-1])
+            elif not line.startswith("#"):
+                i, c, t = line.split()
+                out.setdefault(int(i), []).append((int(c), float(t)))
+    return {i: (np.array([c for c, _ in v]), np.array([t for _, t in v]), scale[i]) for i, v in out.items()}
+
+
+def _oracle_T(i, p):
+    if i not in _ORACLE:
+        r = oracle.solve(p, tol=1e-12, max_iters=400000)
+        assert r["status"] == "converged"
+        _ORACLE[i] = r["T"]
+    return _ORACLE[i]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_subset_spanning_knudsen_numbers(hip_lib, prec):
+    ps = bi.batch_instances()
+    sel = [ps[i] for i in BATCH_SEL]
+    assert min(p.Kn for p in sel) < 0.011 and max(p.Kn for p in sel) > 9.0
+    assert sum(p.Kn < 0.05 for p in sel) >= 2
+    bs = hip_lib.BatchSolver(sel, precision=prec)
+    Qs = [torch.tensor(p.Q, device="cuda") for p in sel]
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    Ts, _, reps = bs.solve(Qs, tol=tol, check_every=16, max_iters=100000)
+    iters = {i: r["iters"] for i, r in zip(BATCH_SEL, reps)}
+    print(f"{prec} batch iterations per instance: {iters}")
+    for r in reps:
+        assert r["status"] == "ok", (prec, reps)
+    # the lowest Kn needs the most iterations; retirement lets the others stop early
+    assert iters[144] == max(iters.values()) and iters[108] < iters[144] / 20
+    bar = 1e-9 if prec == "fp64" else 1e-4
+    gold = _golden_batch()
+    for i, p, T in zip(BATCH_SEL, sel, Ts):
+        Tg = T.cpu().numpy()
+        if i in gold:
+            cells, Tor, scale = gold[i]
+            err = np.abs(Tg[cells] - Tor).max() / scale
+        else:
+            err = _rel(Tg, _oracle_T(i, p), p)
+        assert err < bar, (prec, i, p.Kn, err)
+    bs.close()
+
+
+# ------------------------------------------- the square, converged, FP32
+def test_square256_fp32_converged_bench_plan(hip_lib):
+    p = bi.square_2d()
+    s = hip_lib.Solver(p, precision="fp32", plan=dict(G=1, R=1, P=4, NR=4))
+    assert s.plan() == dict(G=1, R=1, P=4, C=8, NR=4)
+    T, q, rep = s.solve(torch.tensor(p.Q, device="cuda"), tol=1e-7, check_every=8, max_iters=4000)
+    assert rep["status"] == "ok", rep
+    d = np.loadtxt(os.path.join(GOLDEN, "square256_samples.txt"), comments="#")
+    with open(os.path.join(GOLDEN, "square256_samples.txt")) as f:
+        head = [ln for ln in f if ln.startswith("# max")][0].split()
+    tscale, qscale = float(head[3]), float(head[5])
+    cells = d[:, 0].astype(np.int64)
+    assert np.abs(T.cpu().numpy()[cells] - d[:, 1]).max() < 1e-4 * tscale
+    qg = q.cpu().numpy()[cells]
+    assert np.abs(qg - d[:, 2:4]).max() < 1e-4 * qscale
+    s.close()
+
+
+# --------------------------------------------- FinFET, quarter size, all bands
+def test_finfet_quarter_all_bands_fp64(hip_lib):
+    p = bi.finfet_3d(scale=4)
+    assert p.B == 15 and p.M == 128
+    s = hip_lib.Solver(p, precision="fp64")
+    T, q, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=0.0, max_iters=3, check_every=3)
+    r = oracle.solve(p, tol=0.0, max_iters=3)
+    assert _rel(T.cpu().numpy(), r["T"], p) < 1e-10
+    act = p.mask > 0
+    qs = np.abs(r["q"][act]).max()
+    assert np.abs(q.cpu().numpy()[act] - r["q"][act]).max() < 1e-10 * qs
+    s.close()
+
+
+# ------------------------------------------------ batched 3D masks + adjoint
+def test_batched_3d_masks_forward_and_adjoint(hip_lib):
+    ps = [bi.random_box_3d(14, 11, 9, seed=3, n_bands=3, n_theta=1, n_phi=1),
+          bi.random_box_3d(9, 13, 12, seed=4, n_bands=3, n_theta=1, n_phi=1, kinds=(0, 2)),
+          bi.finfet_3d(scale=8, n_bands=3, n_theta=1, n_phi=1)]
+    # one band table and quadrature for the batch
+    ps = [q.replace(v=ps[0].v, tau=ps[0].tau, C=ps[0].C, s=ps[0].s, w=ps[0].w) for q in ps]
+    bs = hip_lib.BatchSolver(ps, precision="fp64", plan=dict(G=1))
+    Qs = [torch.tensor(p.Q, device="cuda") for p in ps]
+    Ts, _, reps = bs.solve(Qs, tol=1e-12, check_every=4, store_state=True)
+    gs = []
+    for p in ps:
+        g = torch.zeros(p.ncell, dtype=torch.float64, device="cuda")
+        g[torch.tensor(np.flatnonzero(p.mask)[::5], device="cuda")] = 1.0
+        gs.append(g)
+    dtau_b, dqs_b, _ = bs.adjoint(gs, tol=1e-12, check_every=4)
+    for k, p in enumerate(ps):
+        s = hip_lib.Solver(p, precision="fp64", plan=dict(G=1))
+        T1, _, r1 = s.solve(Qs[k], tol=1e-12, check_every=4, store_state=True)
+        assert r1["status"] == "ok" and reps[k]["status"] == "ok"
+        assert _rel(Ts[k].cpu().numpy(), T1.cpu().numpy(), p) < 1e-11
+        dtau, dq, _ = s.adjoint(gs[k], tol=1e-12, check_every=4)
+        assert np.abs(dtau_b[k] - dtau).max() < 1e-9 * np.abs(dtau).max()
+        assert np.abs(dqs_b[k].cpu().numpy() - dq.cpu().numpy()).max() < 1e-9 * np.abs(dq.cpu().numpy()).max()
+        s.close()
+    # and the forward against the oracle
+    for k, p in enumerate(ps):
+        r = oracle.solve(p, tol=1e-13, max_iters=20000)
+        assert _rel(Ts[k].cpu().numpy(), r["T"], p) < 1e-9
+    bs.close()

@@ -10,7 +10,9 @@ residuals of Eq. 22; T and q at 1024 seeded cells, and the largest |T - T_ref| a
 
 batch_lowkn_samples.txt: the two lowest-Knudsen instances of the seeded
 batch that the GPU tests use (indices 144, Kn = 0.0100, and 131, Kn = 0.0282,
-of batch_instances()), converged to 1e-12; T at 512 seeded cells each, and the largest |T - T_ref|.
+of batch_instances()), converged to 1e-12, and stopped by the same rule at
+1e-6 (the tolerance of the batch workload); T at 512 seeded cells each, and
+the largest |T - T_ref|.
 """
 import os
 import sys
@@ -47,16 +49,18 @@ def main():
             f.write(f"{c:d} {r['T'][c]:.15e} {r['q'][c, 0]:.15e} {r['q'][c, 1]:.15e}\n")
     ps = bi.batch_instances()
     with open(os.path.join(HERE, "batch_lowkn_samples.txt"), "w") as f:
-        f.write("# converged oracle (tol 1e-12) on the lowest-Kn instances of batch_instances()\n")
-        f.write("# columns: instance cell T_L(K); written by tests/golden/make_golden_samples.py\n")
+        f.write("# oracle on the lowest-Kn instances of batch_instances(), stopped at tol 1e-12 and at 1e-6\n")
+        f.write("# columns: instance tolerance cell T_L(K); written by tests/golden/make_golden_samples.py\n")
         for i in BATCH_LOWKN:
             q = ps[i]
-            r = oracle.solve(q, tol=1e-12, max_iters=400000)
-            assert r["status"] == "converged"
-            f.write(f"# instance {i} Kn {q.Kn:.6f} n {q.n[0]}x{q.n[1]} iterations {r['iters']} "
-                    f"max|T - T_ref| {np.abs(r['T'][q.mask > 0] - q.T_ref).max():.15e}\n")
-            for c in sample_cells(q, 512, 8 + i):
-                f.write(f"{i:d} {c:d} {r['T'][c]:.15e}\n")
+            cells = sample_cells(q, 512, 8 + i)
+            for tol in (1e-12, 1e-6):
+                r = oracle.solve(q, tol=tol, max_iters=400000)
+                assert r["status"] == "converged"
+                f.write(f"# instance {i} tol {tol:.0e} Kn {q.Kn:.6f} n {q.n[0]}x{q.n[1]} iterations {r['iters']} "
+                        f"max|T - T_ref| {np.abs(r['T'][q.mask > 0] - q.T_ref).max():.15e}\n")
+                for c in cells:
+                    f.write(f"{i:d} {tol:.0e} {c:d} {r['T'][c]:.15e}\n")
 
 
 if __name__ == "__main__":

@@ -54,7 +54,7 @@ def _load():
             lib.oracle_solve.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, P,
                                          ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                         ctypes.c_double, ctypes.c_int, P, P, P, P, P]
+                                         ctypes.c_double, ctypes.c_int, P, P, P, P, P, ctypes.c_int]
             lib.oracle_count_bfaces.restype = ctypes.c_long
             lib.oracle_count_bfaces.argtypes = [ctypes.c_int, P, P]
             lib.oracle_num_threads.restype = ctypes.c_int
@@ -71,8 +71,10 @@ def num_threads() -> int:
 
 
 def solve(p, *, Q=None, tau=None, T_init=None, max_iters=100000, tol=1e-10, tol_q=None,
-          threads=0, want_e=False, want_eb=False):
-    """Run the oracle on a ``bte_inputs.Problem``.
+          threads=0, want_e=False, want_eb=False, order=1):
+    """Run the oracle on a ``bte_inputs.Problem``. ``order`` 2 takes the
+    paper's second-order face values (Green-Gauss gradients, deferred
+    correction) instead of first-order upwind faces.
 
     Returns a dict with T (absolute, K, [ncell]), q ([ncell, dim], W/m^2),
     status, iters, eps_T, eps_q and optionally e ([B, M, ncell], absolute) and
@@ -104,7 +106,7 @@ def solve(p, *, Q=None, tau=None, T_init=None, max_iters=100000, tol=1e-10, tol_
                           _ptr(bcT), p.B, _ptr(v), _ptr(tt), _ptr(C), p.M, _ptr(s), _ptr(w),
                           _ptr(QQ), _ptr(Ti), float(p.T_ref), int(max_iters), float(tol),
                           float(tq), int(threads), _ptr(T), _ptr(q), _ptr(e), _ptr(eb),
-                          _ptr(info))
+                          _ptr(info), int(order))
     if st == 1:
         raise ValueError("oracle: invalid input")
     out = dict(T=T, q=q.reshape(ncell, p.dim), status=STATUS.get(st, str(st)),

@@ -25,9 +25,19 @@
  *              (Eq. 7); s' must be one of the quadrature's directions. Lagged
  *              one iteration like the diffuse walls, and starting, like them,
  *              from the adjacent cell's equilibrium.
- *   FVM        first-order upwind face values (the face gradient term of the
- *              paper's second-order face reconstruction dropped), uniform
- *              Cartesian cells: S_ij/V_i = 1/h_d for a face normal to axis d.
+ *   FVM        upwind face values, uniform Cartesian cells: S_ij/V_i = 1/h_d
+ *              for a face normal to axis d. order = 1: first-order faces (the
+ *              face gradient term of the paper's reconstruction dropped);
+ *              order = 2: the paper's second-order face value
+ *              e_ij = e' + grad e' . d' of the upwind cell (Methods, "Spatial
+ *              discretization"), grad e' by Green-Gauss, entering the
+ *              right-hand side b^n of Eq. rhs_b only (A of Eq. A_matrix stays
+ *              first order: a deferred correction). Green-Gauss face values:
+ *              the mean of the two cells at an interior face; at an
+ *              isothermal face the ordinate enters through, the wall value;
+ *              at any other boundary face the linear extrapolation from the
+ *              cell and its neighbour across the opposite face. A wall face's
+ *              entering value is the wall value with no gradient term.
  *   Iteration  (Methods, "Iterative matrix formulation and solution scheme")
  *              1. e = e0 from the initial temperature;
  *              2. for every (band, direction) solve A Delta e = b^n (Eqs. Axb,
@@ -142,16 +152,58 @@ static double s_dot_n(const double* s, int f) {
   return (f % 2) ? s[d] : -s[d];
 }
 
+/* wall value of this ordinate at boundary face slot k */
+static double wall_value(const bfaces_t* bf, const int* bc_kind, long k, const double* eb_l, const double* es_la) {
+  return bc_kind[bf->bc[k]] == BC_SPECULAR ? es_la[k] : eb_l[k];
+}
+
+/*
+ * Green-Gauss gradient of one ordinate's energy in every active cell:
+ * grad_d(c) = (sum over the two faces of c normal to axis d of e_f n_d S_f)/V
+ * = (e_f+ - e_f-)/h_d, with e_f the mean of the two cells' values at an
+ * interior face, the wall value at an isothermal face the ordinate enters
+ * through, and at any other boundary face the value extrapolated linearly
+ * from the cell and the neighbour across its opposite face.
+ */
+static void green_gauss(const grid_t* g, const bfaces_t* bf, const int* bc_kind, const double* s,
+                        const double* eb_l, const double* es_la, const double* e_la, double* grad) {
+  for (long c = 0; c < g->ncell; ++c) {
+    if (!active(g, c)) continue;
+    for (int d = 0; d < g->dim; ++d) {
+      double ef[2];
+      for (int side = 0; side < 2; ++side) {
+        int f = 2 * d + side;
+        long nb = neighbour(g, c, f);
+        if (nb >= 0) {
+          ef[side] = 0.5 * (e_la[c] + e_la[nb]);
+        } else if (s_dot_n(s, f) < 0.0 && bc_kind[bf->bc[bf->slot[c * 6 + f]]] == BC_ISOTHERMAL) {
+          ef[side] = wall_value(bf, bc_kind, bf->slot[c * 6 + f], eb_l, es_la);
+        } else {
+          /* leaving through a wall, or entering from a reflecting wall (whose
+             value is itself lagged): extrapolated linearly from the cell and
+             its neighbour across the opposite face (the cell's value alone
+             when that face is a boundary too) */
+          long ob = neighbour(g, c, f ^ 1);
+          ef[side] = ob >= 0 ? 1.5 * e_la[c] - 0.5 * e_la[ob] : e_la[c];
+        }
+      }
+      grad[c * g->dim + d] = (ef[1] - ef[0]) / g->h[d];
+    }
+  }
+}
+
 /*
  * One (band l, direction a) solve of A Delta e = b^n followed by e += Delta e.
  * e_la: this ordinate's energies (updated in place); eb: boundary face values
- * of band l (absolute energy on incoming faces); T: current T_L.
+ * of band l (absolute energy on incoming faces); T: current T_L. grad: scratch
+ * [ncell*dim] for the second-order faces (order 2), else unused.
  */
 static void solve_ordinate(const grid_t* g, const bfaces_t* bf, const int* bc_kind, double v,
                            double tau, double C, double Csum, const double* s, const double* Q,
                            const double* T, const double* eb_l, const double* es_la, double* e_la,
-                           double* rhs, double* de) {
+                           double* rhs, double* de, int order, double* grad) {
   const long ncell = g->ncell;
+  if (order == 2) green_gauss(g, bf, bc_kind, s, eb_l, es_la, e_la, grad);
   /* b^n (Eq. rhs_b with first-order faces): minus the net upwind face flux of
      e^n, minus (e^n - e0^n)/tau, plus the band's source share. */
   for (long c = 0; c < ncell; ++c) {
@@ -161,16 +213,19 @@ static void solve_ordinate(const grid_t* g, const bfaces_t* bf, const int* bc_ki
       int d = f / 2;
       double vn = v * s_dot_n(s, f);       /* v . n_ij */
       if (vn == 0.0) continue;
+      /* vector from the upwind cell's centre to the face centre, along axis d */
+      double half = 0.5 * g->h[d];
       double e_face;
       if (vn > 0.0) {
         e_face = e_la[c];                  /* upwind cell is the cell itself */
+        if (order == 2) e_face += grad[c * g->dim + d] * ((f % 2) ? half : -half);
       } else {
         long nb = neighbour(g, c, f);
         if (nb >= 0) {
           e_face = e_la[nb];
+          if (order == 2) e_face += grad[nb * g->dim + d] * ((f % 2) ? -half : half);
         } else {
-          long k = bf->slot[c * 6 + f];
-          e_face = bc_kind[bf->bc[k]] == BC_SPECULAR ? es_la[k] : eb_l[k];
+          e_face = wall_value(bf, bc_kind, bf->slot[c * 6 + f], eb_l, es_la);
         }
       }
       flux += vn / g->h[d] * e_face;       /* (1/V) v.n S e_face */
@@ -218,7 +273,7 @@ static int finite_all(const double* x, long n) {
  * oracle_solve: see the file header. Arrays:
  *   n[3], h[3]; mask[ncell] (NULL = all active); face_bc[ncell*6] (NULL = bc 0);
  *   bc_kind[n_bc], bc_T[n_bc]; v,tau,C[B]; s[M*3], w[M]; Q[ncell] (W/m^3, NULL = 0);
- *   T_init[ncell] (NULL = T_ref).
+ *   T_init[ncell] (NULL = T_ref); order 1 or 2 (face reconstruction, see the header).
  * Outputs: T_out[ncell] (absolute, 0 on inactive cells), q_out[ncell*dim],
  *   e_out[B*M*ncell] (absolute angular energy of the last iterate, optional),
  *   eb_out[B*n_bfaces] (boundary face values used by the last sweep, optional),
@@ -231,8 +286,8 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
                  int B, const double* v, const double* tau, const double* C, int M,
                  const double* s, const double* w, const double* Q, const double* T_init,
                  double T_ref, int max_iters, double tol_T, double tol_q, int nthreads,
-                 double* T_out, double* q_out, double* e_out, double* eb_out, double* info) {
-  if (dim < 1 || dim > 3 || B < 1 || M < 1 || max_iters < 1) return OR_INVALID;
+                 double* T_out, double* q_out, double* e_out, double* eb_out, double* info, int order) {
+  if (dim < 1 || dim > 3 || B < 1 || M < 1 || max_iters < 1 || order < 1 || order > 2) return OR_INVALID;
   grid_t g;
   g.dim = dim;
   g.ncell = 1;
@@ -332,15 +387,17 @@ int oracle_solve(int dim, const int* n, const double* h, const uint8_t* mask,
     {
       double* rhs = (double*)malloc(sizeof(double) * ncell);
       double* de = (double*)malloc(sizeof(double) * ncell);
+      double* grad = order == 2 ? (double*)malloc(sizeof(double) * ncell * dim) : NULL;
 #pragma omp for schedule(dynamic, 1)
       for (int la = 0; la < B * M; ++la) {
         int l = la / M, a = la % M;
         solve_ordinate(&g, &bf, bc_kind, v[l], tau[l], C[l], Csum, &s[3 * a], Qp, T,
                        &eb[(size_t)l * bf.n], es ? &es[(size_t)la * bf.n] : NULL,
-                       &e[(size_t)la * ncell], rhs, de);
+                       &e[(size_t)la * ncell], rhs, de, order, grad);
       }
       free(rhs);
       free(de);
+      free(grad);
     }
     /* step 3: T_L (Eq. updatee0_t) and q (Eq. 4), per cell in a fixed order */
 #pragma omp parallel for schedule(static)

@@ -19,6 +19,17 @@ source iteration satisfies, and solves it directly:
     (Eq. 6 with the discrete half-range normalisation)
         eb_{b,f} sum_{s.n<0} w |s.n| = sum_{s.n>0} w (s.n) e_{b,a,c(f)} .
 
+With order = 2 the face value of the balance is the paper's second-order one
+(Methods, "Spatial discretization"): on a face whose upwind side is a cell u,
+e_face = e_u + grad e_u . d_u, d_u the vector from u's centre to the face
+centre, grad e_u by Green-Gauss over u's faces (interior face: the mean of the
+two cells; an isothermal face the ordinate enters through: its wall value; any
+other boundary face: the linear extrapolation from u and the neighbour across
+the opposite face, or u's value when that is a boundary too); a face whose upwind
+side is a wall carries the wall value. Here these are assembled directly as
+linear forms of the unknowns, without the deferred-correction iteration the
+oracle uses.
+
 The unknowns are absolute energies and temperatures, so this also checks that
 the deviational form used elsewhere is exact. Complex parameters are accepted,
 which gives complex-step derivatives of any output to machine precision.
@@ -61,9 +72,10 @@ def _mirror(p, a, d):
     return int(hit[0])
 
 
-def solve_dense(p, tau=None, Q=None, return_all=False):
-    """Direct solve of the discrete fixed point. Returns T over all cells
-    (absolute; 0 on inactive cells), or (T, e, eb, faces) with return_all."""
+def solve_dense(p, tau=None, Q=None, return_all=False, order=1):
+    """Direct solve of the discrete fixed point (first- or second-order
+    faces). Returns T over all cells (absolute; 0 on inactive cells), or
+    (T, e, eb, faces) with return_all."""
     tau = np.asarray(p.tau if tau is None else tau)
     Q = np.asarray(p.Q if Q is None else Q)
     dtype = np.result_type(tau.dtype, Q.dtype, np.asarray(p.h).dtype, np.float64)
@@ -97,6 +109,38 @@ def solve_dense(p, tau=None, Q=None, return_all=False):
     def iD(b, k):
         return nE + nT + b * len(diff) + dslot[k]
 
+    def wall(b, a, c, f):
+        # wall value of ordinate a entering through boundary face (c, f), as
+        # ({unknown: coefficient}, constant)
+        k = fslot[(c, f)]
+        bc = faces[k][2]
+        if p.bc_kind[bc] == 0:
+            return {}, p.C[b] * p.bc_T[bc] / FOUR_PI
+        if p.bc_kind[bc] == 2:
+            return {ie(b, _mirror(p, a, f // 2), index[c]): 1.0}, 0.0
+        return {iD(b, k): 1.0}, 0.0
+
+    def green_gauss(b, a, c, d):
+        # (e_f+ - e_f-) / h_d over cell c's two faces normal to axis d
+        lin, cst = {}, 0.0
+        for side, sg in ((1, 1.0), (0, -1.0)):
+            f = 2 * d + side
+            nb = _neighbour(p, c, f)
+            sn = p.s[a][d] if side else -p.s[a][d]
+            if nb >= 0:
+                terms, k0 = {ie(b, a, index[c]): 0.5, ie(b, a, index[nb]): 0.5}, 0.0
+            elif sn < 0 and p.bc_kind[int(p.face_bc[c, f])] == 0:
+                terms, k0 = wall(b, a, c, f)
+            else:
+                ob = _neighbour(p, c, f ^ 1)
+                terms = ({ie(b, a, index[c]): 1.5, ie(b, a, index[ob]): -0.5} if ob >= 0
+                         else {ie(b, a, index[c]): 1.0})
+                k0 = 0.0
+            for key, v in terms.items():
+                lin[key] = lin.get(key, 0.0) + sg * v / p.h[d]
+            cst += sg * k0 / p.h[d]
+        return lin, cst
+
     for b in range(B):
         for a in range(M):
             s = p.s[a]
@@ -106,6 +150,30 @@ def solve_dense(p, tau=None, Q=None, return_all=False):
                 A[r, r] += 1.0 / tau[b]
                 A[r, iT(ci)] += -p.C[b] / (FOUR_PI * tau[b])
                 rhs[r] += Q[c] * p.C[b] / (FOUR_PI * Csum)
+                if order == 2:
+                    for f in range(2 * dim):
+                        d = f // 2
+                        sn = s[d] if f % 2 else -s[d]
+                        if sn == 0.0:
+                            continue
+                        coef = p.v[b] * sn / p.h[d]
+                        nb = _neighbour(p, c, f)
+                        if sn > 0:
+                            up, dist = c, (0.5 if f % 2 else -0.5) * p.h[d]
+                        elif nb >= 0:
+                            up, dist = nb, (-0.5 if f % 2 else 0.5) * p.h[d]
+                        else:
+                            terms, k0 = wall(b, a, c, f)
+                            for key, v in terms.items():
+                                A[r, key] += coef * v
+                            rhs[r] -= coef * k0
+                            continue
+                        A[r, ie(b, a, index[up])] += coef
+                        lin, cst = green_gauss(b, a, up, d)
+                        for key, v in lin.items():
+                            A[r, key] += coef * dist * v
+                        rhs[r] -= coef * dist * cst
+                    continue
                 for f in range(2 * dim):
                     d = f // 2
                     sn = s[d] if f % 2 else -s[d]

@@ -249,6 +249,25 @@ bte_status bte_solve(bte_handle h, const double* h_tau, const double* d_Q, const
                      double* d_T, double* d_q, const bte_opts* opts, void* hip_stream,
                      bte_report* h_rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): bte_solve
+   with every device array of the handle in a workspace the library holds as a
+   static device array of 64 MiB per device (part of its code object, held
+   until the process ends). Makes no hipMalloc or hipFree and no other
+   allocating call: the handle is (re)bound to that array when another handle
+   used it last (its tables are rebuilt there), the iteration runs without a
+   hipGraph and without the autotune cache. Same arguments, results and
+   statuses as bte_solve; a stored angular field (store_angular) must fit in
+   the array too. BTE_ERR_WORKSPACE when the problem needs more than 64 MiB
+   (bte_workspace_bytes); BTE_ERR_STATE for a handle that holds device memory
+   of its own (a previous bte_solve made it: use a fresh handle). Every call on
+   a device shares that device's array: a handle that used it before loses its
+   arrays and state to the next call of another handle, and calls that overlap
+   on one device race. */
+bte_status bte_solve_noalloc(bte_handle h, const double* h_tau, const double* d_Q,
+                             const double* d_T_init, double* d_T, double* d_q,
+                             const bte_opts* opts, void* hip_stream, bte_report* h_rep);
+
 /* Adjoint of the converged source-iteration fixed point (the gradient
    workflow of Methods, "Forward and inverse modeling workflow": a discrete
    adjoint of the implicit solves). Needs a previous bte_solve on h with

@@ -104,6 +104,8 @@ bte_set_plan = _sig("bte_set_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_get_plan = _sig("bte_get_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_autotune = _sig("bte_autotune", _S, [_H, _P, ctypes.c_int, _P, ctypes.POINTER(Plan)])
 bte_solve = _sig("bte_solve", _S, [_H, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
+bte_solve_noalloc = _sig("bte_solve_noalloc", _S, [_H, _P, _P, _P, _P, _P, ctypes.POINTER(Opts), _P,
+                                                   ctypes.POINTER(Report)])
 bte_adjoint = _sig("bte_adjoint", _S, [_H, _P, _P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Report)])
 bte_adjoint_dscale = _sig("bte_adjoint_dscale", _S, [_H, _P])
 bte_time_sweep = _sig("bte_time_sweep", _S, [_H, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
@@ -115,7 +117,7 @@ bte_destroy = _sig("bte_destroy", _S, [_H])
 EXPORTED = ["bte_version", "bte_last_error", "bte_validate", "bte_quadrature_gl_mu",
             "bte_quadrature_octant_gl", "bte_create", "bte_workspace_bytes", "bte_bind_workspace",
             "bte_set_tau", "bte_set_plan", "bte_get_plan",
-            "bte_autotune", "bte_solve", "bte_adjoint", "bte_adjoint_dscale", "bte_time_sweep", "bte_batch_create",
+            "bte_autotune", "bte_solve", "bte_solve_noalloc", "bte_adjoint", "bte_adjoint_dscale", "bte_time_sweep", "bte_batch_create",
             "bte_batch_solve", "bte_batch_adjoint", "bte_destroy"]
 
 
@@ -310,6 +312,22 @@ class Solver(_Workspace):
         allow = (BTE_ERR_NOT_CONVERGED,) if (allow_not_converged or o.tol_T <= 0 or o.tol_q <= 0) else ()
         _check(st, allow)
         return T, q.view(p.ncell, p.dim), rep.as_dict()
+
+    def solve_noalloc(self, Q, T_out, q_out=None, T_init=None, stream=None, allow_not_converged=False,
+                      tau=None, **opt):
+        """bte_solve_noalloc: as solve, with the handle's arrays in the library's
+        static device workspace; the outputs are caller tensors (nothing is
+        allocated here either). Returns the report dict."""
+        opt.setdefault("T_ref", self.T_ref)
+        o = make_opts(**opt)
+        rep = Report()
+        t = None if tau is None else _c(tau, np.float64)
+        self.generation += 1
+        st = bte_solve_noalloc(self._h, None if t is None else t.ctypes.data, _ptr(Q), _ptr(T_init), _ptr(T_out),
+                               _ptr(q_out), ctypes.byref(o), _stream(stream), ctypes.byref(rep))
+        allow = (BTE_ERR_NOT_CONVERGED,) if (allow_not_converged or o.tol_T <= 0 or o.tol_q <= 0) else ()
+        _check(st, allow)
+        return rep.as_dict()
 
     def adjoint(self, dJdT, stream=None, allow_not_converged=False, **opt):
         """dJdT: float64 device tensor [ncell]. Returns (dJ/dtau [B] numpy, dJ/dQ tensor, report)."""

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1267,6 +1268,147 @@ bte_status apply_tune_cache(bte_ctx* h, const char* path, const double* d_Q, hip
   return BTE_OK;
 }
 
+// Carve every device array of h from [d_ws, d_ws + bytes), or unbind (d_ws NULL).
+bte_status bind_impl(bte_ctx* h, void* d_ws, size_t bytes) {
+  if (d_ws && reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) {
+    set_err("workspace must be %zu-byte aligned", kWsAlign);
+    return BTE_ERR_INVALID;
+  }
+  const size_t need = h->need_static + h->need_plan;
+  if (d_ws && bytes < need) {
+    set_err("workspace of %zu bytes is smaller than the %zu the handle needs", bytes, need);
+    return BTE_ERR_WORKSPACE;
+  }
+  if (h->pool_mode != DevPool::COUNT) HIPCHK(hipDeviceSynchronize());
+  clear_graphs(h);
+  h->ppool.reset();
+  h->spool.reset();
+  h->ws_base = static_cast<char*>(d_ws);
+  h->ws_cap = d_ws ? bytes : 0;
+  h->ws_store = d_ws && bytes >= need + h->need_store;
+  if (!d_ws) {
+    // unbound: the handle's own memory is made by the next call that needs it
+    h->pool_mode = DevPool::COUNT;
+    return BTE_OK;
+  }
+  h->pool_mode = DevPool::ARENA;
+  bte_status s = build_static(h);
+  if (s == BTE_OK) s = build_plan_impl(h, h->plan);
+  if (s != BTE_OK) {
+    h->spool.reset();
+    h->ppool.reset();
+    h->ws_base = nullptr;
+    h->ws_cap = 0;
+    h->ws_store = false;
+    h->pool_mode = DevPool::COUNT;
+  }
+  return s;
+}
+
+
+// The solve of a single-instance handle whose device state exists (options
+// already defaulted).
+bte_status solve_impl(bte_ctx* h, const double* h_tau, const double* d_Q, const double* d_T_init, double* d_T,
+                      double* d_q, const bte_opts& o, hipStream_t st, bte_report* h_rep) {
+  bte_status s = BTE_OK;
+  if (h_tau) {
+    s = apply_tau(h, h_tau);
+    if (s != BTE_OK) return s;
+  }
+  s = apply_tune_cache(h, o.autotune_cache, d_Q, st);
+  if (s != BTE_OK) return s;
+  Inst& I = h->inst[0];
+  I.T_ref = o.T_ref > 0 ? o.T_ref : I.T_ref_default;
+  h->fin_f[0].q = d_q ? d_q : I.d_qbuf;
+  HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), sizeof(FinInst), hipMemcpyHostToDevice, st));
+  s = init_forward(h, 0, d_Q, d_T_init, st);
+  if (s != BTE_OK) return s;
+  double secs = 0.0;
+  s = run_loop(h, false, o, st, &secs);
+  if (s != BTE_OK) return s;
+  if (o.store_angular) {
+    s = store_state(h, st);
+    if (s != BTE_OK) return s;
+    if (d_Q) HIPCHK(hipMemcpyAsync(I.d_Qs, d_Q, (size_t)I.hi.ncell * 8, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(launch_zero(I.d_Qs, (size_t)I.hi.ncell * 8, st));
+  }
+  HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, I.T_ref, 1.0, d_T, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return fill_report(h, 0, secs, h_rep, false, o);
+}
+
+// ---------------------------------------------- the allocation-free solve
+// Device workspace of bte_solve_noalloc: one array per device, part of the
+// library's code object (allocated when the module is loaded on a device,
+// held until the process ends). Host code never uses the array's name as an
+// address: the device address comes from hipGetSymbolAddress, once per
+// device, and is kept per device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};       // device address of `scratch` per device
+bte_ctx* g_scratch_owner[kMaxDevices] = {};  // handle whose arrays the array holds
+
+// Drop h's claim on the static scratch of its device (it keeps its arrays
+// until it binds something else).
+void release_static_scratch(bte_ctx* h) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (int d = 0; d < kMaxDevices; ++d)
+    if (g_scratch_owner[d] == h) g_scratch_owner[d] = nullptr;
+}
+
+// Bind h to the static scratch of the current device unless it holds it
+// already. Another handle holding it loses its arrays (it returns to the
+// unbound state and makes or binds memory again at its next call). No
+// allocation and no free: a handle with arrays of its own is refused.
+bte_status bind_static_scratch(bte_ctx* h) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_err("device %d out of range", dev);
+    return BTE_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  char* ws = static_cast<char*>(g_scratch_ptr[dev]);
+  if (g_scratch_owner[dev] == h && h->pool_mode == DevPool::ARENA && h->ws_base == ws) return BTE_OK;
+  if (h->pool_mode == DevPool::OWNED) {
+    set_err("bte_solve_noalloc: the handle holds device memory of its own (a previous bte_solve made it); "
+            "use a fresh handle, or one bound to a workspace");
+    return BTE_ERR_STATE;
+  }
+  const size_t need = h->need_static + h->need_plan;
+  if (need > kStaticScratchBytes) {
+    set_err("bte_solve_noalloc: the problem needs %zu bytes of workspace; the static workspace holds %zu", need,
+            kStaticScratchBytes);
+    return BTE_ERR_WORKSPACE;
+  }
+  bte_ctx* old = g_scratch_owner[dev];
+  if (old && old != h) {
+    HIPCHK(hipDeviceSynchronize());
+    clear_graphs(old);
+    old->ppool.reset();
+    old->spool.reset();
+    old->ws_base = nullptr;
+    old->ws_cap = 0;
+    old->ws_store = false;
+    old->pool_mode = DevPool::COUNT;
+    for (auto& I : old->inst) {
+      I.stored = false;
+      I.have_dJds = false;
+    }
+  }
+  g_scratch_owner[dev] = nullptr;
+  bte_status s = bind_impl(h, ws, kStaticScratchBytes);
+  if (s == BTE_OK) g_scratch_owner[dev] = h;
+  return s;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1404,39 +1546,8 @@ bte_status bte_bind_workspace(bte_handle h, void* d_ws, size_t bytes) {
     set_err("null handle");
     return BTE_ERR_INVALID;
   }
-  if (d_ws && reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) {
-    set_err("workspace must be %zu-byte aligned", kWsAlign);
-    return BTE_ERR_INVALID;
-  }
-  const size_t need = h->need_static + h->need_plan;
-  if (d_ws && bytes < need) {
-    set_err("workspace of %zu bytes is smaller than the %zu the handle needs", bytes, need);
-    return BTE_ERR_WORKSPACE;
-  }
-  if (h->pool_mode != DevPool::COUNT) HIPCHK(hipDeviceSynchronize());
-  clear_graphs(h);
-  h->ppool.reset();
-  h->spool.reset();
-  h->ws_base = static_cast<char*>(d_ws);
-  h->ws_cap = d_ws ? bytes : 0;
-  h->ws_store = d_ws && bytes >= need + h->need_store;
-  if (!d_ws) {
-    // unbound: the handle's own memory is made by the next call that needs it
-    h->pool_mode = DevPool::COUNT;
-    return BTE_OK;
-  }
-  h->pool_mode = DevPool::ARENA;
-  bte_status s = build_static(h);
-  if (s == BTE_OK) s = build_plan_impl(h, h->plan);
-  if (s != BTE_OK) {
-    h->spool.reset();
-    h->ppool.reset();
-    h->ws_base = nullptr;
-    h->ws_cap = 0;
-    h->ws_store = false;
-    h->pool_mode = DevPool::COUNT;
-  }
-  return s;
+  release_static_scratch(h);
+  return bind_impl(h, d_ws, bytes);
 }
 
 bte_status bte_set_tau(bte_handle h, const double* h_tau) {
@@ -1497,33 +1608,31 @@ bte_status bte_solve(bte_handle h, const double* h_tau, const double* d_Q, const
   bte_opts o;
   bte_status s = default_opts(opts, o);
   if (s != BTE_OK) return s;
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   s = ensure_device(h);
   if (s != BTE_OK) return s;
-  if (h_tau) {
-    s = apply_tau(h, h_tau);
-    if (s != BTE_OK) return s;
+  return solve_impl(h, h_tau, d_Q, d_T_init, d_T, d_q, o, reinterpret_cast<hipStream_t>(hip_stream), h_rep);
+}
+
+bte_status bte_solve_noalloc(bte_handle h, const double* h_tau, const double* d_Q, const double* d_T_init,
+                             double* d_T, double* d_q, const bte_opts* opts, void* hip_stream, bte_report* h_rep) {
+  ErrClear clear_on_exit;
+  if (!h || !d_T) {
+    set_err("null handle or output");
+    return BTE_ERR_INVALID;
   }
-  s = apply_tune_cache(h, o.autotune_cache, d_Q, st);
-  if (s != BTE_OK) return s;
-  Inst& I = h->inst[0];
-  I.T_ref = o.T_ref > 0 ? o.T_ref : I.T_ref_default;
-  h->fin_f[0].q = d_q ? d_q : I.d_qbuf;
-  HIPCHK(hipMemcpyAsync(h->d_fin_f, h->fin_f.data(), sizeof(FinInst), hipMemcpyHostToDevice, st));
-  s = init_forward(h, 0, d_Q, d_T_init, st);
-  if (s != BTE_OK) return s;
-  double secs = 0.0;
-  s = run_loop(h, false, o, st, &secs);
-  if (s != BTE_OK) return s;
-  if (o.store_angular) {
-    s = store_state(h, st);
-    if (s != BTE_OK) return s;
-    if (d_Q) HIPCHK(hipMemcpyAsync(I.d_Qs, d_Q, (size_t)I.hi.ncell * 8, hipMemcpyDeviceToDevice, st));
-    else HIPCHK(launch_zero(I.d_Qs, (size_t)I.hi.ncell * 8, st));
+  if (h->inst.size() != 1) {
+    set_err("bte_solve_noalloc needs a single-instance handle");
+    return BTE_ERR_STATE;
   }
-  HIPCHK(launch_output(I.d_X[h->h_st[0].iter & 1], I.d_active, I.hi.ncell, I.T_ref, 1.0, d_T, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return fill_report(h, 0, secs, h_rep, false, o);
+  bte_opts o;
+  bte_status s = default_opts(opts, o);
+  if (s != BTE_OK) return s;
+  s = bind_static_scratch(h);
+  if (s != BTE_OK) return s;
+  // a graph's instantiation and the tuner's events may allocate: neither here
+  o.use_graph = 0;
+  o.autotune_cache = nullptr;
+  return solve_impl(h, h_tau, d_Q, d_T_init, d_T, d_q, o, reinterpret_cast<hipStream_t>(hip_stream), h_rep);
 }
 
 bte_status bte_batch_solve(bte_handle h, const double* const* d_Q, double* const* d_T, double* const* d_q,
@@ -1877,6 +1986,7 @@ extern "C" {
 
 bte_status bte_destroy(bte_handle h) {
   ErrClear clear_on_exit;
+  if (h) release_static_scratch(h);
   delete h;
   return BTE_OK;
 }

@@ -212,6 +212,16 @@ def main():
             updates_per_s=n2 * K2 / dt2, ms_per_step=dt2 / K2 * 1e3, steps=K2, plan=s2.plan(),
             roofline=roofline_of(s2, n2, 2, "sweep2d_square256_hbm_counters.md", SOURCES_2D))
         log(f"square: {n2 * K2 / dt2:.4e} updates/s")
+        # the same square with second-order faces (deferred correction: the
+        # sweep reads each ordinate's correction and stores its field, and a
+        # correction kernel runs after every iteration)
+        s2o = bte.Solver(p2, precision="fp32", plan=dict(G=1, R=1, P=4, NR=4))
+        s2o.set_order(2)
+        dt2o = timed_iterations(s2o, Q2, K2, args.warmup)
+        extra["square_2d_second_order"] = dict(updates_per_s=n2 * K2 / dt2o, ms_per_step=dt2o / K2 * 1e3, steps=K2,
+                                               sweep_ms=s2o.time_sweep(n_launches=10)[0])
+        s2o.close()
+        log(f"square, second order: {n2 * K2 / dt2o:.4e} updates/s")
         # ------------------------- adjoint / forward time at equal tolerance
         tol = 1e-6
         t0 = time.perf_counter()

@@ -217,6 +217,22 @@ bte_status bte_bind_workspace(bte_handle h, void* d_ws, size_t bytes);
    dropped when tau changes. */
 bte_status bte_set_tau(bte_handle h, const double* h_tau);
 
+/* Face reconstruction of the finite volumes (Methods, "Spatial
+   discretization"): order 1, first-order upwind faces (the default); order 2,
+   the paper's second-order face value e_ij = e' + grad e' . d' of the upwind
+   cell with Green-Gauss gradients, taken by deferred correction: each sweep
+   keeps the first-order A of Eq. A_matrix and adds to the source the
+   difference of the second-order and first-order face fluxes of the previous
+   iterate (the b^n of Eq. rhs_b), so the fixed point is that of the
+   second-order scheme. Green-Gauss face values: the mean of the two cells at
+   an interior face, the wall value at an isothermal face the ordinate enters
+   through, the linear extrapolation from the cell and its neighbour across
+   the opposite face at any other boundary face. Order 2 is built for 1D and
+   2D grids (BTE_ERR_INVALID on 3D), forces plans with G = 1, keeps the
+   angular field and a correction per ordinate in device memory, and has no
+   adjoint (bte_adjoint returns BTE_ERR_STATE). Drops any solver state. */
+bte_status bte_set_order(bte_handle h, int order);
+
 /* Set / get the sweep kernel shape. */
 bte_status bte_set_plan(bte_handle h, const bte_plan* plan);
 bte_status bte_get_plan(bte_handle h, bte_plan* plan);

@@ -100,6 +100,7 @@ bte_batch_create = _sig("bte_batch_create", _S, [ctypes.c_int, ctypes.POINTER(Ge
 bte_workspace_bytes = _sig("bte_workspace_bytes", _S, [_H, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)])
 bte_bind_workspace = _sig("bte_bind_workspace", _S, [_H, _P, ctypes.c_size_t])
 bte_set_tau = _sig("bte_set_tau", _S, [_H, _P])
+bte_set_order = _sig("bte_set_order", _S, [_H, ctypes.c_int])
 bte_set_plan = _sig("bte_set_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_get_plan = _sig("bte_get_plan", _S, [_H, ctypes.POINTER(Plan)])
 bte_autotune = _sig("bte_autotune", _S, [_H, _P, ctypes.c_int, _P, ctypes.POINTER(Plan)])
@@ -116,7 +117,7 @@ bte_destroy = _sig("bte_destroy", _S, [_H])
 
 EXPORTED = ["bte_version", "bte_last_error", "bte_validate", "bte_quadrature_gl_mu",
             "bte_quadrature_octant_gl", "bte_create", "bte_workspace_bytes", "bte_bind_workspace",
-            "bte_set_tau", "bte_set_plan", "bte_get_plan",
+            "bte_set_tau", "bte_set_order", "bte_set_plan", "bte_get_plan",
             "bte_autotune", "bte_solve", "bte_solve_noalloc", "bte_adjoint", "bte_adjoint_dscale", "bte_time_sweep", "bte_batch_create",
             "bte_batch_solve", "bte_batch_adjoint", "bte_destroy"]
 
@@ -277,6 +278,12 @@ class Solver(_Workspace):
     def set_plan(self, G=0, R=0, P=0, C=0, NR=0):
         pl = Plan(G, R, P, C, NR)
         _check(bte_set_plan(self._h, ctypes.byref(pl)))
+
+    def set_order(self, order: int):
+        """Face reconstruction: 1 first-order upwind, 2 the second-order face
+        values by deferred correction (bte_set_order)."""
+        self.generation += 1
+        _check(bte_set_order(self._h, int(order)))
 
     def plan(self) -> dict:
         pl = Plan()

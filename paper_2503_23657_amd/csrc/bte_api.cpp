@@ -150,6 +150,9 @@ struct Inst {
   int part_ld = 0;  // padded row stride of d_part (cells)
   void* d_store = nullptr;
   double* d_tgrad = nullptr;
+  void* d_corr = nullptr;         // second-order faces: [n_grp][pos_per_oct] correction
+  double* d_corr_coef = nullptr;  // [n_grp][3]
+  int* d_bslot = nullptr;         // [ncell*6]
   std::vector<int> grp_band;    // instance-local group -> band
   bool stored = false;
   int fwd_parity = 0;           // parity of the converged forward state
@@ -187,6 +190,7 @@ struct bte_ctx {
   GroupSet gs;                         // ordinate groups of the current plan
   Plan sched_plan;                     // plan the host schedules were built for
   bool sched_valid = false;
+  int order = 1;                       // face reconstruction: 1 first order, 2 second order (deferred correction)
   char dev_name[96] = {0};             // device architecture and CU count (autotune-cache key)
   // shared device arrays (plan-dependent)
   InstDev* d_inst_f = nullptr;
@@ -269,11 +273,39 @@ DevPool* new_pool(bte_ctx* h, size_t offset) {
 
 bte_status finish_plan(bte_ctx* h, const Plan& pl, DevPool& pp);
 
+// Second-order faces: per group (one ordinate a of band b, G = 1) and grid
+// axis d, -t0 w0 v_b s_{a,d} / 2, the factor of the Green-Gauss gradient
+// difference in the deferred correction (in the sweep's weighted variable:
+// w0 is the group's weight in the temperature sum, t0 the time unit).
+std::vector<double> corr_coefficients(const bte_ctx* h, const HostInst& hi) {
+  const GroupSet& gs = h->gs;
+  const int ng = (int)gs.band.size();
+  std::vector<double> out((size_t)ng * 3, 0.0);
+  double D = 0.0;
+  for (int b = 0; b < h->B; ++b) D += h->C[b] / h->tau[b];
+  for (int g = 0; g < ng; ++g) {
+    const int a = gs.ords[(size_t)g * gs.G];
+    if (a < 0) continue;
+    const int b = gs.band[g];
+    const Ordinate& o = h->ords[a];
+    double den = h->t0 / h->tau[b];
+    for (int d = 0; d < hi.dim; ++d) den += h->t0 * h->v[b] * std::fabs(o.s[d]) / hi.h[d];
+    const double w0 = o.w * h->C[b] / (4.0 * kPi * h->tau[b] * D) / den;
+    for (int d = 0; d < hi.dim; ++d) out[(size_t)g * 3 + d] = -h->t0 * w0 * h->v[b] * o.s[d] / 2.0;
+  }
+  return out;
+}
+
 // (Re)build everything that depends on the plan: schedules, group tables and
 // the plan-dependent arrays.
 bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   Plan pl = pl_in;
   const bool L3 = h->dim == 3;
+  if (h->order == 2 && (pl.G != 1 || h->dim == 3)) {
+    // the correction array and the stored field hold one ordinate per group
+    set_err("second-order faces need 1D/2D grids and plans with G = 1");
+    return BTE_ERR_INVALID;
+  }
   if (h->has_specular && pl.G != 1) {
     // a specular inflow belongs to one ordinate, and the out-stream entry of a
     // group must hold one ordinate's value
@@ -421,6 +453,19 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     I.stored = false;
     I.have_dJds = false;
     HIPCHK(pp.alloc(&I.d_tgrad, (size_t)n_grp_inst * 2));
+    I.d_corr = nullptr;
+    if (h->order == 2) {
+      char* pc;
+      const size_t nc = (size_t)n_grp_inst * S.pos_per_oct * es;
+      HIPCHK(pp.alloc(&pc, nc));
+      HIPCHK(pp.memset(pc, 0, nc));  // positions of no cell stay 0
+      I.d_corr = pc;
+      char* ps;
+      HIPCHK(pp.alloc(&ps, (size_t)n_grp_inst * I.hi.ncell * es));
+      I.d_store = ps;
+      HIPCHK(pp.upload(&I.d_corr_coef, corr_coefficients(h, I.hi)));
+      HIPCHK(pp.upload(&I.d_bslot, I.hi.bslot));
+    }
     // descriptors
     for (int adj = 0; adj < 2; ++adj) {
       InstDev& d = adj ? ida[k] : idf[k];
@@ -452,7 +497,8 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
       d.outv = I.d_outv;
       d.part = I.d_part;
       d.part_ld = I.part_ld;
-      d.store_u = nullptr;
+      d.store_u = (!adj && h->order == 2) ? I.d_store : nullptr;
+      d.corr = adj ? nullptr : I.d_corr;
       d.tgrad = I.d_tgrad;
       d.status = reinterpret_cast<int*>((adj ? h->d_st_a : h->d_st_f) + k);
       d.lag = S.lag;
@@ -493,7 +539,9 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   }
   // LDS carve-up
   const int R = L3 ? 1 : pl.R, P = pl.P, G = pl.G, Cc = pl.C;
-  h->nacc_max = std::max(1 + h->dim, 2);
+  // second-order sweeps carry three planes on flux iterations in 1D too (the
+  // y-flux plane then holds zeros): one compiled variant per shape
+  h->nacc_max = std::max(h->order == 2 ? 3 : 1 + h->dim, 2);
   auto al = [](size_t x) { return (x + 15) / 16 * 16; };
   size_t off = 0;
   SweepArgs& sa = h->sa;
@@ -613,7 +661,7 @@ bte_status finish_plan(bte_ctx* h, const Plan& pl, DevPool& pp) {
   for (auto& I : h->inst)
     st += ((size_t)I.n_grp * I.hi.ncell * pl.G * es + kWsAlign - 1) / kWsAlign * kWsAlign;
   h->need_store = st;
-  if (h->pool_mode == DevPool::ARENA && h->ws_store) {
+  if (h->pool_mode == DevPool::ARENA && h->ws_store && h->order == 1) {
     for (auto& I : h->inst) {
       char* p;
       HIPCHK(pp.alloc(&p, (size_t)I.n_grp * I.hi.ncell * pl.G * es));
@@ -970,13 +1018,34 @@ bte_status enqueue_specular(bte_ctx* h, bool adj, hipStream_t st) {
   return BTE_OK;
 }
 
+// Second-order faces: the next sweep's correction from the stored field.
+bte_status enqueue_corr(bte_ctx* h, hipStream_t st) {
+  for (size_t k = 0; k < h->inst.size(); ++k) {
+    Inst& I = h->inst[k];
+    CorrArgs a;
+    a.inst = h->d_inst_f;
+    a.inst_id = (int)k;
+    a.n_grp = I.n_grp;
+    a.grp = h->d_gi_f + I.grp0;
+    a.coef = I.d_corr_coef;
+    a.bslot = I.d_bslot;
+    a.bf_bc = I.d_bf_bc;
+    a.bc_kind = I.d_bc_kind;
+    a.active = I.d_active;
+    for (int d = 0; d < 3; ++d) a.h[d] = I.hi.h[d];
+    HIPCHK(launch_corr(h->precision, a, I.hi.ncell, st));
+  }
+  return BTE_OK;
+}
+
 // n iterations; the last one checks convergence, the last two carry the flux.
 bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStream_t st) {
-  const int nq = 1 + h->dim;
+  const bool second = !adj && h->order == 2;
+  const int nq = second ? 3 : 1 + h->dim;
   for (int k = 0; k < n; ++k) {
-    const bool last = k == n - 1, second = k == n - 2;
-    const bool qit = !adj && (last || second);
-    bte_status s = enqueue_sweep(h, adj, qit ? nq : 1, SWEEP_PLAIN, 0, st);
+    const bool last = k == n - 1, second_last = k == n - 2;
+    const bool qit = !adj && (last || second_last);
+    bte_status s = enqueue_sweep(h, adj, qit ? nq : 1, second ? SWEEP_SECOND : SWEEP_PLAIN, 0, st);
     if (s != BTE_OK) return s;
     int fl = 0;
     if (qit) fl |= FIN_Q;
@@ -989,6 +1058,10 @@ bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStre
     }
     if (h->has_specular) {
       s = enqueue_specular(h, adj, st);
+      if (s != BTE_OK) return s;
+    }
+    if (second) {
+      s = enqueue_corr(h, st);
       if (s != BTE_OK) return s;
     }
   }
@@ -1115,11 +1188,32 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   HIPCHK(launch_ubf_init(h->precision, u, st));
   HIPCHK(launch_status_reset(h->d_st_f + k, (double)I.hi.n_active, st));
   I.stored = false;
-    I.have_dJds = false;
+  I.have_dJds = false;
+  if (h->order == 2) {
+    // the first sweep's correction: the initial field is the equilibrium at
+    // the initial temperature, the same for every ordinate
+    HIPCHK(launch_store_fill(h->precision, I.d_store, I.d_X[0], I.n_grp, I.hi.ncell, st));
+    CorrArgs a;
+    a.inst = h->d_inst_f;
+    a.inst_id = (int)k;
+    a.n_grp = I.n_grp;
+    a.grp = h->d_gi_f + I.grp0;
+    a.coef = I.d_corr_coef;
+    a.bslot = I.d_bslot;
+    a.bf_bc = I.d_bf_bc;
+    a.bc_kind = I.d_bc_kind;
+    a.active = I.d_active;
+    for (int d = 0; d < 3; ++d) a.h[d] = I.hi.h[d];
+    HIPCHK(launch_corr(h->precision, a, I.hi.ncell, st));
+  }
   return BTE_OK;
 }
 
 bte_status store_state(bte_ctx* h, hipStream_t st) {
+  if (h->order == 2) {
+    set_err("the adjoint (and the angular field it keeps) is built for first-order faces");
+    return BTE_ERR_STATE;
+  }
   // one more forward sweep from the converged state that writes u per ordinate
   const size_t es = elem(h->precision);
   std::vector<InstDev> idf(h->inst.size());
@@ -1171,6 +1265,11 @@ bte_status upload_coefficients(bte_ctx* h) {
   HIPCHK(hipDeviceSynchronize());  // a sweep in flight may still read the tables
   HIPCHK(hipMemcpy(h->d_gt_f, a.data(), a.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(h->d_gt_a, b.data(), b.size(), hipMemcpyHostToDevice));
+  if (h->order == 2)
+    for (auto& I : h->inst) {
+      const std::vector<double> cc = corr_coefficients(h, I.hi);
+      HIPCHK(hipMemcpy(I.d_corr_coef, cc.data(), cc.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
   return BTE_OK;
 }
 
@@ -1559,6 +1658,32 @@ bte_status bte_set_tau(bte_handle h, const double* h_tau) {
   return apply_tau(h, h_tau);
 }
 
+bte_status bte_set_order(bte_handle h, int order) {
+  ErrClear clear_on_exit;
+  if (!h || (order != 1 && order != 2)) {
+    set_err("null handle or order not 1 or 2");
+    return BTE_ERR_INVALID;
+  }
+  if (order == 2 && h->dim == 3) {
+    set_err("second-order faces are built for 1D and 2D grids");
+    return BTE_ERR_INVALID;
+  }
+  if (order == h->order) return BTE_OK;
+  const int old_order = h->order;
+  const Plan old = h->plan;
+  Plan p = h->plan;
+  if (order == 2) p.G = 1;
+  h->order = order;
+  bte_status s = build_plan(h, p);
+  if (s != BTE_OK) {
+    const std::string e = g_err;
+    h->order = old_order;
+    (void)build_plan(h, old);
+    g_err = e;
+  }
+  return s;
+}
+
 bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
   ErrClear clear_on_exit;
   if (!h || !plan) {
@@ -1861,10 +1986,11 @@ bte_status bte_time_sweep(bte_handle h, int n_launches, void* hip_stream, double
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  bte_status s = enqueue_sweep(h, false, 1, SWEEP_PLAIN, 1, st);  // warm-up
+  const int mode = h->order == 2 ? SWEEP_SECOND : SWEEP_PLAIN;
+  bte_status s = enqueue_sweep(h, false, 1, mode, 1, st);  // warm-up
   if (s != BTE_OK) return s;
   HIPCHK(hipEventRecord(e0, st));
-  for (int i = 0; i < n_launches && s == BTE_OK; ++i) s = enqueue_sweep(h, false, 1, SWEEP_PLAIN, 1, st);
+  for (int i = 0; i < n_launches && s == BTE_OK; ++i) s = enqueue_sweep(h, false, 1, mode, 1, st);
   HIPCHK(hipEventRecord(e1, st));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;

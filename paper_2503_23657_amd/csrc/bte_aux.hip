@@ -371,6 +371,59 @@ __global__ void zero_kernel(unsigned* p, long long n) {
   if (i < n) p[i] = 0u;
 }
 
+// ---------------------------------------------- second-order faces
+// neighbour of cell c across face f (0..5 = -x, +x, -y, +y, -z, +z), -1 when
+// that face is a boundary (domain edge or inactive cell)
+__device__ __forceinline__ int corr_nb(const InstDev& I, const unsigned char* act, int c, int f) {
+  const int i = c % I.nx, j = (c / I.nx) % I.ny, k = c / (I.nx * I.ny);
+  const int d = f >> 1, up = f & 1;
+  const int n = d == 0 ? I.nx : (d == 1 ? I.ny : I.nz);
+  const int x = (d == 0 ? i : (d == 1 ? j : k)) + (up ? 1 : -1);
+  if (x < 0 || x >= n) return -1;
+  const int nb = c + (up ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? I.nx : I.nx * I.ny));
+  return act[nb] ? nb : -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) corr_kernel(CorrArgs A) {
+  const InstDev& I = A.inst[A.inst_id];
+  const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+  if (st->done) return;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (c >= I.ncell || !A.active[c]) return;
+  const int4 gi = A.grp[g];
+  const int o = gi.y;
+  const T* u = reinterpret_cast<const T*>(I.store_u) + (size_t)g * I.ncell;
+  const T* ubf = reinterpret_cast<const T*>(I.ubf) + (size_t)gi.w * I.n_bface;
+  // Green-Gauss face value of cell x at its face f
+  auto face = [&](int x, int f) -> double {
+    const int nb = corr_nb(I, A.active, x, f);
+    if (nb >= 0) return 0.5 * ((double)u[x] + (double)u[nb]);
+    const int d = f >> 1;
+    const bool entering = (f & 1) == ((o >> d) & 1);
+    const int slot = A.bslot[(size_t)x * 6 + f];
+    if (entering && A.bc_kind[A.bf_bc[slot]] == 0) return (double)ubf[slot];
+    const int ob = corr_nb(I, A.active, x, f ^ 1);
+    return ob >= 0 ? 1.5 * (double)u[x] - 0.5 * (double)u[ob] : (double)u[x];
+  };
+  double corr = 0.0;
+  for (int d = 0; d < I.dim; ++d) {
+    const double gc = (face(c, 2 * d + 1) - face(c, 2 * d)) / A.h[d];
+    const int up = corr_nb(I, A.active, c, 2 * d + ((o >> d) & 1));
+    const double gu = up >= 0 ? (face(up, 2 * d + 1) - face(up, 2 * d)) / A.h[d] : 0.0;
+    corr += A.coef[(size_t)g * 3 + d] * (gc - gu);
+  }
+  T* out = reinterpret_cast<T*>(I.corr) + (size_t)g * I.pos_per_oct;
+  out[I.pos[(size_t)o * I.ncell + c]] = (T)corr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) store_fill_kernel(T* store, const double* X, int ncell) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < ncell) store[(size_t)blockIdx.y * ncell + c] = (T)X[c];
+}
+
 template __global__ void finalize_kernel<float>(FinArgs, const FinInst*);
 template __global__ void finalize_kernel<double>(FinArgs, const FinInst*);
 template __global__ void wall_update_kernel<float>(WallArgs);
@@ -439,6 +492,25 @@ hipError_t launch_ubf_init(int prec, const UbfInitArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(ubf_init_kernel<float>, dim3(nblk(n)), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(ubf_init_kernel<double>, dim3(nblk(n)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr(int prec, const CorrArgs& a, int ncell, hipStream_t st) {
+  if (a.n_grp <= 0 || ncell <= 0) return hipSuccess;
+  const dim3 grid(nblk(ncell), a.n_grp);
+  if (prec == BTE_PREC_FP32) hipLaunchKernelGGL(corr_kernel<float>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(corr_kernel<double>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_fill(int prec, void* store, const double* X, int n_grp, int ncell, hipStream_t st) {
+  if (n_grp <= 0 || ncell <= 0) return hipSuccess;
+  const dim3 grid(nblk(ncell), n_grp);
+  if (prec == BTE_PREC_FP32)
+    hipLaunchKernelGGL(store_fill_kernel<float>, grid, dim3(256), 0, st, reinterpret_cast<float*>(store), X, ncell);
+  else
+    hipLaunchKernelGGL(store_fill_kernel<double>, grid, dim3(256), 0, st, reinterpret_cast<double*>(store), X,
+                       ncell);
   return hipGetLastError();
 }
 

@@ -127,6 +127,9 @@ struct InstDev {
   int in_E;                 // entries per chunk row of in_tab (multiple of 64, <= 256)
   const int* in_tab;        // [n_oct][R][T/kC2 + 2][in_E] inflow face slot of each stream entry (-1 pad)
   const int* chunk_fl;      // [n_oct][R][T/kC2 + 1] CF2_* flags of each chunk (0 pad)
+  // second-order faces (1D/2D, one ordinate per group): the deferred
+  // correction of each group's source, in its octant's skewed layout
+  void* corr;               // [n_grp][pos_per_oct] sweep precision
 };
 
 // Job: instance, first group of the bundle (global index), instance-local job
@@ -236,6 +239,28 @@ struct SpecArgs {
   int B, M;
   int oct_xor;               // 0: forward; n_oct - 1: transposed sweeps
   const double* scale;       // [B][3] factor per band and face axis (transposed sweeps), or NULL
+};
+
+// Deferred correction of the second-order faces (Methods, "Spatial
+// discretization"; Eq. rhs_b): for every group (one ordinate) and active cell,
+// from the stored angular field u of the last sweep,
+//   corr = sum_d coef_d (grad_d u(c) - grad_d u(up_d(c))),
+// grad by Green-Gauss (face value: the mean of two cells, the wall value at an
+// isothermal face the ordinate enters through, else the linear extrapolation
+// from the cell and its neighbour across the opposite face); the upwind cell's
+// term is absent when the upwind side is a wall. Written to the group's
+// skewed layout, in the sweep's variable.
+struct CorrArgs {
+  const InstDev* inst;
+  int inst_id;
+  int n_grp;                 // groups of the instance
+  const int4* grp;           // [n_grp] (band, octant, local group, inflow-table row)
+  const double* coef;        // [n_grp][3] -t0 w0 v_b s_d / 2 per grid axis (0: padding group)
+  const int* bslot;          // [ncell*6] boundary-face slot of each face, or -1
+  const int* bf_bc;          // [n_bface]
+  const int* bc_kind;        // [n_bc]
+  const unsigned char* active;
+  double h[3];
 };
 
 struct InitArgs {

@@ -76,8 +76,10 @@ __device__ __forceinline__ int2 ldrec_b(rsrc_t r, int voff, int soff) {
 template <typename V>
 __device__ __forceinline__ V ldv(rsrc_t r, int voff, int soff) {
   constexpr int B = (int)sizeof(V);
-  static_assert(B == 8 || B % 16 == 0, "vector loads of 8 bytes or whole 16-byte parts");
-  if constexpr (B == 8) {
+  static_assert(B == 4 || B == 8 || B % 16 == 0, "vector loads of 4 or 8 bytes or whole 16-byte parts");
+  if constexpr (B == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else if constexpr (B == 8) {
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   } else {
     typedef unsigned u4_t __attribute__((ext_vector_type(4)));

@@ -8,7 +8,7 @@ namespace bte {
 
 
 // Sweep modes.
-enum { SWEEP_PLAIN = 0, SWEEP_STORE = 1, SWEEP_TAUGRAD = 2 };
+enum { SWEEP_PLAIN = 0, SWEEP_STORE = 1, SWEEP_TAUGRAD = 2, SWEEP_SECOND = 3 };
 
 // One sweep launch. prec: BTE_PREC_*; l3: 3D layout; returns hipErrorInvalidValue
 // for a (G, nacc, mode) combination that is not compiled.
@@ -33,5 +33,9 @@ hipError_t launch_output(const double* X, const unsigned char* active, int n, do
 hipError_t launch_status_reset(StatusDev* stt, double n_active, hipStream_t st);
 hipError_t launch_ubf_init(int prec, const UbfInitArgs& a, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// second-order faces: the correction of every group from the stored field,
+// and the stored field set to the initial temperature deviation X
+hipError_t launch_corr(int prec, const CorrArgs& a, int ncell, hipStream_t st);
+hipError_t launch_store_fill(int prec, void* store, const double* X, int n_grp, int ncell, hipStream_t st);
 
 }  // namespace bte

@@ -106,7 +106,12 @@ constexpr unsigned rowmask(unsigned bits, int nr) {
 
 }  // namespace s2d
 
-enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2 };
+// M2_SECOND: second-order faces by deferred correction (Methods, "Spatial
+// discretization"; Eq. rhs_b): each cell's source gains the group's correction
+// term computed from the previous iterate (read per step from the group's
+// skewed correction array), and the new angular field is stored for the next
+// correction
+enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2, M2_SECOND = 3 };
 
 template <typename T, int G, int NR, int P, int NACC, int MODE>
 __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
@@ -116,7 +121,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
   // prefetched records and values fits in ~96 registers (G ordinates' worth
   // of other state scales with it), half a chunk above that; a chunk and half
   // a chunk time the same on the bench shapes, so registers decide
-  constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1);
+  constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1) +
+                            (MODE == M2_SECOND ? NR * (int)sizeof(T) / 4 : 0);
   constexpr int KD = kRingRegs * kC2 * G <= 96 ? kC2 : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
@@ -218,6 +224,14 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const GAS int2* REC = gp(I.sched + slot * Tp * 64);
     const GAS VX* XQ = gp(reinterpret_cast<const VX*>(I.xq[iter & 1]) + slot * Tp * 64);
     const GAS VX* XF = MODE == M2_TAUGRAD ? gp(reinterpret_cast<const VX*>(I.xf) + slot * Tp * 64) : nullptr;
+    // second-order correction of this group: [n_grp][pos_per_oct] in the
+    // octant's skewed layout, a VR of the lane's rows per step
+    const GAS VR* XC = MODE == M2_SECOND
+                           ? gp(reinterpret_cast<const VR*>(reinterpret_cast<const T*>(I.corr) +
+                                                            (size_t)g_loc * I.pos_per_oct) +
+                                (long long)r * Tp * 64)
+                           : nullptr;
+    const int lo_xc = lane * (int)sizeof(VR);
     const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)ubf_row * I.n_bface);
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
@@ -287,14 +301,17 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     int2 RR[KD];
     VX RX[KD];
     VX RXF[KD];
+    VR RC[KD];
     {
       const rsrc_t rr = vbase(REC, 8, 0), rx = vbase(XQ, sizeof(VX), 0);
       const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), 0) : rx;
+      const rsrc_t rc = MODE == M2_SECOND ? vbase(XC, sizeof(VR), 0) : rx;
 #pragma unroll
       for (int u = 0; u < KD; ++u) {
         RR[u] = ldrec_b(rr, lo_rec, u * 64 * 8);
         RX[u] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
         if (MODE == M2_TAUGRAD) RXF[u] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_SECOND) RC[u] = ldv<VR>(rc, lo_xc, u * 64 * (int)sizeof(VR));
       }
     }
 
@@ -410,6 +427,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       int out_cnt = 0;
       const rsrc_t rr = vbase(REC, 8, ch * kC2 + KD), rx = vbase(XQ, sizeof(VX), ch * kC2 + KD);
       const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), ch * kC2 + KD) : rx;
+      const rsrc_t rc = MODE == M2_SECOND ? vbase(XC, sizeof(VR), ch * kC2 + KD) : rx;
       // strip-entry x-inflows of the step about to run (read one step ahead;
       // the chunk's first step reads its own after the chunk barrier)
       // (two register sets by step parity, so no value is copied)
@@ -438,6 +456,11 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         T S[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) S[k] = kS * xq[2 * k] + cQ * xq[2 * k + 1];
+        if constexpr (MODE == M2_SECOND) {
+          const VR xc = RC[sl];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) S[k] += xc[k];
+        }
 
         // upwind value of row 0: the lane below's top row of the previous step;
         // lane 0 takes the ring value of this step
@@ -556,7 +579,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         }
 
         // ---- stored angular field / tau-gradient sums
-        if (MODE == M2_STORE && rec.x >= 0) {
+        if ((MODE == M2_STORE || MODE == M2_SECOND) && rec.x >= 0) {
 #pragma unroll
           for (int k = 0; k < NR; ++k)
             if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
@@ -610,6 +633,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         RR[sl] = ldrec_b(rr, lo_rec, u * 64 * 8);
         RX[sl] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
         if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_SECOND) RC[sl] = ldv<VR>(rc, lo_xc, u * 64 * (int)sizeof(VR));
       };
 #pragma unroll
       for (int u = 0; u < kC2; ++u) step(u);

@@ -3,6 +3,6 @@
 
 namespace bte {
 
-BTE2D_UNIT(double, 1, d1)
+BTE2D_UNIT_WITH_SECOND(double, 1, d1)
 
 }  // namespace bte

@@ -3,6 +3,6 @@
 
 namespace bte {
 
-BTE2D_UNIT(float, 1, f1)
+BTE2D_UNIT_WITH_SECOND(float, 1, f1)
 
 }  // namespace bte

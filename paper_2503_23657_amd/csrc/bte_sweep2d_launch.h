@@ -77,16 +77,39 @@ static int occ2d_one(int block, size_t lds) {
     default: break;                                     \
   }
 
-// one (precision, G) translation unit
-#define BTE2D_UNIT(T_, G_, SUFFIX)                                                                      \
+// second-order sweeps (mode 3, temperature-only and flux iterations): one
+// ordinate per lane only
+#define BTE2D_CASES_SECOND_NR(T_, G_, NR_, FN, ...)   \
+  BTE2D_CASE(T_, G_, NR_, 1, 1, 3, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 1, 3, 3, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 2, 1, 3, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 2, 3, 3, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 4, 1, 3, FN, __VA_ARGS__) \
+  BTE2D_CASE(T_, G_, NR_, 4, 3, 3, FN, __VA_ARGS__)
+#define BTE2D_DISPATCH_SECOND(T_, G_, FN, ...)          \
+  switch (BTE2D_KEY(NR, P, nacc, mode)) {               \
+    BTE2D_CASES_SECOND_NR(T_, G_, 1, FN, __VA_ARGS__)   \
+    BTE2D_CASES_SECOND_NR(T_, G_, 2, FN, __VA_ARGS__)   \
+    BTE2D_CASES_SECOND_NR(T_, G_, 4, FN, __VA_ARGS__)   \
+    default: break;                                     \
+  }
+
+// one (precision, G) translation unit; SECOND: also the second-order variants
+#define BTE2D_UNIT_IMPL(T_, G_, SUFFIX, SECOND_LAUNCH, SECOND_OCC)                                      \
   hipError_t launch_sweep2d_##SUFFIX(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, \
                                      int block, size_t lds, hipStream_t st) {                         \
     BTE2D_DISPATCH(T_, G_, launch2d_one, a, grid, block, lds, st)                                     \
+    SECOND_LAUNCH                                                                                     \
     return hipErrorInvalidValue;                                                                      \
   }                                                                                                   \
   int sweep2d_blocks_per_cu_##SUFFIX(int NR, int P, int nacc, int mode, int block, size_t lds) {      \
     BTE2D_DISPATCH(T_, G_, occ2d_one, block, lds)                                                     \
+    SECOND_OCC                                                                                        \
     return 0;                                                                                         \
   }
+#define BTE2D_UNIT(T_, G_, SUFFIX) BTE2D_UNIT_IMPL(T_, G_, SUFFIX, , )
+#define BTE2D_UNIT_WITH_SECOND(T_, G_, SUFFIX)                                    \
+  BTE2D_UNIT_IMPL(T_, G_, SUFFIX, BTE2D_DISPATCH_SECOND(T_, G_, launch2d_one, a, grid, block, lds, st), \
+                  BTE2D_DISPATCH_SECOND(T_, G_, occ2d_one, block, lds))
 
 }  // namespace bte

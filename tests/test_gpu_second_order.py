@@ -1,0 +1,114 @@
+"""Second-order faces by deferred correction (Methods, "Spatial
+discretization"; Eq. rhs_b) on the GPU against the FP64 oracle with the same
+reconstruction: fixed iteration counts at 1e-10 of max|T - T_ref| (FP64),
+converged at 1e-9 (FP64) and 1e-4 (FP32 sweeps), the 1D film of the paper's
+grid study and masked 2D boxes with isothermal, diffuse and specular walls,
+several kernel shapes."""
+import numpy as np
+import pytest
+
+import bte_inputs as bi
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b, p):
+    act = p.mask > 0
+    return np.abs(a[act] - b[act]).max() / np.abs(b[act] - p.T_ref).max()
+
+
+def _solver(hip_lib, p, prec="fp64", plan=None):
+    s = hip_lib.Solver(p, precision=prec)
+    s.set_order(2)
+    if plan:
+        s.set_plan(**plan)
+    assert s.plan()["G"] == 1
+    return s
+
+
+@pytest.mark.parametrize("n", [50, 200])
+def test_film_second_order_fixed_iterations(hip_lib, n):
+    p = bi.film_1d(n_cells=n)
+    s = _solver(hip_lib, p)
+    T, q, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=0.0, max_iters=9, check_every=3)
+    r = oracle.solve(p, tol=0.0, max_iters=9, order=2)
+    assert _rel(T.cpu().numpy(), r["T"], p) < 1e-10
+    qs = np.abs(r["q"]).max()
+    assert np.abs(q.cpu().numpy() - r["q"]).max() < 1e-10 * qs
+    s.close()
+
+
+def test_film_second_order_converged(hip_lib):
+    p = bi.film_1d()
+    s = _solver(hip_lib, p)
+    T, _, rep = s.solve(torch.tensor(p.Q, device="cuda"), tol=1e-12, check_every=4)
+    r = oracle.solve(p, tol=1e-12, order=2)
+    assert rep["status"] == "ok" and abs(rep["iters"] - r["iters"]) <= 4
+    assert _rel(T.cpu().numpy(), r["T"], p) < 1e-9
+    # and it is not the first-order solution
+    r1 = oracle.solve(p, tol=1e-12)
+    assert _rel(T.cpu().numpy(), r1["T"], p) > 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("kinds,plan", [((0, 1), None), ((0, 1), dict(NR=2, P=1)), ((0, 2), None),
+                                        ((0, 0), dict(NR=1, P=2))])
+def test_masked_2d_second_order_fixed_iterations(hip_lib, kinds, plan):
+    p = bi.multi_hole_2d(37, 70, seed=6, n_bands=3, n_theta=2, n_phi=1, kinds=kinds)
+    s = _solver(hip_lib, p, plan=plan)
+    T, q, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=0.0, max_iters=6, check_every=3)
+    r = oracle.solve(p, tol=0.0, max_iters=6, order=2)
+    assert _rel(T.cpu().numpy(), r["T"], p) < 1e-10
+    act = p.mask > 0
+    qs = np.abs(r["q"][act]).max()
+    assert np.abs(q.cpu().numpy()[act] - r["q"][act]).max() < 1e-10 * qs
+    s.close()
+
+
+def test_square_second_order_converged_fp64_and_fp32(hip_lib):
+    p = bi.square_2d(64, L=0.25e-6, n_bands=6, n_theta=2, n_phi=2)
+    r = oracle.solve(p, tol=1e-12, order=2)
+    for prec, tol, bar in (("fp64", 1e-12, 1e-9), ("fp32", 1e-7, 1e-4)):
+        s = _solver(hip_lib, p, prec)
+        T, _, rep = s.solve(torch.tensor(p.Q, device="cuda"), tol=tol, check_every=8, max_iters=5000)
+        assert rep["status"] == "ok", (prec, rep)
+        assert _rel(T.cpu().numpy(), r["T"], p) < bar, prec
+        s.close()
+
+
+def test_second_order_batch_matches_single(hip_lib):
+    ps = [bi.square_2d(n, L=0.1e-6, n_bands=3, n_theta=2, n_phi=1) for n in (20, 33)]
+    bs = hip_lib.BatchSolver(ps, precision="fp64")
+    assert hip_lib.bte_set_order(bs._h, 2) == hip_lib.BTE_OK
+    Qs = [torch.tensor(p.Q, device="cuda") for p in ps]
+    Ts, _, _ = bs.solve(Qs, tol=0.0, max_iters=7, check_every=7)
+    for p, T in zip(ps, Ts):
+        r = oracle.solve(p, tol=0.0, max_iters=7, order=2)
+        assert _rel(T.cpu().numpy(), r["T"], p) < 1e-10
+    bs.close()
+
+
+def test_second_order_refusals(hip_lib):
+    p3 = bi.random_box_3d(6, 5, 4, seed=1, n_bands=2, n_theta=1, n_phi=1)
+    s = hip_lib.Solver(p3, precision="fp64")
+    with pytest.raises(hip_lib.BTEError) as ei:
+        s.set_order(2)
+    assert ei.value.status == hip_lib.BTE_ERR_INVALID
+    s.close()
+    p = bi.square_2d(12, L=0.1e-6, n_bands=2, n_theta=1, n_phi=1)
+    s = _solver(hip_lib, p)
+    with pytest.raises(hip_lib.BTEError):
+        s.set_plan(G=2)
+    assert s.plan()["G"] == 1
+    Q = torch.tensor(p.Q, device="cuda")
+    with pytest.raises(hip_lib.BTEError) as ei:
+        s.solve(Q, tol=1e-8, store_state=True)
+    assert ei.value.status == hip_lib.BTE_ERR_STATE
+    # back to first order: the ordinary solve and its adjoint work again
+    s.set_order(1)
+    T, _, _ = s.solve(Q, tol=0.0, max_iters=5, check_every=5)
+    r = oracle.solve(p, tol=0.0, max_iters=5)
+    assert _rel(T.cpu().numpy(), r["T"], p) < 1e-10
+    s.close()

@@ -73,7 +73,7 @@ def source_hash(files) -> str:
 
 
 SOURCES_2D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_kutil.h")
-SOURCES_3D = ("bte_sweep.hip", "bte_sweep_f.hip", "bte_kutil.h")
+SOURCES_3D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_sweep3r_f.hip", "bte_kutil.h")
 
 
 def profiled_traffic(summary: str, kernel: str, files):

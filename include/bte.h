@@ -112,16 +112,24 @@ typedef struct {
 } bte_quadrature;
 
 /* Kernel shape of the sweep (chosen by bte_autotune, or set by hand).
-   G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D: 1, 2 or 4;
-      1 whenever a specular wall is present).
+   G: ordinates per register slot of a lane (1D/2D: 1 or 2; 3D rows-per-lane:
+      1; 3D pencil blocks: 1, 2 or 4; 1 whenever a specular wall is present).
    R: 1D/2D only, waves per workgroup that pipeline successive strips of
       64*NR rows (R*P <= 4); 3D: always 1.
    P: waves per workgroup that sweep different ordinate groups of one octant
       in lockstep and add their partial sums per cell before writing them
-      (1D/2D: 1, 2 or 4 with R*P <= 4; 3D: 1..8).
-   C: 3D only, steps between workgroup barriers (multiple of 8 in 8..64 and of
-      P); 1D/2D always use chunks of 8 steps.
-   NR: 1D/2D only, rows owned by each lane of a strip (1, 2 or 4).
+      (1D/2D: 1, 2 or 4 with R*P <= 4; 3D rows-per-lane: 1, 2, 4 or 8; 3D
+      pencil blocks: 1..8).
+   C: 3D pencil blocks only, steps between workgroup barriers (multiple of 8
+      in 8..64 and of P); the other layouts use chunks of 8 steps.
+   NR: 1D/2D, rows owned by each lane of a strip (1, 2 or 4). 3D: a negative
+      value selects the pencil-block layout (reported as 0), 1 or 2 the
+      rows-per-lane layout (lanes along one grid axis of at most 128 cells,
+      each lane NR cells of it; the step axis cut into blocks of 8 columns
+      streamed block by block, plane by plane along the third axis; the axes
+      are assigned for the fewest boundary entries; taken when the problem
+      fits, with the NR the grid needs), reported back as the rows per lane
+      used.
    Zero fields mean "keep the current value". A shape whose LDS need exceeds
    the per-workgroup limit is rejected with BTE_ERR_INVALID. */
 typedef struct { int G, R, P, C, NR; } bte_plan;

@@ -362,6 +362,8 @@ class Solver(_Workspace):
         profiler reports it), for matching counter summaries."""
         pl = self.plan()
         t = "float" if self.prec == PREC_FP32 else "double"
+        if self.problem.dim == 3 and pl["NR"] >= 1:
+            return f"sweep2d_kernel<{t}, 1, {pl['NR']}, {pl['P']}, 1, 0, true>"
         if self.problem.dim == 3:
             return f"sweep_kernel<{t}, {pl['G']}, 1, 0, true>"
         return f"sweep2d_kernel<{t}, {pl['G']}, {pl['NR']}, {pl['P']}, 1, 0>"

@@ -16,6 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbte_hip.so")
 SOURCES = ["bte_sweep2d_f1.hip", "bte_sweep2d_f2.hip", "bte_sweep2d_d1.hip", "bte_sweep2d_d2.hip",
+           "bte_sweep3r_f.hip", "bte_sweep3r_d.hip",
            "bte_sweep_f.hip", "bte_sweep_d.hip", "bte_aux.hip", "bte_dispatch.cpp", "bte_setup.cpp", "bte_api.cpp"]
 ARCH = os.environ.get("BTE_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

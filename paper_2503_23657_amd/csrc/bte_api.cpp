@@ -153,6 +153,10 @@ struct Inst {
   void* d_corr = nullptr;         // second-order faces: [n_grp][pos_per_oct] correction
   double* d_corr_coef = nullptr;  // [n_grp][3]
   int* d_bslot = nullptr;         // [ncell*6]
+  int* d_xpre = nullptr;          // 3D rows-per-lane: step-axis wall faces of the first column
+  int* d_gpre = nullptr;          // 3D rows-per-lane: lane 0's lane-axis wall faces
+  int* d_out_tab = nullptr;       // 3D rows-per-lane: outflow entries per chunk
+  int* d_out_chunk = nullptr;     // 3D rows-per-lane: stream offset per chunk
   std::vector<int> grp_band;    // instance-local group -> band
   bool stored = false;
   int fwd_parity = 0;           // parity of the converged forward state
@@ -191,6 +195,7 @@ struct bte_ctx {
   Plan sched_plan;                     // plan the host schedules were built for
   bool sched_valid = false;
   int order = 1;                       // face reconstruction: 1 first order, 2 second order (deferred correction)
+  bool l3r = false;                    // 3D problem swept by the rows-per-lane kernel (else the pencil-block one)
   char dev_name[96] = {0};             // device architecture and CU count (autotune-cache key)
   // shared device arrays (plan-dependent)
   InstDev* d_inst_f = nullptr;
@@ -301,6 +306,8 @@ std::vector<double> corr_coefficients(const bte_ctx* h, const HostInst& hi) {
 bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   Plan pl = pl_in;
   const bool L3 = h->dim == 3;
+  // 3D: NR >= 1 asks for the rows-per-lane layout, NR = 0 for the pencil blocks
+  const bool R3 = L3 && pl.NR >= 1;
   if (h->order == 2 && (pl.G != 1 || h->dim == 3)) {
     // the correction array and the stored field hold one ordinate per group
     set_err("second-order faces need 1D/2D grids and plans with G = 1");
@@ -312,9 +319,20 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     set_err("specular walls need plans with G = 1");
     return BTE_ERR_INVALID;
   }
-  if (L3) {
+  if (R3) {
     pl.R = 1;
-    pl.NR = 1;
+    pl.C = kC2;
+    if (pl.G != 1) {
+      set_err("the 3D rows-per-lane layout takes G = 1 (NR = 0 selects the pencil-block layout)");
+      return BTE_ERR_INVALID;
+    }
+    if (pl.P != 1 && pl.P != 2 && pl.P != 4 && pl.P != 8) {
+      set_err("plan P must be 1, 2, 4 or 8 in the 3D rows-per-lane layout");
+      return BTE_ERR_INVALID;
+    }
+  } else if (L3) {
+    pl.R = 1;
+    pl.NR = 0;
     if (pl.G != 1 && pl.G != 2 && pl.G != 4) {
       set_err("plan G must be 1, 2 or 4");
       return BTE_ERR_INVALID;
@@ -360,6 +378,28 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   h->sched_valid = false;
   if (!reuse_sched) h->gs = build_groups(h->ords, h->B, h->dim, pl.G, pl.P);
   const GroupSet& gs = h->gs;
+  if (R3 && !reuse_sched) {
+    // rows-per-lane schedules of every instance, with one NR for all (the
+    // kernel's shape): the largest any instance needs
+    int nr = std::min(std::max(pl.NR, 1), 2);
+    for (int pass = 0; pass < 2; ++pass) {
+      Plan p3 = pl;
+      p3.NR = nr;
+      int nrmax = 1;
+      for (auto& I : h->inst) {
+        std::string err;
+        if (!build_schedule_3r(I.hi, p3, I.sch, err)) {
+          set_err("%s", err.c_str());
+          return BTE_ERR_INVALID;
+        }
+        nrmax = std::max(nrmax, I.sch.NR);
+      }
+      if (nrmax == nr) break;
+      nr = nrmax;
+    }
+    pl.NR = nr;
+  }
+  h->l3r = R3;
   const int n_grp_inst = (int)gs.band.size();
   const int n_bund = (int)gs.bundle_first.size();
   const int n_oct = 1 << h->dim;
@@ -372,7 +412,7 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   for (size_t k = 0; k < h->inst.size(); ++k) {
     Inst& I = h->inst[k];
     std::string err;
-    if (!reuse_sched && !build_schedule(I.hi, pl, I.sch, err)) {
+    if (!reuse_sched && !R3 && !build_schedule(I.hi, pl, I.sch, err)) {
       set_err("%s", err.c_str());
       return BTE_ERR_INVALID;
     }
@@ -428,6 +468,16 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     HIPCHK(pp.upload(&I.d_out_base, S.out_base));
     HIPCHK(pp.upload(&I.d_pre_slot, S.pre_slot));
     HIPCHK(pp.upload(&I.d_ofk, S.ofk));
+    I.d_xpre = nullptr;
+    I.d_gpre = nullptr;
+    I.d_out_tab = nullptr;
+    I.d_out_chunk = nullptr;
+    if (S.l3r) {
+      HIPCHK(pp.upload(&I.d_xpre, S.xpre));
+      HIPCHK(pp.upload(&I.d_gpre, S.gpre));
+      HIPCHK(pp.upload(&I.d_out_tab, S.out_tab));
+      HIPCHK(pp.upload(&I.d_out_chunk, S.out_chunk));
+    }
     std::vector<int2> gob(n_oct * h->B);
     for (int i = 0; i < n_oct * h->B; ++i) gob[i] = make_int2(gs.ob_first[i], gs.ob_count[i]);
     HIPCHK(pp.upload(&I.d_grp_ob, gob));
@@ -510,6 +560,20 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
       d.in_E = S.in_E;
       d.in_tab = I.d_in_tab;
       d.chunk_fl = I.d_chunk_fl;
+      for (int e = 0; e < 3; ++e) d.ax[e] = S.ax[e];
+      for (int oo = 0; oo < 8; ++oo) {
+        const int st[3] = {1, I.hi.n[0], I.hi.n[0] * I.hi.n[1]};
+        // the groups of the transposed sweeps run the flipped octant's schedule,
+        // and the kernel indexes with its job's (schedule) octant
+        d.dyo[oo] = ((oo >> S.ax[1]) & 1 ? -1 : 1) * st[S.ax[1]];
+      }
+      d.n_pl = S.n_pl;
+      d.n_per = S.n_per;
+      d.xpre = I.d_xpre;
+      d.gpre = I.d_gpre;
+      d.out_tab = I.d_out_tab;
+      d.out_chunk = I.d_out_chunk;
+      d.out_E = S.out_E;
     }
     for (int b = 0; b < n_bund; ++b) {
       const int o = gs.bundle_oct[b];
@@ -546,21 +610,23 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   size_t off = 0;
   SweepArgs& sa = h->sa;
   memset(&sa, 0, sizeof(sa));
-  if (!L3) {
+  if (!L3 || R3) {
     // 1D/2D: ring [P][R][W_max + 1][G], cell ids [2][R][kC2][72], inflow
     // [P*R][2][E], outflow [P*R][o_max], staging [planes][P*R][kC2][64*NR + 8
     // dwords] with max(2, nacc) planes (double-buffered for the
     // temperature-only sweep)
     int E = 64;
     for (auto& I : h->inst) E = std::max(E, I.sch.in_E);
+    // (the 3D rows layout has no strip ring and emits its outflows from the
+    // staging: neither takes LDS)
     sa.lds_zring = (int)off;
-    off += al((size_t)P * R * (W_max + 1) * G * es);
+    off += R3 ? 0 : al((size_t)P * R * (W_max + 1) * G * es);
     sa.lds_cid = (int)off;
     off += al((size_t)2 * R * kC2 * (64 + 8) * 4);  // records, rows padded to 72 ints
     sa.lds_in = (int)off;
     off += al((size_t)P * R * 2 * E * es);
     sa.lds_out = (int)off;
-    off += al((size_t)P * R * o_max * es);
+    off += R3 ? 0 : al((size_t)P * R * o_max * es);
     sa.lds_stage = (int)off;
     h->lds_stage_plane = al((size_t)P * R * kC2 * (64 * pl.NR + 32 / es) * es);  // rows padded by 8 dwords
     off += (size_t)std::max(2, h->nacc_max) * h->lds_stage_plane;
@@ -585,10 +651,26 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     sa.e_max = E;
     sa.o_max = o_max;
     h->block = R * P * 64;
-    int bpc = sweep2d_blocks_per_cu(prec, G, pl.NR, P, 1, SWEEP_PLAIN, h->block,
-                                    sa.lds_stage + 2 * h->lds_stage_plane);
+    int bpc = R3 ? sweep3r_blocks_per_cu(prec, pl.NR, P, 1, SWEEP_PLAIN, h->block,
+                                         sa.lds_stage + 2 * h->lds_stage_plane)
+                 : sweep2d_blocks_per_cu(prec, G, pl.NR, P, 1, SWEEP_PLAIN, h->block,
+                                         sa.lds_stage + 2 * h->lds_stage_plane);
     if (bpc < 1) bpc = 1;
     h->grid = std::max(1, std::min(h->n_jobs, bpc * h->n_cu));
+    if (R3) {
+      // the step-axis buffers: one value per plane, lane and row, per
+      // (workgroup, wave p)
+      int npl = 1;
+      for (auto& I : h->inst) npl = std::max(npl, I.sch.n_pl);
+      h->zg_stride = (long long)npl * 64 * pl.NR;
+      char* zg;
+      const size_t zb = (size_t)h->grid * P * h->zg_stride * es;
+      HIPCHK(pp.alloc(&zg, zb));
+      HIPCHK(pp.memset(zg, 0, zb));
+      h->d_zg = zg;
+      sa.zg = zg;
+      sa.zg_stride = h->zg_stride;
+    }
     return finish_plan(h, pl, pp);
   }
   sa.lds_zring = (int)off;
@@ -905,12 +987,13 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
   if (s != BTE_OK) return s;
   Plan pl;
   if (h->dim == 3) {
-    // one ordinate per lane, eight waves of one octant per workgroup (fewer
-    // when the LDS of the shape does not fit)
+    // the rows-per-lane layout, P waves of one octant per workgroup (fewer
+    // when the LDS does not fit); the pencil blocks when the problem does not
+    // fit the rows-per-lane layout
     pl.G = 1;
     pl.R = 1;
-    pl.P = 8;
-    pl.C = 8;
+    pl.P = precision == BTE_PREC_FP32 ? 8 : 4;
+    pl.C = kC2;
     pl.NR = 1;
   } else {
     // one strip of 64*NR rows covers ny <= 256; P waves share the partial sums
@@ -923,6 +1006,17 @@ bte_status create_common(int n_inst, const bte_geometry* geoms, const bte_bands*
     pl.C = kC2;
   }
   s = build_plan(h.get(), pl);
+  while (s != BTE_OK && h->dim == 3 && pl.NR >= 1 && pl.P > 1) {
+    pl.P /= 2;
+    s = build_plan(h.get(), pl);
+  }
+  if (s != BTE_OK && h->dim == 3 && pl.NR >= 1) {
+    // pencil blocks: one ordinate per lane, eight waves of one octant per workgroup
+    pl.P = 8;
+    pl.NR = 0;
+    pl.C = 8;
+    s = build_plan(h.get(), pl);
+  }
   while (s != BTE_OK && h->dim == 3 && pl.P > 1) {
     pl.P /= 2;
     s = build_plan(h.get(), pl);
@@ -949,10 +1043,13 @@ bte_status enqueue_sweep(bte_ctx* h, bool adj, int nacc, int mode, int force, hi
   a.grp_i = adj ? h->d_gi_a : h->d_gi_f;
   a.grp_t = adj ? h->d_gt_a : h->d_gt_f;
   a.force = force;
-  if (h->dim < 3) {
+  if (h->dim < 3 || h->l3r) {
     const size_t lds = (size_t)a.lds_stage + (size_t)std::max(2, nacc) * h->lds_stage_plane;
-    HIPCHK(launch_sweep2d(h->precision, h->plan.G, h->plan.NR, h->plan.P, nacc, mode, a, h->grid, h->block, lds,
-                          st));
+    if (h->l3r)
+      HIPCHK(launch_sweep3r(h->precision, h->plan.NR, h->plan.P, nacc, mode, a, h->grid, h->block, lds, st));
+    else
+      HIPCHK(launch_sweep2d(h->precision, h->plan.G, h->plan.NR, h->plan.P, nacc, mode, a, h->grid, h->block, lds,
+                            st));
     return BTE_OK;
   }
   const size_t lds = (size_t)a.lds_stage + (size_t)nacc * h->lds_stage_plane;
@@ -1695,7 +1792,7 @@ bte_status bte_set_plan(bte_handle h, const bte_plan* plan) {
   if (plan->R) p.R = plan->R;
   if (plan->P) p.P = plan->P;
   if (plan->C) p.C = plan->C;
-  if (plan->NR) p.NR = plan->NR;
+  if (plan->NR) p.NR = plan->NR < 0 ? 0 : plan->NR;  // 3D: NR < 0 selects the pencil-block layout
   const Plan old = h->plan;
   bte_status s = build_plan(h, p);
   if (s != BTE_OK) {
@@ -2045,9 +2142,10 @@ bte_status autotune_impl(bte_ctx* h, const double* d_Q, int n_iters, hipStream_t
                         st));
   std::vector<Plan> cand;
   if (h->dim == 3) {
+    for (int P : {1, 2, 4, 8}) cand.push_back(Plan{1, 1, P, kC2, 1});
     for (int G : {1, 2, 4})
       for (int P : {1, 2, 4, 8})
-        for (int C : {8, 16, 32}) cand.push_back(Plan{G, 1, P, C, 1});
+        for (int C : {8, 16, 32}) cand.push_back(Plan{G, 1, P, C, 0});
   } else {
     int ny = 1;
     for (auto& I : h->inst) ny = std::max(ny, I.hi.n[1]);

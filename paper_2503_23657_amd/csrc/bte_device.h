@@ -75,6 +75,23 @@ constexpr int CF2_INY_UP = 2;   // some y-inflow on a row k >= 1 of a lane
 constexpr int CF2_OUT = 4;      // some outflow entry in the chunk
 constexpr int CF2_XST = 8;      // some lane-step with F2_XSTART in the chunk
 
+// 3D rows-per-lane sweep: the 1D/2D kernel with a third (plane) axis. Kernel
+// axes: steps along grid axis ax[0], cut into blocks of kC2 columns, lanes (NR
+// <= 2 rows each) along ax[1], planes along ax[2]; a lane streams block after
+// block, in a block plane after plane, in a plane the block's columns. 8 flag
+// bits per row (k at bit 8k): active, inflow along the step / lane / plane
+// axis, outflow (reflecting wall) along them (the outflows themselves are
+// listed per chunk in out_tab). The inflow offset sits at F2_INOFF_SHIFT as in
+// 1D/2D.
+constexpr uint32_t F3_ACT = 1u << 0;
+constexpr uint32_t F3_INX = 1u << 1;
+constexpr uint32_t F3_INY = 1u << 2;
+constexpr uint32_t F3_INZ = 1u << 3;
+constexpr uint32_t F3_OUTX = 1u << 4;
+constexpr uint32_t F3_OUTY = 1u << 5;
+constexpr uint32_t F3_OUTZ = 1u << 6;
+constexpr int F3_ROW_BITS = 8;
+
 // group coefficient record: GS(G) values of the sweep type, in this order
 //   kS, cQ, a[3][G], den[G], wacc[kNAcc][G], wo[3][G], wt[2][G], inv[G]
 __host__ __device__ constexpr int grp_stride(int G) { return 2 + G * (3 + 1 + kNAcc + 3 + 2 + 1); }
@@ -130,6 +147,17 @@ struct InstDev {
   // second-order faces (1D/2D, one ordinate per group): the deferred
   // correction of each group's source, in its octant's skewed layout
   void* corr;               // [n_grp][pos_per_oct] sweep precision
+  // 3D rows-per-lane layout
+  int ax[3];                // grid axis of the step, lane and plane axes
+  int dyo[8];               // cell-index step from row k to row k + 1, per octant
+  int n_pl;                 // planes
+  int n_per;                // plane periods of kC2 steps (blocks x planes)
+  const int* xpre;          // [n_oct][n_pl][64*nr] step-axis wall face of the first column's cells (-1)
+  const int* gpre;          // [n_oct][T] lane-axis wall face + 1 of lane 0's row 0 at each step (0: none)
+  const int* out_tab;       // [n_oct][T/kC2 + 2][out_E] outflow entries of each chunk, read from the staging
+                            //   ((((u*64 + l)*nr + k) << 2 | kernel axis) + 1, 0 pad)
+  const int* out_chunk;     // [n_oct][T/kC2 + 1] stream offset of each chunk's first outflow entry
+  int out_E;                // entries per chunk row of out_tab (multiple of 64, <= 256)
 };
 
 // Job: instance, first group of the bundle (global index), instance-local job
@@ -175,7 +203,8 @@ struct SweepArgs {
   int W_max;
   int e_max, o_max;
   int force;            // 1: sweep even instances marked done (timing / store passes)
-  void* zg;             // 3D: global z-rings, one per (workgroup, wave p)
+  void* zg;             // 3D: pencil layout: global z-rings; rows layout: step-axis buffers
+                        //     of the planes; one per (workgroup, wave p)
   long long zg_stride;  // elements per (workgroup, wave p)
 };
 

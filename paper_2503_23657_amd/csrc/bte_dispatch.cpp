@@ -15,6 +15,24 @@ int sweep_blocks_per_cu_d(bool l3, int G, int nacc, int mode, int block, size_t 
   hipError_t launch_sweep2d_##SUFFIX(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, \
                                      int block, size_t lds, hipStream_t st);                          \
   int sweep2d_blocks_per_cu_##SUFFIX(int NR, int P, int nacc, int mode, int block, size_t lds);
+hipError_t launch_sweep3r_f(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, int block, size_t lds,
+                           hipStream_t st);
+hipError_t launch_sweep3r_d(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, int block, size_t lds,
+                           hipStream_t st);
+int sweep3r_blocks_per_cu_f(int NR, int P, int nacc, int mode, int block, size_t lds);
+int sweep3r_blocks_per_cu_d(int NR, int P, int nacc, int mode, int block, size_t lds);
+
+hipError_t launch_sweep3r(int prec, int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, int block,
+                          size_t lds, hipStream_t st) {
+  return prec == BTE_PREC_FP32 ? launch_sweep3r_f(NR, P, nacc, mode, a, grid, block, lds, st)
+                               : launch_sweep3r_d(NR, P, nacc, mode, a, grid, block, lds, st);
+}
+
+int sweep3r_blocks_per_cu(int prec, int NR, int P, int nacc, int mode, int block, size_t lds) {
+  return prec == BTE_PREC_FP32 ? sweep3r_blocks_per_cu_f(NR, P, nacc, mode, block, lds)
+                               : sweep3r_blocks_per_cu_d(NR, P, nacc, mode, block, lds);
+}
+
 BTE2D_DECL(f1)
 BTE2D_DECL(f2)
 BTE2D_DECL(d1)

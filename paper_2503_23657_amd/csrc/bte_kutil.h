@@ -92,4 +92,20 @@ __device__ __forceinline__ V ldv(rsrc_t r, int voff, int soff) {
   }
 }
 
+// as ldv, at device scope (cache policy sc1: the load misses the CU's vector
+// cache and reads L2), for data the same wave stored earlier
+template <typename V>
+__device__ __forceinline__ V ldv_glc(rsrc_t r, int voff, int soff) {
+  constexpr int B = (int)sizeof(V);
+  constexpr int kSc1 = 0x10;
+  static_assert(B == 4 || B == 8 || B == 16, "vector loads of 4, 8 or 16 bytes");
+  if constexpr (B == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kSc1));
+  } else if constexpr (B == 8) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kSc1));
+  } else {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kSc1));
+  }
+}
+
 }  // namespace bte

@@ -24,6 +24,12 @@ hipError_t launch_sweep2d(int prec, int G, int NR, int P, int nacc, int mode, co
                           int block, size_t lds, hipStream_t st);
 int sweep2d_blocks_per_cu(int prec, int G, int NR, int P, int nacc, int mode, int block, size_t lds);
 
+// One launch of the 3D rows-per-lane sweep (the 1D/2D kernel with a plane
+// axis; one ordinate per lane, NR in {1, 2}).
+hipError_t launch_sweep3r(int prec, int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, int block,
+                          size_t lds, hipStream_t st);
+int sweep3r_blocks_per_cu(int prec, int NR, int P, int nacc, int mode, int block, size_t lds);
+
 hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st);
 hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st);
 hipError_t launch_spec_update(int prec, const SpecArgs& a, hipStream_t st);

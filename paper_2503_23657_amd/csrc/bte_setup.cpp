@@ -535,8 +535,271 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
   return true;
 }
 
+// 3D rows-per-lane schedule for one choice of the lane and plane axes (the
+// step axis is x, so that consecutive steps of a lane are consecutive cells).
+// The step axis is cut into blocks of C = kC2 columns. Every lane runs
+// through the same sequence of positions: block after block, in a block plane
+// after plane, in a plane the block's C columns; lane l takes position
+// s = t - l at clock step t (s = (b*n_pl + p)*C + c: block b, plane p, column
+// c). So lane l works on the cell lane l-1 had one step before (the lane-axis
+// link), its plane-axis upwind cell is its own position s - C (the value it
+// computed C steps earlier, kept in registers) and, inside a block, its
+// step-axis upwind cell is position s - 1. The first column of a block takes
+// the step-axis value of the previous block's last column in the same plane,
+// which every lane keeps per plane in a buffer of its own; for the first block
+// that buffer is prefilled with the wall faces of xpre. Lane 0's row 0 takes
+// the lane-axis wall face of gpre at each step (stored as slot + 1, 0: none).
+// Every other boundary value (the first plane's walls included) is an entry
+// of the inflow stream, in order per step: lanes, rows ascending, step / lane
+// / plane axis. Outflow entries, per step: rows, axes, lanes; the kernel
+// emits a chunk's entries after the chunk from its staged values, as listed in
+// out_tab. Positions: (t*64 + l)*NR + k.
+static bool build_3r_axes(const HostInst& hi, int A0, int A1, int A2, const Plan& plan, Schedule& s,
+                          std::string& err) {
+  const int C = kC2;
+  const int n0 = hi.n[A0], n1 = hi.n[A1], n2 = hi.n[A2];
+  const int NR = std::max(std::min(plan.NR, 2), n1 <= 64 ? 1 : 2);
+  if (n1 > 128) {
+    err = "lane axis longer than 128 cells";
+    return false;
+  }
+  if (n2 < 4) {
+    // the step-axis buffer of a plane is written back at least three plane
+    // periods before it is read again
+    err = "fewer than 4 planes";
+    return false;
+  }
+  const int nb = (n0 + C - 1) / C;
+  const int n_per = nb * n2;
+  const int T = n_per * C + 64;  // the last lane ends 63 steps after lane 0 (rounded to whole chunks)
+  const int Tp = T + kPad2;
+  s = Schedule();
+  s.l3r = true;
+  s.ax[0] = A0;
+  s.ax[1] = A1;
+  s.ax[2] = A2;
+  s.T = T;
+  s.R = 1;
+  s.C = C;
+  s.W = nb * C;
+  s.NR = NR;
+  s.du = 0;
+  s.nS = 1;
+  s.lag = 0;
+  s.ring = 0;
+  s.n_pl = n2;
+  s.n_per = n_per;
+  s.n_oct = 8;
+  s.pos_per_oct = (long long)Tp * 64 * NR;
+  if (s.pos_per_oct * s.n_oct > (1ll << 31) - 1) {
+    err = "schedule too large";
+    return false;
+  }
+  if ((long long)hi.ncell >= (1ll << 26)) {
+    err = "too many cells for the rows-per-lane sweep (limit 2^26)";
+    return false;
+  }
+  const int n_oct = 8, nch = T / C, nbf = (int)hi.bf_cell.size();
+  const int H = 64 * NR;
+  s.sched.assign((size_t)n_oct * Tp * 64, make_int2(-1, 0));
+  s.pos.assign((size_t)n_oct * hi.ncell, -1);
+  s.in_slot.clear();
+  s.in_chunk.assign((size_t)n_oct * (nch + 1), 0);
+  s.out_base.assign(n_oct, 0);
+  s.ofk.assign((size_t)n_oct * std::max(nbf, 1), -1);
+  s.xpre.assign((size_t)n_oct * n2 * H, -1);
+  s.gpre.assign((size_t)n_oct * T, 0);
+  s.e_max = 1;
+  s.o_max = 1;
+  const int stride[3] = {1, hi.n[0], hi.n[0] * hi.n[1]};
+  const int ax[3] = {A0, A1, A2};
+  std::vector<int> out_face((size_t)NR * 3 * 64);
+  std::vector<int> out_count(n_oct, 0);
+  std::vector<std::vector<int>> out_ent(n_oct);
+  s.out_chunk.assign((size_t)n_oct * (nch + 1), 0);
+  for (int o = 0; o < n_oct; ++o) {
+    int* chk = &s.in_chunk[(size_t)o * (nch + 1)];
+    int* och = &s.out_chunk[(size_t)o * (nch + 1)];
+    bool flip[3];
+    int up[3], dn[3];
+    for (int e = 0; e < 3; ++e) {
+      flip[e] = (o >> ax[e]) & 1;
+      up[e] = 2 * ax[e] + (flip[e] ? 1 : 0);
+      dn[e] = 2 * ax[e] + (flip[e] ? 0 : 1);
+    }
+    int out_k = 0;
+    for (int t = 0; t < T; ++t) {
+      if (t % C == 0) chk[t / C] = (int)s.in_slot.size();
+      std::fill(out_face.begin(), out_face.end(), -1);
+      for (int l = 0; l < 64; ++l) {
+        const int q = t - l;
+        if (q < 0 || q >= n_per * C) continue;
+        const int per = q / C, c = q % C;
+        const int bk = per / n2, pl = per % n2;
+        const int v = bk * C + c;
+        if (v >= n0) continue;
+        const int in_first = (int)s.in_slot.size() - chk[t / C];
+        bool any_in = false;
+        unsigned fl = 0;
+        int cid0 = -1, gm = 0;
+        for (int k = 0; k < NR; ++k) {
+          const int jp = l * NR + k;
+          if (jp >= n1) break;
+          gm |= 1 << k;
+          int co[3];
+          co[0] = flip[0] ? n0 - 1 - v : v;
+          co[1] = flip[1] ? n1 - 1 - jp : jp;
+          co[2] = flip[2] ? n2 - 1 - pl : pl;
+          int cell = 0;
+          for (int e = 0; e < 3; ++e) cell += co[e] * stride[ax[e]];
+          if (k == 0) cid0 = cell;
+          if (!hi.active[cell]) continue;
+          const int sh = F3_ROW_BITS * k;
+          fl |= F3_ACT << sh;
+          s.pos[(size_t)o * hi.ncell + cell] = (int)(((long long)t * 64 + l) * NR + k);
+          for (int e = 0; e < 3; ++e) {
+            const int su = hi.bslot[(size_t)cell * 6 + up[e]];
+            if (su < 0) continue;
+            if (e == 0 && v == 0) {
+              s.xpre[((size_t)o * n2 + pl) * H + jp] = su;
+            } else if (e == 1 && jp == 0) {
+              s.gpre[(size_t)o * T + t] = su + 1;
+            } else {
+              fl |= (F3_INX << e) << sh;
+              s.in_slot.push_back(su);
+              any_in = true;
+            }
+          }
+          for (int e = 0; e < 3; ++e) {
+            const int sd = hi.bslot[(size_t)cell * 6 + dn[e]];
+            if (sd < 0 || !reflecting(hi.bc_kind[hi.bf_bc[sd]])) continue;
+            fl |= (F3_OUTX << e) << sh;
+            out_face[((size_t)k * 3 + e) * 64 + l] = sd;
+          }
+        }
+        if (any_in) {
+          if (in_first > (int)F2_INOFF_MASK) {
+            err = "too many boundary inflows per chunk";
+            return false;
+          }
+          fl |= (unsigned)in_first << F2_INOFF_SHIFT;
+        }
+        const int full = gm == (1 << NR) - 1 ? 16 : 0;
+        s.sched[((size_t)o * Tp + t) * 64 + l] = make_int2(cid0 >= 0 ? (cid0 << 5) | full | gm : -1, (int)fl);
+      }
+      if (t % C == 0) och[t / C] = out_k;
+      for (int kd = 0; kd < NR * 3; ++kd)
+        for (int l = 0; l < 64; ++l) {
+          const int sd = out_face[(size_t)kd * 64 + l];
+          if (sd < 0) continue;
+          s.ofk[(size_t)o * nbf + sd] = out_k++;
+          const int k = kd / 3, e = kd % 3;
+          out_ent[o].push_back((((((t % C) * 64 + l) * NR + k) << 2) | e) + 1);
+        }
+    }
+    och[nch] = out_k;
+    chk[nch] = (int)s.in_slot.size();
+    for (int ch = 0; ch < nch; ++ch) s.e_max = std::max(s.e_max, chk[ch + 1] - chk[ch]);
+    out_count[o] = out_k;
+  }
+  int n_stream = 1;
+  for (int o = 0; o < n_oct; ++o) n_stream = std::max(n_stream, out_count[o]);
+  s.n_out_stride = n_stream;
+  // per-chunk flags (inflow entries only: the outflows leave after the chunk)
+  s.chunk_fl.assign((size_t)n_oct * (nch + 1), 0);
+  unsigned in_all = 0;
+  for (int k = 0; k < NR; ++k) in_all |= (F3_INX | F3_INY | F3_INZ) << (F3_ROW_BITS * k);
+  for (int o = 0; o < n_oct; ++o)
+    for (int ch = 0; ch < nch; ++ch) {
+      int cf = 0;
+      for (int t = ch * C; t < (ch + 1) * C; ++t)
+        for (int l = 0; l < 64; ++l) {
+          const unsigned fl = (unsigned)s.sched[((size_t)o * Tp + t) * 64 + l].y;
+          if (fl & in_all) cf |= CF2_IN | CF2_INY_UP;
+        }
+      const int* och = &s.out_chunk[(size_t)o * (nch + 1)];
+      s.o_max = std::max(s.o_max, och[ch + 1] - och[ch]);
+      s.chunk_fl[(size_t)o * (nch + 1) + ch] = cf;
+    }
+  if (s.e_max > 256) {
+    err = "too many boundary inflows per chunk";
+    return false;
+  }
+  if (s.o_max > 256) {
+    err = "too many reflecting-wall outflows per chunk";
+    return false;
+  }
+  s.in_E = std::max(64, (s.e_max + 63) / 64 * 64);
+  s.in_tab.assign((size_t)n_oct * (nch + 2) * s.in_E, -1);
+  for (int o = 0; o < n_oct; ++o) {
+    const int* chk = &s.in_chunk[(size_t)o * (nch + 1)];
+    for (int ch = 0; ch < nch; ++ch)
+      for (int e = chk[ch]; e < chk[ch + 1]; ++e)
+        s.in_tab[((size_t)o * (nch + 2) + ch) * s.in_E + (e - chk[ch])] = s.in_slot[e];
+  }
+  s.out_E = std::max(64, (s.o_max + 63) / 64 * 64);
+  s.out_tab.assign((size_t)n_oct * (nch + 2) * s.out_E, 0);
+  for (int o = 0; o < n_oct; ++o) {
+    const int* och = &s.out_chunk[(size_t)o * (nch + 1)];
+    for (int ch = 0; ch < nch; ++ch)
+      for (int e = och[ch]; e < och[ch + 1]; ++e)
+        s.out_tab[((size_t)o * (nch + 2) + ch) * s.out_E + (e - och[ch])] = out_ent[o][e];
+  }
+  for (int o = 0; o < n_oct; ++o)
+    for (int c = 0; c < hi.ncell; ++c)
+      if (hi.active[c] && s.pos[(size_t)o * hi.ncell + c] < 0) {
+        err = "internal: cell missing from the schedule";
+        return false;
+      }
+  return true;
+}
+
+// relative cost of a 3D rows-per-lane schedule: its chunks, a chunk with
+// inflow entries (they run the slow path) counting twice
+static double cost_3r(const Schedule& s) {
+  const int nch = s.T / s.C;
+  double c = 0.0;
+  for (int o = 0; o < s.n_oct; ++o)
+    for (int ch = 0; ch < nch; ++ch) c += (s.chunk_fl[(size_t)o * (nch + 1) + ch] & CF2_IN) ? 2.0 : 1.0;
+  return c;
+}
+
+bool build_schedule_3r(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err) {
+  if (hi.dim != 3) {
+    err = "the rows-per-lane 3D layout needs a 3D problem";
+    return false;
+  }
+  // every assignment of the grid axes to the step, lane and plane axes whose
+  // lane axis fits 128 cells; the cheapest schedule wins
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  double best = -1.0;
+  std::string e1;
+  for (const auto& pm : perm) {
+    if (hi.n[pm[1]] > 128) continue;
+    Schedule cand;
+    std::string e;
+    if (!build_3r_axes(hi, pm[0], pm[1], pm[2], plan, cand, e)) {
+      if (e1.empty()) e1 = e;
+      continue;
+    }
+    const double c = cost_3r(cand);
+    if (best < 0.0 || c < best) {
+      best = c;
+      s = std::move(cand);
+    }
+  }
+  if (best >= 0.0) return true;
+  err = e1.empty() ? "no lane axis of at most 128 cells" : e1;
+  return false;
+}
+
 bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err) {
   if (hi.dim < 3) return build_schedule_2d(hi, plan, s, err);
+  if (plan.NR >= 1) {
+    std::string e3;
+    if (build_schedule_3r(hi, plan, s, e3)) return true;
+  }
+  s = Schedule();
   const bool L3 = hi.dim == 3;
   const int LJ = L3 ? 8 : 1, LK = L3 ? 8 : 64;
   const int R = L3 ? 1 : plan.R;

@@ -73,6 +73,21 @@ struct Schedule {
   std::vector<int> chunk_fl;         // 1D/2D: [n_oct][R][T/C + 1] CF2_* flags
   int in_E = 64;
   int n_out_stride = 1;              // max out-stream length over octants
+  // 3D rows-per-lane layout (the 1D/2D kernel with a plane axis): the step
+  // axis is cut into blocks of kC2 columns; a lane streams block by block, in
+  // each block plane by plane, in each plane the block's columns
+  bool l3r = false;
+  int ax[3] = {0, 1, 2};             // grid axis of the kernel's step, lane and plane axes
+  int n_pl = 0;                      // planes (cells along the plane axis)
+  int n_per = 0;                     // plane periods of kC2 steps: blocks x planes
+  std::vector<int> xpre;             // [n_oct][n_pl][64*NR] step-axis wall face of the first column's cells (-1)
+  std::vector<int> gpre;             // [n_oct][T] lane-axis wall face + 1 of lane 0's row 0 at each step (0: none)
+  // reflecting-wall outflows, emitted per chunk from the staged values: entry
+  // (((u*64 + l)*NR + k) << 2 | axis) + 1 of each outflow of chunk step u,
+  // lane l, row k, in stream order (0 pad), and the stream offset of each chunk
+  int out_E = 64;
+  std::vector<int> out_tab;          // [n_oct][T/C + 2][out_E]
+  std::vector<int> out_chunk;        // [n_oct][T/C + 1]
 };
 
 // Validation of the public structures; returns "" when valid.
@@ -96,8 +111,14 @@ void group_coefficients(const GroupSet& gs, const std::vector<Ordinate>& ords, c
                         const std::vector<double>& C, double t0, bool adjoint,
                         std::vector<double>& out);
 
-// Sweep schedule of an instance.
+// Sweep schedule of an instance. For 3D problems plan.NR = 0 selects the
+// pencil-block layout; NR >= 1 the rows-per-lane layout when the problem fits
+// it (a lane axis of at most 128 cells, at most 256 stream entries per chunk),
+// else the pencil-block layout.
 bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err);
+
+// 3D rows-per-lane schedule (false, with err, when the problem does not fit).
+bool build_schedule_3r(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err);
 
 // sum over incoming directions of w |s . n| for a face normal to axis d.
 double half_range(const std::vector<Ordinate>& ords, int d);

@@ -50,6 +50,10 @@
 namespace bte {
 namespace s2d {
 
+// the kernel's lambdas are inlined whatever their size: the chunk steps index
+// register arrays with the step number, which must fold to a constant
+#define BTE_INL __attribute__((always_inline))
+
 template <typename T, int N>
 struct Vec {
   typedef T type __attribute__((ext_vector_type(N)));
@@ -89,6 +93,23 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
 }
 
+// store a vector of V at byte offsets voff (per lane) + soff (uniform); an
+// offset past the buffer drops the store
+template <typename V>
+__device__ __forceinline__ void stv(const V& v, rsrc_t r, int voff, int soff) {
+  constexpr int B = (int)sizeof(V);
+  if constexpr (B == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  } else if constexpr (B == 8) {
+    typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, voff, soff, 0);
+  } else {
+    static_assert(B == 16, "stores of 4, 8 or 16 bytes");
+    typedef unsigned u4_t __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), r, voff, soff, 0);
+  }
+}
+
 constexpr int min_c(int a, int b) { return a < b ? a : b; }
 // largest power of two <= x (1 for x < 1)
 constexpr int pow2_floor(int x) {
@@ -97,10 +118,10 @@ constexpr int pow2_floor(int x) {
   return p;
 }
 
-// the flag bits `bits` repeated for rows 0..nr-1
-constexpr unsigned rowmask(unsigned bits, int nr) {
+// the flag bits `bits` repeated for rows 0..nr-1 (rb flag bits per row)
+constexpr unsigned rowmask(unsigned bits, int nr, int rb = F2_ROW_BITS) {
   unsigned m = 0;
-  for (int k = 0; k < nr; ++k) m |= bits << (F2_ROW_BITS * k);
+  for (int k = 0; k < nr; ++k) m |= bits << (rb * k);
   return m;
 }
 
@@ -113,9 +134,28 @@ constexpr unsigned rowmask(unsigned bits, int nr) {
 // correction
 enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2, M2_SECOND = 3 };
 
-template <typename T, int G, int NR, int P, int NACC, int MODE>
-__global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
+// L3: the 3D rows-per-lane layout (see bte_device.h): the same kernel with
+// lanes along the grid's lane axis and the step axis cut into blocks of kC2
+// columns, streamed block by block and in a block plane by plane, so that a
+// chunk of kC2 steps is one plane period of every lane. The plane-axis upwind
+// value is the lane's own value of the same chunk step one chunk earlier,
+// kept in registers; the step-axis upwind value of a block's first column is
+// the previous block's last column in the same plane, kept per plane in a
+// buffer of the wave (one load and one store per lane and chunk, the first
+// block's wall values prefilled); lane 0's lane-axis upwind value comes from
+// the wall table gpre.
+template <typename T, int G, int NR, int P, int NACC, int MODE, bool L3 = false>
+__global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   using namespace s2d;
+  static_assert(!L3 || (NR <= 2 && G == 1 && MODE != M2_SECOND),
+                "3D rows-per-lane: NR <= 2, one ordinate per lane, first-order faces");
+  constexpr int RB = L3 ? F3_ROW_BITS : F2_ROW_BITS;  // flag bits per row
+  constexpr unsigned B_ACT = L3 ? F3_ACT : F2_ACT;
+  constexpr unsigned B_INX = L3 ? F3_INX : F2_INX;
+  constexpr unsigned B_INY = L3 ? F3_INY : F2_INY;
+  constexpr unsigned B_INZ = L3 ? F3_INZ : 0u;
+  constexpr unsigned B_OUTX = L3 ? F3_OUTX : F2_OUTX;
+  constexpr int ND = L3 ? 3 : 2;  // kernel axes with outflow entries
   constexpr int NV = 2 * NR;                  // (X, Q) values of one lane-step
   // prefetch distance in steps (divides kC2): a whole chunk while the ring of
   // prefetched records and values fits in ~96 registers (G ordinates' worth
@@ -177,16 +217,20 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const int g_loc = gi.z;
     const CAS T* gt = cp(reinterpret_cast<const T*>(A.grp_t)) + (size_t)g_glob * GS;
     T kS = gt[0], cQ = gt[1];
-    T a0[G], a1[G], den[G], inv[G], wo0[G], wo1[G];
+    T a0[G], a1[G], a2[G], den[G], inv[G], wo0[G], wo1[G], wo2[G];
     T wacc[NACC][G];
+    // grid axes of the kernel's step, lane and plane axes (1D/2D: x, y)
+    const int ax0 = L3 ? I.ax[0] : 0, ax1 = L3 ? I.ax[1] : 1, ax2 = L3 ? I.ax[2] : 2;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      a0[g] = gt[go_a(G, 0) + g];
-      a1[g] = gt[go_a(G, 1) + g];
+      a0[g] = gt[go_a(G, ax0) + g];
+      a1[g] = gt[go_a(G, ax1) + g];
+      a2[g] = L3 ? gt[go_a(G, ax2) + g] : T(0);
       den[g] = gt[go_den(G) + g];
       inv[g] = gt[go_inv(G) + g];
-      wo0[g] = gt[go_wo(G, 0) + g];
-      wo1[g] = gt[go_wo(G, 1) + g];
+      wo0[g] = gt[go_wo(G, ax0) + g];
+      wo1[g] = gt[go_wo(G, ax1) + g];
+      wo2[g] = L3 ? gt[go_wo(G, ax2) + g] : T(0);
 #pragma unroll
       for (int a = 0; a < NACC; ++a) wacc[a][g] = gt[go_wacc(G, a) + g];
     }
@@ -205,6 +249,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       inv[0] *= iw;
       wo0[0] *= iw;
       wo1[0] *= iw;
+      wo2[0] *= iw;
 #pragma unroll
       for (int a = 1; a < NACC; ++a) wacc[a][0] *= iw;
       tg_scale = (double)iw;
@@ -216,9 +261,9 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     const int nch = T_steps / kC2;
     const int nx = I.nx, ny = I.ny;
     const int du = I.du, n_strip = I.n_strip;
-    const bool ring_w = n_strip > 1;  // some strip has a successor
+    const bool ring_w = !L3 && n_strip > 1;  // some strip has a successor (1D/2D lane-axis link)
     const int H = 64 * NR;
-    const int dy = (o & 2) ? -nx : nx;  // cell-index step from row k to row k+1
+    const int dy = L3 ? I.dyo[o] : ((o & 2) ? -nx : nx);  // cell-index step from row k to row k+1
     const long long slot = (long long)o * R + r;
     // uniform bases; lanes add 32-bit offsets
     const GAS int2* REC = gp(I.sched + slot * Tp * 64);
@@ -246,12 +291,32 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     rsrc_t PRS[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
+    // 3D: this wave's step-axis buffer (a VR per plane and lane)
+    const int n_pl = L3 ? I.n_pl : 1;
+    const int zrow = 64 * NR * (int)sizeof(T);  // bytes per plane
+    GAS T* ZR = L3 ? gp(reinterpret_cast<T*>(A.zg) + ((long long)blockIdx.x * P + p) * A.zg_stride) : nullptr;
+    const rsrc_t ZRR = mkrsrc(ZR, L3 ? (unsigned)(n_pl * zrow) : 0u);
+    const int lo_z = lane * NR * (int)sizeof(T);
 
     // ---- clear the ring; prefill the ring read by strip 0 (slot R-1's) with
     //      the bottom-wall inflow of every column
-    for (int e = lane; e < RW; e += 64) my_ring[e] = T(0);
+    if constexpr (!L3)
+      for (int e = lane; e < RW; e += 64) my_ring[e] = T(0);
     __syncthreads();
-    if (r == 0) {
+    if constexpr (L3) {
+      // the first block's step-axis wall values, one per plane
+      const GAS int* xp = gp(I.xpre + (size_t)o * n_pl * H);
+      for (int pl = 0; pl < n_pl; ++pl) {
+        VR zv;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const int sl = xp[(size_t)pl * H + lane * NR + k];
+          zv[k] = sl >= 0 ? UBF[sl] * den[0] : T(0);
+        }
+        stv(zv, ZRR, lo_z, pl * zrow);
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the buffer is written before it is read
+    } else if (r == 0) {
       T* zr = ring + (size_t)(p * R + (R - 1)) * RW;
       const GAS int* pre = gp(I.pre_slot + (size_t)o * I.W);
       for (int c = lane; c < I.W; c += 64) {
@@ -291,28 +356,58 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     double tg0 = 0.0, tg1 = 0.0;
     int out_tot = 0;
 
-    // ---- per-step inputs, prefetched KD steps ahead into a register ring;
-    //      every chunk reads them through buffer views based at its first
-    //      prefetched step (the schedule is padded by kPad2 >= KD steps)
+    // ---- per-step inputs, prefetched KD steps ahead into a register ring
+    //      (the schedule is padded by kPad2 >= KD steps)
     const int lo_rec = lane * 8, lo_xq = lane * (int)sizeof(VX);
-    auto vbase = [&](auto base, int esz, int step0) {
-      return mkrsrc((const char*)base + (size_t)step0 * 64 * esz, 0xFFFFFFFFu);
-    };
+    // one buffer view per array over the slot's steps; a chunk adds its first
+    // prefetched step as a uniform offset
+    const unsigned nposs = (unsigned)Tp * 64u;
+    const rsrc_t RRB = mkrsrc(REC, nposs * 8u);
+    const rsrc_t RXB = mkrsrc(XQ, nposs * (unsigned)sizeof(VX));
+    const rsrc_t RFB = MODE == M2_TAUGRAD ? mkrsrc(XF, nposs * (unsigned)sizeof(VX)) : RXB;
+    const rsrc_t RCB = MODE == M2_SECOND ? mkrsrc(XC, nposs * (unsigned)sizeof(VR)) : RXB;
     int2 RR[KD];
     VX RX[KD];
     VX RXF[KD];
     VR RC[KD];
     {
-      const rsrc_t rr = vbase(REC, 8, 0), rx = vbase(XQ, sizeof(VX), 0);
-      const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), 0) : rx;
-      const rsrc_t rc = MODE == M2_SECOND ? vbase(XC, sizeof(VR), 0) : rx;
 #pragma unroll
       for (int u = 0; u < KD; ++u) {
-        RR[u] = ldrec_b(rr, lo_rec, u * 64 * 8);
-        RX[u] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
-        if (MODE == M2_TAUGRAD) RXF[u] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
-        if (MODE == M2_SECOND) RC[u] = ldv<VR>(rc, lo_xc, u * 64 * (int)sizeof(VR));
+        RR[u] = ldrec_b(RRB, lo_rec, u * 64 * 8);
+        RX[u] = ldv<VX>(RXB, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_TAUGRAD) RXF[u] = ldv<VX>(RFB, lo_xq, u * 64 * (int)sizeof(VX));
+        if (MODE == M2_SECOND) RC[u] = ldv<VR>(RCB, lo_xc, u * 64 * (int)sizeof(VR));
       }
+    }
+
+    // 3D plane link and block link. Lane l's chunk-step u is column
+    // (u - l) mod kC2 of its block: column 0 at u = l mod kC2 (plane period
+    // q = ch - l/kC2 of chunk ch), the last column at u = (l + 1) mod kC2
+    // (period ch - (l + kC2 - 1)/kC2). zreg[u]: the value of chunk-step u one
+    // chunk earlier (the same column one plane back); xl: the step-axis value
+    // of this chunk's column-0 step, xn: the next chunk's (in flight). The
+    // last-column value is read back from the chunk's staged sums (the lane's
+    // own values) and stored at the end of the chunk to the period's plane.
+    VR zreg[L3 ? kC2 : 1], xl, xn;
+    int qL = 0, pL = 0, qS = 0, pS = 0;  // period and plane of the next load / store
+    if constexpr (L3) {
+#pragma unroll
+      for (int u = 0; u < kC2; ++u)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) zreg[u][k] = T(0);
+      auto pmod = [&](int q) BTE_INL { return ((q % n_pl) + n_pl) % n_pl; };
+      qL = -(lane / kC2);
+      pL = pmod(qL);
+      auto xload = [&]() BTE_INL {
+        const VR v = ldv_glc<VR>(ZRR, qL >= 0 && qL < I.n_per ? pL * zrow + lo_z : kOOB, 0);
+        ++qL;
+        pL = pL + 1 == n_pl ? 0 : pL + 1;
+        return v;
+      };
+      xl = xload();
+      xn = xload();
+      qS = -((lane + kC2 - 1) / kC2);
+      pS = pmod(qS);
     }
 
     // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
@@ -323,16 +418,42 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     wt_.init(lane - 63, r, R, du, n_strip);
     T ghv[G];
     int wcv;
-    auto chunk_cols = [&]() {
+    // 3D: lane 0's lane-axis wall values, pipelined so that no chunk waits on
+    // a gather: ghv holds chunk c's values (lane m: step m), ghn the raw
+    // gathered values of chunk c+1, gsl the wall slots (+1, 0: none) of chunk c+2
+    T ghn = T(0);
+    int gsl = 0, gch = 0;  // gch: chunk of the slots to load next
+    const rsrc_t GPR = mkrsrc(L3 ? gp(I.gpre) + (size_t)o * T_steps : nullptr, L3 ? (unsigned)T_steps * 4u : 0u);
+    auto gslot = [&]() BTE_INL {
+      const int t = gch * kC2 + lane;
+      ++gch;
+      return bld<int>(GPR, lane < kC2 ? t * 4 : kOOB);
+    };
+    auto ggather = [&](int g1) BTE_INL { return bld<T>(UBR, g1 > 0 ? (g1 - 1) * (int)sizeof(T) : kOOB); };
+    if constexpr (L3) {
+      ghv[0] = ggather(gslot()) * den[0];
+      ghn = ggather(gslot());
+      gsl = gslot();
+    }
+    auto chunk_cols = [&]() BTE_INL {
       const bool gok = lane < kC2 && gt_.valid(n_strip, nx);
-      const bool wok = lane < kC2 && wt_.valid(n_strip, nx) && wt_.s * H + H - 1 < ny;
+      if constexpr (L3) {
+        // the gather issued a chunk ago, then the next one and the slots after
+        ghv[0] = ghn * den[0];
+        ghn = ggather(gsl);
+        gsl = gslot();
+        wcv = W_max * G;
+        (void)gok;
+      } else {
 #pragma unroll
-      for (int g = 0; g < G; ++g) ghv[g] = gok ? prev_ring[gt_.v * G + g] : T(0);
-      wcv = (wok ? wt_.v : W_max) * G;
+        for (int g = 0; g < G; ++g) ghv[g] = gok ? prev_ring[gt_.v * G + g] : T(0);
+        const bool wok = lane < kC2 && wt_.valid(n_strip, nx) && wt_.s * H + H - 1 < ny;
+        wcv = (wok ? wt_.v : W_max) * G;
+      }
       gt_.advance(kC2, R);
       wt_.advance(kC2, R);
     };
-    chunk_cols();
+    if constexpr (!L3) chunk_cols();
     // per-chunk flags (CF2_*), uniform: scalar loads from read-only memory
     const CAS int* CFL = cp(I.chunk_fl) + slot * (nch + 1);
     int cfl = CFL[0];
@@ -369,7 +490,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     constexpr int PQ = PIPE ? P : 1;
     VR wraw[NACC][MB][PQ];
     // read a batch of pairs of chunk chw (its records and every wave's sums)
-    auto wo_read = [&](int b, int chw) {
+    auto wo_read = [&](int b, int chw) BTE_INL {
       const int bw = chw & 1;
       const int* scr = scid + (bw * R + r) * kC2 * CS;
 #pragma unroll
@@ -393,7 +514,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
     };
     // add the batch's partials and store the lane's rows (inactive cells'
     // entries are ignored by the finalize); `on` false: nothing
-    auto wo_store = [&](bool on) {
+    auto wo_store = [&](bool on) BTE_INL {
 #pragma unroll
       for (int mi = 0; mi < MB; ++mi) {
         const int v = on ? wvv[mi] : -1;
@@ -411,28 +532,63 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       }
     };
 
+    // ---- 3D: a chunk's reflecting-wall outflows, read back from its staged
+    //      values (one ordinate per lane: the staged temperature partial of
+    //      the wave is the lane's own value) and written to the out-stream
+    //      after the chunk; oe holds the entries of chunk `c`, och its stream
+    //      offset, and the entries of the chunk after are loaded behind them
+    constexpr int kOPL = 4;  // entries per lane per chunk (<= 256 per chunk)
+    int oe[kOPL];
+    int och = 0;
+    const int NOE = L3 ? I.out_E >> 6 : 0;
+    const rsrc_t OTR = mkrsrc(L3 ? gp(I.out_tab) + (size_t)o * (nch + 2) * I.out_E : nullptr,
+                              L3 ? (unsigned)((nch + 2) * I.out_E) * 4u : 0u);
+    const CAS int* OCH = L3 ? cp(I.out_chunk) + (size_t)o * (nch + 1) : nullptr;
+    auto out_load = [&](int c) BTE_INL {
+#pragma unroll
+      for (int m = 0; m < kOPL; ++m) oe[m] = bld<int>(OTR, m < NOE ? (c * I.out_E + m * 64 + lane) * 4 : kOOB);
+    };
+    if constexpr (L3) {
+      out_load(0);
+      och = OCH[0];
+    }
+    auto emit = [&](int c) BTE_INL {
+      const T* sb = stage + (size_t)(NACC == 1 ? (c & 1) : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
+      // the axis weight of an entry by arithmetic (a select between the
+      // three would be turned into an indexed read of a stack copy)
+      const T wA = wo0[0], wB = wo1[0] - wo0[0], wC = wo2[0] - wo1[0];
+#pragma unroll
+      for (int m = 0; m < kOPL; ++m) {
+        const int e = oe[m] - 1;  // stored + 1 (0: no entry, also what a read past the table gives)
+        const int idx = e >> 2, d = e & 3;
+        const T v = sb[(e >= 0 ? idx / (64 * NR) : 0) * RS + (idx & (64 * NR - 1))];
+        const T w = fma(T(d >= 2), wC, fma(T(d >= 1), wB, wA));
+        bst(w * v, OUR, e >= 0 ? (och + m * 64 + lane) * (int)sizeof(T) : kOOB);
+      }
+      out_load(c + 1);
+      och = OCH[min(c + 1, nch)];
+    };
+
     // ---- one chunk of kC2 steps; IN: 0 no flagged inflow entries in the
     //      chunk, 1 x-inflows and row-0 y-inflows only (folded into the chain
     //      inputs), 2 any inflow (its own chain with selects); OUT: reflecting-wall
     //      outflow entries present; XS: lanes entering their strip at the x wall
     //      (F2_XSTART), whose x-inflows are read from LDS a step ahead
-    auto chunk = [&](auto in_tag, auto out_tag, auto xs_tag, const int ch) {
+    auto chunk = [&](auto in_tag, auto out_tag, auto xs_tag, const int ch) BTE_INL {
       constexpr int IN = decltype(in_tag)::value;
-      constexpr bool OUT = decltype(out_tag)::value;
-      constexpr bool XS = decltype(xs_tag)::value;
+      constexpr bool OUT = decltype(out_tag)::value && !L3;  // 3D: outflows leave after the chunk
+      constexpr bool XS = decltype(xs_tag)::value && !L3;  // 3D: every inflow goes through the stream
       const int bufi = ch & 1;
       const T* inbuf = my_inb + bufi * E;
       T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
       int* scw = scid + (bufi * R + r) * kC2 * CS;
       int out_cnt = 0;
-      const rsrc_t rr = vbase(REC, 8, ch * kC2 + KD), rx = vbase(XQ, sizeof(VX), ch * kC2 + KD);
-      const rsrc_t rf = MODE == M2_TAUGRAD ? vbase(XF, sizeof(VX), ch * kC2 + KD) : rx;
-      const rsrc_t rc = MODE == M2_SECOND ? vbase(XC, sizeof(VR), ch * kC2 + KD) : rx;
+      const int s0 = (ch * kC2 + KD) * 64;  // first position prefetched in this chunk
       // strip-entry x-inflows of the step about to run (read one step ahead;
       // the chunk's first step reads its own after the chunk barrier)
       // (two register sets by step parity, so no value is copied)
       T xv[2][NR];
-      auto read_xv = [&](const int2 rnext, T* dst) {
+      auto read_xv = [&](const int2 rnext, T* dst) BTE_INL {
         // a lane-step's entries end inside the chunk's stream: clamping the
         // offset keeps the reads of the other lanes in bounds
         const int e0 = min((int)(((unsigned)rnext.y >> F2_INOFF_SHIFT) & F2_INOFF_MASK), E - NR);
@@ -442,7 +598,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       };
       if constexpr (XS) read_xv(RR[0], xv[0]);
 
-      auto step = [&](const int u) {
+      auto step = [&](const int u) BTE_INL {
         const int sl = u % KD;
         const int2 rec = RR[sl];
         // both halves of the record stay live until here, whatever the body
@@ -452,6 +608,22 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         const VX xq = RX[sl];
         VX xf;
         if (MODE == M2_TAUGRAD) xf = RXF[sl];
+        // 3D: the plane-axis upwind values (chunk-step u one chunk back) and
+        // the step-axis ones (the previous column, or for the block's first
+        // column the buffer value)
+        // (3D: the previous step's values are zreg[um], so the lane's own
+        // state is the delay line alone)
+        const int um = (u + kC2 - 1) % kC2;
+        VR zr;
+        T xin[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) xin[k] = f[0][k];
+        if constexpr (L3) {
+          zr = zreg[u];
+          const bool c0 = (lane & (kC2 - 1)) == u;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) xin[k] = c0 ? xl[k] : zreg[um][k];
+        }
         const unsigned fl = (unsigned)rec.y;
         T S[NR];
 #pragma unroll
@@ -466,7 +638,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         // lane 0 takes the ring value of this step
         T zc[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), f[g][NR - 1]);
+        for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), L3 ? zreg[um][NR - 1] : f[g][NR - 1]);
 
         // a lane entering its strip at the x wall takes its x-inflows as the
         // rows' x-upwind values (after the lane below has had the old top row)
@@ -479,8 +651,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           if (u + 1 < kC2) read_xv(RR[(u + 1) % KD], xv[(u + 1) & 1]);
         }
 
-        constexpr unsigned kInAll = rowmask(F2_INX | F2_INY, NR);
-        if (IN == 1 && __ballot(fl & kInAll) != 0ull) {
+        constexpr unsigned kInAll = rowmask(B_INX | B_INY | B_INZ, NR, RB);
+        if (!L3 && IN == 1 && __ballot(fl & kInAll) != 0ull) {
           // x-inflows replace the rows' x-upwind values and a row-0 y-inflow
           // the lane-below value before the common chain (the lane's entries:
           // rows ascending, x before y, from its offset)
@@ -500,21 +672,25 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           }
         }
         if (IN == 2 && __ballot(fl & kInAll) != 0ull) {
-          // entries of this lane: rows ascending, x before y, from its offset
+          // entries of this lane: rows ascending, then the step, lane and
+          // plane axes, from its offset
           const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
-            const unsigned b = fl >> (F2_ROW_BITS * k);
-            const unsigned below = fl & kInAll & ((1u << (F2_ROW_BITS * k)) - 1u);
+            const unsigned b = fl >> (RB * k);
+            const unsigned below = fl & kInAll & ((1u << (RB * k)) - 1u);
             const int ex = e0 + __builtin_popcount(below);
-            const int ey = ex + ((b & F2_INX) ? 1 : 0);
+            const int ey = ex + ((b & B_INX) ? 1 : 0);
             const T vx = inbuf[min(ex, E - 1)];
             const T vy = inbuf[min(ey, E - 1)];
+            T vz = T(0);
+            if constexpr (L3) vz = inbuf[min(ey + ((b & B_INY) ? 1 : 0), E - 1)];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-              const T xu = (b & F2_INX) ? vx * den[g] : f[g][k];
-              const T zu = (b & F2_INY) ? vy * den[g] : zc[g];
-              const T fn = fma(a1[g], zu, fma(a0[g], xu, S[k]));
+              const T xu = (b & B_INX) ? vx * den[g] : (L3 ? xin[k] : f[g][k]);
+              const T zu = (b & B_INY) ? vy * den[g] : zc[g];
+              T fn = fma(a1[g], zu, fma(a0[g], xu, S[k]));
+              if constexpr (L3) fn = fma(a2[g], (b & B_INZ) ? vz * den[g] : zr[k], fn);
               f[g][k] = fn;
               zc[g] = fn;
             }
@@ -525,10 +701,21 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-              const T fn = fma(a1[g], zc[g], fma(a0[g], f[g][k], S[k]));
+              // the lane-axis value (the step's critical chain) enters last
+              T fn;
+              if constexpr (L3)  // accumulated in the plane-link value's register
+                fn = fma(a1[g], zc[g],
+                         fma(a0[g], xin[k], fma(kS, xq[2 * k], fma(cQ, xq[2 * k + 1], a2[g] * zr[k]))));
+              else
+                fn = fma(a1[g], zc[g], fma(a0[g], f[g][k], S[k]));
               f[g][k] = fn;
               zc[g] = fn;
             }
+        }
+        if constexpr (L3) {
+          // the plane link of the next chunk
+#pragma unroll
+          for (int k = 0; k < NR; ++k) zreg[u][k] = f[0][k];
         }
 
         // ---- fused band/direction sums of the rows, staged for the workgroup
@@ -557,19 +744,19 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         }
 
         // ---- reflecting-wall outflow stream: rows, then axes, then lanes
-        constexpr unsigned kOutAll = rowmask(F2_OUTX | F2_OUTY, NR);
+        constexpr unsigned kOutAll = rowmask(B_OUTX | (B_OUTX << 1) | (L3 ? B_OUTX << 2 : 0u), NR, RB);
         if (OUT && __ballot(fl & kOutAll) != 0ull) {
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
 #pragma unroll
-            for (int d = 0; d < 2; ++d) {
-              const unsigned bit = (F2_OUTX << d) << (F2_ROW_BITS * k);
+            for (int d = 0; d < ND; ++d) {
+              const unsigned bit = (B_OUTX << d) << (RB * k);
               const unsigned long long m = __ballot(fl & bit);
               if (m != 0ull) {
                 if (fl & bit) {
                   T v = T(0);
 #pragma unroll
-                  for (int g = 0; g < G; ++g) v = fma(d == 0 ? wo0[g] : wo1[g], f[g][k], v);
+                  for (int g = 0; g < G; ++g) v = fma(d == 0 ? wo0[g] : (d == 1 ? wo1[g] : wo2[g]), f[g][k], v);
                   my_outb[out_cnt + lanes_below(m)] = v;
                 }
                 out_cnt += __popcll(m);
@@ -582,7 +769,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         if ((MODE == M2_STORE || MODE == M2_SECOND) && rec.x >= 0) {
 #pragma unroll
           for (int k = 0; k < NR; ++k)
-            if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
+            if ((fl >> (RB * k)) & B_ACT) {
               GAS T* su =
                   gp(reinterpret_cast<T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 5) + k * dy) * G);
 #pragma unroll
@@ -594,7 +781,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
           const CAS T* wt1 = gt + go_wt(G, 1);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
-            if ((fl >> (F2_ROW_BITS * k)) & F2_ACT) {
+            if ((fl >> (RB * k)) & B_ACT) {
               const GAS T* su =
                   gp(reinterpret_cast<const T*>(I.store_u) + ((size_t)g_loc * I.ncell + (rec.x >> 5) + k * dy) * G);
               double s0 = 0.0, s1 = 0.0;
@@ -613,6 +800,8 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         if constexpr (PIPE) {
           if (u % 2 == 0 && u / 2 < NB) wo_read(u / 2, ch - 1);
           if (u % 2 == 1 && u / 2 < NB) wo_store(ch > 0);
+          // and its outflows
+          if (L3 && u == kC2 - 3 && ch > 0) emit(ch - 1);
         }
         // ---- inflow pipeline, one stream row per step at the chunk's end,
         //      rows in descending order: values of chunk ch+1 to LDS (a row
@@ -630,10 +819,10 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         //      fence keeps the loads after the last use of the old values, so
         //      every slot is reloaded in place
         __builtin_amdgcn_sched_barrier(0);
-        RR[sl] = ldrec_b(rr, lo_rec, u * 64 * 8);
-        RX[sl] = ldv<VX>(rx, lo_xq, u * 64 * (int)sizeof(VX));
-        if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(rf, lo_xq, u * 64 * (int)sizeof(VX));
-        if (MODE == M2_SECOND) RC[sl] = ldv<VR>(rc, lo_xc, u * 64 * (int)sizeof(VR));
+        RR[sl] = ldrec_b(RRB, lo_rec, (s0 + u * 64) * 8);
+        RX[sl] = ldv<VX>(RXB, lo_xq, (s0 + u * 64) * (int)sizeof(VX));
+        if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(RFB, lo_xq, (s0 + u * 64) * (int)sizeof(VX));
+        if (MODE == M2_SECOND) RC[sl] = ldv<VR>(RCB, lo_xc, (s0 + u * 64) * (int)sizeof(VR));
       };
 #pragma unroll
       for (int u = 0; u < kC2; ++u) step(u);
@@ -641,6 +830,20 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
       // ---- end of chunk: the staged sums, the ring and the outflow entries
       //      of every wave are complete
       lds_barrier();
+      if constexpr (L3) {
+        // the block's last column of this chunk's period to its plane; the
+        // column-0 value of the chunk after the next one (its plane was
+        // written at least a chunk ago: four or more planes)
+        // (the lane's last column is chunk step u = l - 1 mod kC2)
+        const VR xs = *reinterpret_cast<const VR*>(stg0 + ((lane + kC2 - 1) & (kC2 - 1)) * RS + lane * NR);
+        stv(xs, ZRR, qS >= 0 && qS < I.n_per ? pS * zrow + lo_z : kOOB, 0);
+        ++qS;
+        pS = pS + 1 == n_pl ? 0 : pS + 1;
+        xl = xn;
+        xn = ldv_glc<VR>(ZRR, qL >= 0 && qL < I.n_per ? pL * zrow + lo_z : kOOB, 0);
+        ++qL;
+        pL = pL + 1 == n_pl ? 0 : pL + 1;
+      }
       // flags of the next chunk were read a chunk ago; read the one after
       cfl = cfl_next;
       cfl_next = CFL[min(ch + 2, nch)];
@@ -656,8 +859,9 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         out_tot += out_cnt;
       }
       if constexpr (!PIPE) {
-        // single-buffered staging: write the chunk out now, then wait for
-        // every reader before the next chunk stages again
+        // single-buffered staging: write the chunk (and its outflows) out
+        // now, then wait for every reader before the next chunk stages again
+        if constexpr (L3) emit(ch);
 #pragma unroll
         for (int b = 0; b < PAIRS / MB; ++b) {
           wo_read(b, ch);
@@ -727,6 +931,7 @@ __global__ void __launch_bounds__(256) sweep2d_kernel(SweepArgs A) {
         wo_read(b, nch - 1);
         wo_store(nch > 0);
       }
+      if (L3 && nch > 0) emit(nch - 1);
     }
 
     if (MODE == M2_TAUGRAD) {

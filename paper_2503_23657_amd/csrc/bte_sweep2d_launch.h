@@ -29,9 +29,9 @@ static inline int dyn_lds_limit_2d(const void* k) {
   return dyn;
 }
 
-template <typename T, int G, int NR, int P, int NACC, int MODE>
+template <typename T, int G, int NR, int P, int NACC, int MODE, bool L3 = false>
 static hipError_t launch2d_one(const SweepArgs& a, int grid, int block, size_t lds, hipStream_t st) {
-  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE>;
+  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE, L3>;
   static int lim = -1;
   if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
   if ((long long)lds > lim) return hipErrorInvalidValue;
@@ -39,10 +39,10 @@ static hipError_t launch2d_one(const SweepArgs& a, int grid, int block, size_t l
   return hipGetLastError();
 }
 
-template <typename T, int G, int NR, int P, int NACC, int MODE>
+template <typename T, int G, int NR, int P, int NACC, int MODE, bool L3 = false>
 static int occ2d_one(int block, size_t lds) {
   int n = 0;
-  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE>;
+  auto k = sweep2d_kernel<T, G, NR, P, NACC, MODE, L3>;
   static int lim = -1;
   if (lim < 0) lim = dyn_lds_limit_2d(reinterpret_cast<const void*>(k));
   if ((long long)lds > lim) return 0;
@@ -111,5 +111,38 @@ static int occ2d_one(int block, size_t lds) {
 #define BTE2D_UNIT_WITH_SECOND(T_, G_, SUFFIX)                                    \
   BTE2D_UNIT_IMPL(T_, G_, SUFFIX, BTE2D_DISPATCH_SECOND(T_, G_, launch2d_one, a, grid, block, lds, st), \
                   BTE2D_DISPATCH_SECOND(T_, G_, occ2d_one, block, lds))
+
+// 3D rows-per-lane variants: one ordinate per lane, NR in {1, 2}, P in
+// {1, 2, 4, 8}, (NACC, mode) in {(1, plain), (4, plain: flux iterations),
+// (1, store), (2, tau-gradient)}
+#define BTE3R_CASE(T_, NR_, P_, N_, M_, FN, ...) \
+  case BTE2D_KEY(NR_, P_, N_, M_): return FN<T_, 1, NR_, P_, N_, M_, true>(__VA_ARGS__);
+#define BTE3R_CASES_P(T_, NR_, P_, FN, ...)       \
+  BTE3R_CASE(T_, NR_, P_, 1, 0, FN, __VA_ARGS__) \
+  BTE3R_CASE(T_, NR_, P_, 4, 0, FN, __VA_ARGS__) \
+  BTE3R_CASE(T_, NR_, P_, 1, 1, FN, __VA_ARGS__) \
+  BTE3R_CASE(T_, NR_, P_, 2, 2, FN, __VA_ARGS__)
+#define BTE3R_DISPATCH(T_, FN, ...)               \
+  switch (BTE2D_KEY(NR, P, nacc, mode)) {         \
+    BTE3R_CASES_P(T_, 1, 1, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 1, 2, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 1, 4, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 1, 8, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 2, 1, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 2, 2, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 2, 4, FN, __VA_ARGS__)      \
+    BTE3R_CASES_P(T_, 2, 8, FN, __VA_ARGS__)      \
+    default: break;                               \
+  }
+#define BTE3R_UNIT(T_, SUFFIX)                                                                          \
+  hipError_t launch_sweep3r_##SUFFIX(int NR, int P, int nacc, int mode, const SweepArgs& a, int grid, \
+                                     int block, size_t lds, hipStream_t st) {                         \
+    BTE3R_DISPATCH(T_, launch2d_one, a, grid, block, lds, st)                                         \
+    return hipErrorInvalidValue;                                                                      \
+  }                                                                                                   \
+  int sweep3r_blocks_per_cu_##SUFFIX(int NR, int P, int nacc, int mode, int block, size_t lds) {      \
+    BTE3R_DISPATCH(T_, occ2d_one, block, lds)                                                         \
+    return 0;                                                                                         \
+  }
 
 }  // namespace bte

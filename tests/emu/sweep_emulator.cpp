@@ -57,6 +57,7 @@ int main(int argc, char** argv) {
   auto ords = fold_ordinates(&qq, dim);
   Plan plan{G, R, P, Cc, NR};
   if (dim == 3) plan.R = 1;
+  if (dim == 3 && NR == 0) plan.C = Cc;
   if (dim < 3) plan.C = Cc = kC2;
   Schedule S;
   std::string err;
@@ -362,11 +363,148 @@ int main(int argc, char** argv) {
       }
     }
   };
+  // 3D rows-per-lane kernel: lane l owns rows NR*l + k along the lane axis;
+  // the step axis is cut into blocks of kC2 columns and every lane runs
+  // through block b, plane p, column c at position s = (b*n_pl + p)*kC2 + c,
+  // taking position s at clock t = s + l. Its plane-axis upwind value is its
+  // own value of chunk step t mod kC2 one chunk earlier (zreg), its step-axis
+  // upwind value the previous step's, except in a block's first column: there
+  // the value its per-plane buffer held when it was loaded, at the end of the
+  // chunk two chunks back (the buffer takes each chunk's last-column values at
+  // the chunk's end, and is prefilled with the first block's wall values).
+  // Lane 0's lane-axis upwind value is the wall value of gpre; other wall
+  // values come from the inflow stream.
+  auto sweep3r = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
+                     bool adj, const std::vector<double>& ub, std::vector<double>& acc0, std::vector<double>& acc1,
+                     std::vector<double>* store, const std::vector<double>* stored, const std::vector<double>* dTf,
+                     std::vector<double>* tg) {
+    acc0.assign(ncell, 0.0);
+    acc1.assign(ncell, 0.0);
+    const int NR = S.NR;
+    const int Tp = T + kPad2, H = 64 * NR, nchk = T / kC2, npl = S.n_pl, nper = S.n_per;
+    const int stride[3] = {1, n0, n0 * n1};
+    const int FB = F3_ROW_BITS;
+    unsigned kInAll = 0;
+    for (int k = 0; k < NR; ++k) kInAll |= (F3_INX | F3_INY | F3_INZ) << (FB * k);
+    auto pmod = [&](int q) { return ((q % npl) + npl) % npl; };
+    for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
+      const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
+      const int dyc = (((o >> S.ax[1]) & 1) ? -1 : 1) * stride[S.ax[1]];
+      for (int p = 0; p < P; ++p) {
+        const int grp = gs.bundle_first[bu] + p;
+        const double* gt = cf.data() + (size_t)grp * GS;
+        const int band = gs.band[grp];
+        const int urow = has_spec ? band * Mf + std::max(0, gs.ords[(size_t)grp * G]) : band;
+        const double kS = gt[0], cQ = gt[1], den = gt[go_den(G)];
+        if (G != 1) { printf("3D rows layout with G > 1\n"); exit(2); }
+        std::vector<double> f(H, 0.0), zreg((size_t)kC2 * H, 0.0), xb((size_t)npl * H, 0.0);
+        std::vector<double> xl(H, 0.0), xn(H, 0.0), xs(H, 0.0);
+        // the first block's step-axis wall values
+        for (int pl = 0; pl < npl; ++pl)
+          for (int j = 0; j < H; ++j) {
+            const int sl = S.xpre[((size_t)o * npl + pl) * H + j];
+            xb[(size_t)pl * H + j] = sl >= 0 ? ub[(size_t)urow * nbf + sl] * den : 0.0;
+          }
+        std::vector<int> qL(64), qS(64);
+        auto xload = [&](int l, std::vector<double>& dst) {
+          const bool ok = qL[l] >= 0 && qL[l] < nper;
+          for (int k = 0; k < NR; ++k) dst[(size_t)l * NR + k] = ok ? xb[(size_t)pmod(qL[l]) * H + l * NR + k] : 0.0;
+          ++qL[l];
+        };
+        for (int l = 0; l < 64; ++l) {
+          qL[l] = -(l / kC2);
+          qS[l] = -((l + kC2 - 1) / kC2);
+          xload(l, xl);
+          xload(l, xn);
+        }
+        int out_cnt = 0;
+        for (int t = 0; t < T; ++t) {
+          const int ch = t / kC2, u = t % kC2;
+          const int* itab = &S.in_tab[((size_t)o * (nchk + 2) + ch) * S.in_E];
+          const int sg = S.gpre[(size_t)o * T + t];  // face slot + 1
+          const double gh = sg > 0 ? ub[(size_t)urow * nbf + sg - 1] * den : 0.0;
+          std::vector<double> fold = f, fnew = f;
+          std::vector<int2> ent(64);
+          for (int l = 0; l < 64; ++l) ent[l] = S.sched[((size_t)o * Tp + t) * 64 + l];
+          for (int l = 0; l < 64; ++l) {
+            if (ent[l].x < 0) continue;
+            const unsigned fl = (unsigned)ent[l].y;
+            const int cid0 = ent[l].x >> 5;
+            const int gm = ent[l].x & 15;
+            const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
+            const bool c0 = (l % kC2) == u;
+            double zc = l == 0 ? gh : fold[(size_t)(l - 1) * NR + NR - 1];
+            for (int k = 0; k < NR; ++k) {
+              const unsigned b = fl >> (FB * k);
+              if ((b & F3_ACT) && !((gm >> k) & 1)) { printf("bad grid mask\n"); exit(2); }
+              const bool act = (b & F3_ACT) != 0;
+              const int cell = act ? cid0 + k * dyc : -1;
+              const double S_ = act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0;
+              const unsigned below = fl & kInAll & ((1u << (FB * k)) - 1u);
+              const int ex = e0 + __builtin_popcount(below);
+              const int ey = ex + ((b & F3_INX) ? 1 : 0);
+              const int ez = ey + ((b & F3_INY) ? 1 : 0);
+              const double xin = c0 ? xl[(size_t)l * NR + k] : fold[(size_t)l * NR + k];
+              const double xu = (b & F3_INX) ? ub[(size_t)urow * nbf + itab[ex]] * den : xin;
+              const double yu = (b & F3_INY) ? ub[(size_t)urow * nbf + itab[ey]] * den : zc;
+              const double zr = zreg[(size_t)u * H + l * NR + k];
+              const double zu = (b & F3_INZ) ? ub[(size_t)urow * nbf + itab[ez]] * den : zr;
+              const double fn = gt[go_a(G, S.ax[2])] * zu + gt[go_a(G, S.ax[1])] * yu + gt[go_a(G, S.ax[0])] * xu + S_;
+              fnew[(size_t)l * NR + k] = fn;
+              zc = fn;
+              if (act) {
+                acc0[cell] += gt[go_wacc(G, 0)] * fn;
+                acc1[cell] += gt[go_wacc(G, 1)] * fn;
+                if (store) (*store)[(size_t)grp * ncell + cell] = fn * gt[go_inv(G)];
+                if (tg) {
+                  const double uf = (*stored)[(size_t)grp * ncell + cell];
+                  (*tg)[2 * grp] += gt[go_wt(G, 0)] * fn * (uf - (*dTf)[cell]);
+                  (*tg)[2 * grp + 1] += Xs[cell] * gt[go_wt(G, 1)] * uf;
+                }
+              }
+            }
+          }
+          // outflow stream: rows, then axes, then lanes
+          for (int k = 0; k < NR; ++k)
+            for (int e = 0; e < 3; ++e)
+              for (int l = 0; l < 64; ++l) {
+                const unsigned fl = (unsigned)ent[l].y;
+                if (ent[l].x < 0 || !((fl >> (FB * k)) & (F3_OUTX << e))) continue;
+                outv[(size_t)grp * S.n_out_stride + out_cnt++] = gt[go_wo(G, S.ax[e])] * fnew[(size_t)l * NR + k];
+              }
+          // the plane link and the last-column capture (idle lanes keep
+          // their values: nothing active reads them)
+          for (int l = 0; l < 64; ++l) {
+            if (ent[l].x < 0) continue;
+            const bool c7 = (l % kC2) == (u + 1) % kC2;
+            for (int k = 0; k < NR; ++k) {
+              zreg[(size_t)u * H + l * NR + k] = fnew[(size_t)l * NR + k];
+              if (c7) xs[(size_t)l * NR + k] = fnew[(size_t)l * NR + k];
+            }
+          }
+          f = fnew;
+          if (u == kC2 - 1) {
+            // end of chunk: last-column values to their planes, then the loads
+            for (int l = 0; l < 64; ++l) {
+              if (qS[l] >= 0 && qS[l] < nper)
+                for (int k = 0; k < NR; ++k) xb[(size_t)pmod(qS[l]) * H + l * NR + k] = xs[(size_t)l * NR + k];
+              ++qS[l];
+            }
+            for (int l = 0; l < 64; ++l) {
+              for (int k = 0; k < NR; ++k) xl[(size_t)l * NR + k] = xn[(size_t)l * NR + k];
+              xload(l, xn);
+            }
+          }
+        }
+      }
+    }
+  };
   auto run_sweep = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
                        bool adj, const std::vector<double>& ub, std::vector<double>& a0v, std::vector<double>& a1v,
                        std::vector<double>* store, const std::vector<double>* stored, const std::vector<double>* dTf,
                        std::vector<double>* tg) {
     if (dim < 3) sweep2d(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
+    else if (S.l3r) sweep3r(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
     else sweep(Xs, Qs, cf, adj, ub, a0v, a1v, store, stored, dTf, tg);
   };
   // lagged wall values from the last sweep's outflow entries. Forward: the

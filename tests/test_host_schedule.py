@@ -62,9 +62,20 @@ CASES = [
      (1, 1, 2, 8, 2)),
     ("holes_nr4_r2", lambda: bi.multi_hole_2d(50, 300, seed=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 2, 2, 8, 4)),
     ("holes_nr2_seq", lambda: bi.multi_hole_2d(30, 200, seed=5, n_bands=1, n_theta=1, n_phi=1), 3, (2, 1, 1, 8, 2)),
+    # 3D: NR = 0 selects the pencil-block layout, NR >= 1 the rows-per-lane one
     ("box3d_diffuse", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4,
-     (2, 1, 1, 8, 1)),
-    ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
+     (2, 1, 1, 8, 0)),
+    ("finfet_small", lambda: bi.finfet_3d(scale=8, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 0)),
+    ("box3d_rows", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1), 4,
+     (1, 1, 2, 8, 1)),
+    ("box3d_rows_p1", lambda: bi.random_box_3d(21, 17, 13, seed=2, n_bands=2, n_theta=1, n_phi=1), 4,
+     (1, 1, 1, 8, 1)),
+    ("box3d_rows_4planes", lambda: bi.random_box_3d(19, 70, 4, seed=7, n_bands=1, n_theta=1, n_phi=1), 3,
+     (1, 1, 4, 8, 1)),
+    ("box3d_rows_nr2", lambda: bi.random_box_3d(9, 70, 100, seed=3, n_bands=1, n_theta=1, n_phi=1), 3,
+     (1, 1, 2, 8, 1)),
+    ("finfet_rows", lambda: bi.finfet_3d(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
+    ("finfet_rows_mixed", lambda: bi.finfet_3d_mixed(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 1, 8, 1)),
     # specular walls (every boundary but the isothermal bottom, hole faces included)
     ("film_specular", lambda: _film_specular(), 6, (1, 1, 1, 8, 1)),
     ("box_specular", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)), 5,
@@ -72,7 +83,9 @@ CASES = [
     ("holes_specular_nr4_r2", lambda: bi.multi_hole_2d(50, 300, seed=4, n_bands=2, n_theta=1, n_phi=1,
                                                         kinds=(0, 2)), 3, (1, 2, 2, 8, 4)),
     ("box3d_specular", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)), 4,
-     (1, 1, 2, 8, 1)),
+     (1, 1, 2, 8, 0)),
+    ("box3d_specular_rows", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1,
+                                                      kinds=(0, 2)), 4, (1, 1, 2, 8, 1)),
 ]
 
 
@@ -120,7 +133,8 @@ def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
 
 
 @pytest.mark.parametrize("dim,kind,plan", [(2, 1, (2, 1, 1, 8, 1)), (2, 1, (1, 1, 2, 8, 2)), (2, 2, (1, 1, 1, 8, 1)),
-                                           (2, 2, (1, 2, 1, 8, 1)), (3, 1, (2, 1, 2, 8, 1)), (3, 2, (1, 1, 2, 8, 1))])
+                                           (2, 2, (1, 2, 1, 8, 1)), (3, 1, (2, 1, 2, 8, 0)), (3, 2, (1, 1, 2, 8, 0)),
+                                           (3, 1, (1, 1, 2, 8, 1)), (3, 2, (1, 1, 1, 8, 1))])
 def test_emulated_adjoint_with_walls_matches_dense(emu, tmp_path, dim, kind, plan):
     """Transposed sweeps with the wall-value adjoint (the transpose of the
     lagged diffuse or specular reflection) against complex-step derivatives of

@@ -151,9 +151,10 @@ struct InstDev {
   int ax[3];                // grid axis of the step, lane and plane axes
   int dyo[8];               // cell-index step from row k to row k + 1, per octant
   int n_pl;                 // planes
-  int n_per;                // plane periods of kC2 steps (blocks x planes)
+  int n_per;                // plane periods of kC2 steps (the most of any octant)
   const int* xpre;          // [n_oct][n_pl][64*nr] step-axis wall face of the first column's cells (-1)
-  const int* gpre;          // [n_oct][T] lane-axis wall face + 1 of lane 0's row 0 at each step (0: none)
+  const int* gpre;          // [n_oct][T + n_per] lane-axis wall face + 1 of lane 0's row 0 at each step
+                            //   (0: none), then the plane + 1 of each plane period (0: none)
   const int* out_tab;       // [n_oct][T/kC2 + 2][out_E] outflow entries of each chunk, read from the staging
                             //   ((((u*64 + l)*nr + k) << 2 | kernel axis) + 1, 0 pad)
   const int* out_chunk;     // [n_oct][T/kC2 + 1] stream offset of each chunk's first outflow entry

@@ -538,16 +538,21 @@ static bool build_schedule_2d(const HostInst& hi, const Plan& plan, Schedule& s,
 // 3D rows-per-lane schedule for one choice of the lane and plane axes (the
 // step axis is x, so that consecutive steps of a lane are consecutive cells).
 // The step axis is cut into blocks of C = kC2 columns. Every lane runs
-// through the same sequence of positions: block after block, in a block plane
-// after plane, in a plane the block's C columns; lane l takes position
-// s = t - l at clock step t (s = (b*n_pl + p)*C + c: block b, plane p, column
-// c). So lane l works on the cell lane l-1 had one step before (the lane-axis
-// link), its plane-axis upwind cell is its own position s - C (the value it
-// computed C steps earlier, kept in registers) and, inside a block, its
-// step-axis upwind cell is position s - 1. The first column of a block takes
-// the step-axis value of the previous block's last column in the same plane,
-// which every lane keeps per plane in a buffer of its own; for the first block
-// that buffer is prefilled with the wall faces of xpre. Lane 0's row 0 takes
+// through the same sequence of positions: block after block, in a block the
+// planes from the first to the last that hold an active cell of the block (in
+// sweep order), in a plane the block's C columns; lane l takes position
+// s = t - l at clock step t (s = q*C + c: plane period q, column c; the period
+// table ptab gives the plane of each period). So lane l works on the cell lane
+// l-1 had one step before (the lane-axis link), its plane-axis upwind cell is
+// its own position s - C (the value it computed C steps earlier, kept in
+// registers; at a block's first plane that cell is inactive or outside, and
+// the inflow is a stream entry) and, inside a block, its step-axis upwind
+// cell is position s - 1. The first column of a block takes the step-axis
+// value of the previous block's last column in the same plane, which every
+// lane keeps per plane in a buffer of its own (a plane the previous block
+// skipped left no value there: its cells are inactive, so the inflow is a
+// stream entry); for the first block that buffer is prefilled with the wall
+// faces of xpre. Lane 0's row 0 takes
 // the lane-axis wall face of gpre at each step (stored as slot + 1, 0: none).
 // Every other boundary value (the first plane's walls included) is an entry
 // of the inflow stream, in order per step: lanes, rows ascending, step / lane
@@ -570,7 +575,48 @@ static bool build_3r_axes(const HostInst& hi, int A0, int A1, int A2, const Plan
     return false;
   }
   const int nb = (n0 + C - 1) / C;
-  const int n_per = nb * n2;
+  const int stride[3] = {1, hi.n[0], hi.n[0] * hi.n[1]};
+  const int ax[3] = {A0, A1, A2};
+  // per octant and block (sweep orientation): the planes it streams
+  std::vector<int> blo((size_t)8 * nb), bhi((size_t)8 * nb);
+  int n_per = 0;
+  for (int o = 0; o < 8; ++o) {
+    const bool f0 = (o >> A0) & 1, f2 = (o >> A2) & 1;
+    int np = 0;
+    for (int b = 0; b < nb; ++b) {
+      int lo = n2, hi_ = -1;
+      for (int v = b * C; v < std::min(n0, b * C + C); ++v)
+        for (int p = 0; p < n2; ++p)
+          for (int j = 0; j < n1; ++j) {
+            const int g0 = f0 ? n0 - 1 - v : v;
+            if (!hi.active[(size_t)g0 * stride[A0] + (size_t)j * stride[A1] + (size_t)p * stride[A2]]) continue;
+            const int ps = f2 ? n2 - 1 - p : p;
+            lo = std::min(lo, ps);
+            hi_ = std::max(hi_, ps);
+          }
+      blo[(size_t)o * nb + b] = lo;
+      bhi[(size_t)o * nb + b] = hi_;
+    }
+    // a plane two consecutive blocks share is stored by the first (at the end
+    // of its period's chunk) at least 3 periods before the second loads it
+    // (a chunk ahead): widen ranges that overlap by fewer planes
+    for (int b = 0; b + 1 < nb; ++b) {
+      int& h0 = bhi[(size_t)o * nb + b];
+      int& l1 = blo[(size_t)o * nb + b + 1];
+      if (h0 < 0 || l1 >= n2) continue;
+      while (h0 - l1 + 1 >= 1 && h0 - l1 + 1 < 3) {
+        if (h0 < n2 - 1)
+          ++h0;
+        else
+          --l1;
+      }
+    }
+    for (int b = 0; b < nb; ++b) {
+      const int lo = blo[(size_t)o * nb + b], hi_ = bhi[(size_t)o * nb + b];
+      np += hi_ >= lo ? hi_ - lo + 1 : 0;
+    }
+    n_per = std::max(n_per, np);
+  }
   const int T = n_per * C + 64;  // the last lane ends 63 steps after lane 0 (rounded to whole chunks)
   const int Tp = T + kPad2;
   s = Schedule();
@@ -608,11 +654,21 @@ static bool build_3r_axes(const HostInst& hi, int A0, int A1, int A2, const Plan
   s.out_base.assign(n_oct, 0);
   s.ofk.assign((size_t)n_oct * std::max(nbf, 1), -1);
   s.xpre.assign((size_t)n_oct * n2 * H, -1);
-  s.gpre.assign((size_t)n_oct * T, 0);
+  s.gpre.assign((size_t)n_oct * (T + n_per), 0);
   s.e_max = 1;
   s.o_max = 1;
-  const int stride[3] = {1, hi.n[0], hi.n[0] * hi.n[1]};
-  const int ax[3] = {A0, A1, A2};
+  // period -> (block, plane) of each octant; the plane + 1 also goes to the
+  // period table after the octant's gpre row
+  std::vector<int> per_b((size_t)n_oct * n_per, -1), per_p((size_t)n_oct * n_per, -1);
+  for (int o = 0; o < n_oct; ++o) {
+    int q = 0;
+    for (int b = 0; b < nb; ++b)
+      for (int p = blo[(size_t)o * nb + b]; p <= bhi[(size_t)o * nb + b]; ++p, ++q) {
+        per_b[(size_t)o * n_per + q] = b;
+        per_p[(size_t)o * n_per + q] = p;
+        s.gpre[(size_t)o * (T + n_per) + T + q] = p + 1;
+      }
+  }
   std::vector<int> out_face((size_t)NR * 3 * 64);
   std::vector<int> out_count(n_oct, 0);
   std::vector<std::vector<int>> out_ent(n_oct);
@@ -635,7 +691,8 @@ static bool build_3r_axes(const HostInst& hi, int A0, int A1, int A2, const Plan
         const int q = t - l;
         if (q < 0 || q >= n_per * C) continue;
         const int per = q / C, c = q % C;
-        const int bk = per / n2, pl = per % n2;
+        const int bk = per_b[(size_t)o * n_per + per], pl = per_p[(size_t)o * n_per + per];
+        if (bk < 0) continue;  // past this octant's periods
         const int v = bk * C + c;
         if (v >= n0) continue;
         const int in_first = (int)s.in_slot.size() - chk[t / C];
@@ -663,7 +720,7 @@ static bool build_3r_axes(const HostInst& hi, int A0, int A1, int A2, const Plan
             if (e == 0 && v == 0) {
               s.xpre[((size_t)o * n2 + pl) * H + jp] = su;
             } else if (e == 1 && jp == 0) {
-              s.gpre[(size_t)o * T + t] = su + 1;
+              s.gpre[(size_t)o * (T + n_per) + t] = su + 1;
             } else {
               fl |= (F3_INX << e) << sh;
               s.in_slot.push_back(su);

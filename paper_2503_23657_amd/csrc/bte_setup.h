@@ -79,9 +79,10 @@ struct Schedule {
   bool l3r = false;
   int ax[3] = {0, 1, 2};             // grid axis of the kernel's step, lane and plane axes
   int n_pl = 0;                      // planes (cells along the plane axis)
-  int n_per = 0;                     // plane periods of kC2 steps: blocks x planes
+  int n_per = 0;                     // plane periods of kC2 steps (the most of any octant)
   std::vector<int> xpre;             // [n_oct][n_pl][64*NR] step-axis wall face of the first column's cells (-1)
-  std::vector<int> gpre;             // [n_oct][T] lane-axis wall face + 1 of lane 0's row 0 at each step (0: none)
+  std::vector<int> gpre;             // [n_oct][T + n_per] lane-axis wall face + 1 of lane 0's row 0 at each
+                                     // step (0: none), then the plane + 1 of each plane period
   // reflecting-wall outflows, emitted per chunk from the staged values: entry
   // (((u*64 + l)*NR + k) << 2 | axis) + 1 of each outflow of chunk step u,
   // lane l, row k, in stream order (0 pad), and the stream offset of each chunk

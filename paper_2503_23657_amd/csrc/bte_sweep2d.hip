@@ -382,32 +382,33 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
 
     // 3D plane link and block link. Lane l's chunk-step u is column
     // (u - l) mod kC2 of its block: column 0 at u = l mod kC2 (plane period
-    // q = ch - l/kC2 of chunk ch), the last column at u = (l + 1) mod kC2
+    // q = ch - l/kC2 of chunk ch), the last column at u = l - 1 mod kC2
     // (period ch - (l + kC2 - 1)/kC2). zreg[u]: the value of chunk-step u one
     // chunk earlier (the same column one plane back); xl: the step-axis value
     // of this chunk's column-0 step, xn: the next chunk's (in flight). The
     // last-column value is read back from the chunk's staged sums (the lane's
     // own values) and stored at the end of the chunk to the period's plane.
+    // The plane of a period comes from the period table (plane + 1, 0: no
+    // period), read a chunk before it is needed.
     VR zreg[L3 ? kC2 : 1], xl, xn;
-    int qL = 0, pL = 0, qS = 0, pS = 0;  // period and plane of the next load / store
+    int qL = 0, qS = 0, pL1 = 0, pS1 = 0;  // period and plane + 1 of the next load / store
+    const rsrc_t GPR = mkrsrc(L3 ? gp(I.gpre) + (size_t)o * (T_steps + I.n_per) : nullptr,
+                              L3 ? (unsigned)(T_steps + I.n_per) * 4u : 0u);
+    auto ptab = [&](int q) BTE_INL { return bld<int>(GPR, q >= 0 && q < I.n_per ? (T_steps + q) * 4 : kOOB); };
+    auto xoff = [&](int p1) BTE_INL { return p1 > 0 ? (p1 - 1) * zrow + lo_z : kOOB; };
     if constexpr (L3) {
 #pragma unroll
       for (int u = 0; u < kC2; ++u)
 #pragma unroll
         for (int k = 0; k < NR; ++k) zreg[u][k] = T(0);
-      auto pmod = [&](int q) BTE_INL { return ((q % n_pl) + n_pl) % n_pl; };
       qL = -(lane / kC2);
-      pL = pmod(qL);
-      auto xload = [&]() BTE_INL {
-        const VR v = ldv_glc<VR>(ZRR, qL >= 0 && qL < I.n_per ? pL * zrow + lo_z : kOOB, 0);
-        ++qL;
-        pL = pL + 1 == n_pl ? 0 : pL + 1;
-        return v;
-      };
-      xl = xload();
-      xn = xload();
+      xl = ldv_glc<VR>(ZRR, xoff(ptab(qL)), 0);
+      ++qL;
+      xn = ldv_glc<VR>(ZRR, xoff(ptab(qL)), 0);
+      ++qL;
+      pL1 = ptab(qL);
       qS = -((lane + kC2 - 1) / kC2);
-      pS = pmod(qS);
+      pS1 = ptab(qS);
     }
 
     // ghost values (lane 0's upwind row) and ring-write offsets (lane 63's top
@@ -423,11 +424,10 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     // gathered values of chunk c+1, gsl the wall slots (+1, 0: none) of chunk c+2
     T ghn = T(0);
     int gsl = 0, gch = 0;  // gch: chunk of the slots to load next
-    const rsrc_t GPR = mkrsrc(L3 ? gp(I.gpre) + (size_t)o * T_steps : nullptr, L3 ? (unsigned)T_steps * 4u : 0u);
     auto gslot = [&]() BTE_INL {
       const int t = gch * kC2 + lane;
       ++gch;
-      return bld<int>(GPR, lane < kC2 ? t * 4 : kOOB);
+      return bld<int>(GPR, lane < kC2 && t < T_steps ? t * 4 : kOOB);
     };
     auto ggather = [&](int g1) BTE_INL { return bld<T>(UBR, g1 > 0 ? (g1 - 1) * (int)sizeof(T) : kOOB); };
     if constexpr (L3) {
@@ -836,13 +836,11 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         // written at least a chunk ago: four or more planes)
         // (the lane's last column is chunk step u = l - 1 mod kC2)
         const VR xs = *reinterpret_cast<const VR*>(stg0 + ((lane + kC2 - 1) & (kC2 - 1)) * RS + lane * NR);
-        stv(xs, ZRR, qS >= 0 && qS < I.n_per ? pS * zrow + lo_z : kOOB, 0);
-        ++qS;
-        pS = pS + 1 == n_pl ? 0 : pS + 1;
+        stv(xs, ZRR, xoff(pS1), 0);
+        pS1 = ptab(++qS);
         xl = xn;
-        xn = ldv_glc<VR>(ZRR, qL >= 0 && qL < I.n_per ? pL * zrow + lo_z : kOOB, 0);
-        ++qL;
-        pL = pL + 1 == n_pl ? 0 : pL + 1;
+        xn = ldv_glc<VR>(ZRR, xoff(pL1), 0);
+        pL1 = ptab(++qL);
       }
       // flags of the next chunk were read a chunk ago; read the one after
       cfl = cfl_next;

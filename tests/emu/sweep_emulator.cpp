@@ -365,8 +365,9 @@ int main(int argc, char** argv) {
   };
   // 3D rows-per-lane kernel: lane l owns rows NR*l + k along the lane axis;
   // the step axis is cut into blocks of kC2 columns and every lane runs
-  // through block b, plane p, column c at position s = (b*n_pl + p)*kC2 + c,
-  // taking position s at clock t = s + l. Its plane-axis upwind value is its
+  // through block b, plane p, column c at position s = q*kC2 + c (plane
+  // period q; the schedule's period table gives its plane), taking position s
+  // at clock t = s + l. Its plane-axis upwind value is its
   // own value of chunk step t mod kC2 one chunk earlier (zreg), its step-axis
   // upwind value the previous step's, except in a block's first column: there
   // the value its per-plane buffer held when it was loaded, at the end of the
@@ -386,7 +387,9 @@ int main(int argc, char** argv) {
     const int FB = F3_ROW_BITS;
     unsigned kInAll = 0;
     for (int k = 0; k < NR; ++k) kInAll |= (F3_INX | F3_INY | F3_INZ) << (FB * k);
-    auto pmod = [&](int q) { return ((q % npl) + npl) % npl; };
+    const int TP = T + nper;  // gpre row: wall slots per step, then the period table
+    // plane + 1 of period q of octant o (0: none)
+    auto ptab = [&](int o, int q) { return q >= 0 && q < nper ? S.gpre[(size_t)o * TP + T + q] : 0; };
     for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
       const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
       const int dyc = (((o >> S.ax[1]) & 1) ? -1 : 1) * stride[S.ax[1]];
@@ -407,8 +410,8 @@ int main(int argc, char** argv) {
           }
         std::vector<int> qL(64), qS(64);
         auto xload = [&](int l, std::vector<double>& dst) {
-          const bool ok = qL[l] >= 0 && qL[l] < nper;
-          for (int k = 0; k < NR; ++k) dst[(size_t)l * NR + k] = ok ? xb[(size_t)pmod(qL[l]) * H + l * NR + k] : 0.0;
+          const int p1 = ptab(o, qL[l]);
+          for (int k = 0; k < NR; ++k) dst[(size_t)l * NR + k] = p1 > 0 ? xb[(size_t)(p1 - 1) * H + l * NR + k] : 0.0;
           ++qL[l];
         };
         for (int l = 0; l < 64; ++l) {
@@ -421,7 +424,7 @@ int main(int argc, char** argv) {
         for (int t = 0; t < T; ++t) {
           const int ch = t / kC2, u = t % kC2;
           const int* itab = &S.in_tab[((size_t)o * (nchk + 2) + ch) * S.in_E];
-          const int sg = S.gpre[(size_t)o * T + t];  // face slot + 1
+          const int sg = S.gpre[(size_t)o * TP + t];  // face slot + 1
           const double gh = sg > 0 ? ub[(size_t)urow * nbf + sg - 1] * den : 0.0;
           std::vector<double> fold = f, fnew = f;
           std::vector<int2> ent(64);
@@ -486,8 +489,9 @@ int main(int argc, char** argv) {
           if (u == kC2 - 1) {
             // end of chunk: last-column values to their planes, then the loads
             for (int l = 0; l < 64; ++l) {
-              if (qS[l] >= 0 && qS[l] < nper)
-                for (int k = 0; k < NR; ++k) xb[(size_t)pmod(qS[l]) * H + l * NR + k] = xs[(size_t)l * NR + k];
+              const int p1 = ptab(o, qS[l]);
+              if (p1 > 0)
+                for (int k = 0; k < NR; ++k) xb[(size_t)(p1 - 1) * H + l * NR + k] = xs[(size_t)l * NR + k];
               ++qS[l];
             }
             for (int l = 0; l < 64; ++l) {

@@ -147,7 +147,8 @@ struct Inst {
   void* d_xqa[2] = {nullptr, nullptr};
   void* d_outv = nullptr;
   void* d_part = nullptr;
-  int part_ld = 0;  // padded row stride of d_part (cells)
+  int part_ld = 0;  // cells per job in a partial-sum plane (ncell padded to cell blocks)
+  int part_jg = 0;  // log2 of the jobs per group of a plane
   void* d_store = nullptr;
   double* d_tgrad = nullptr;
   void* d_corr = nullptr;         // second-order faces: [n_grp][pos_per_oct] correction
@@ -496,8 +497,12 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     HIPCHK(pp.alloc(&ov, (size_t)n_grp_inst * S.n_out_stride * es));
     I.d_outv = ov;
     char* pt;
-    I.part_ld = (I.hi.ncell + kPartAlign - 1) / kPartAlign * kPartAlign;
-    HIPCHK(pp.alloc(&pt, (size_t)kNAcc * n_bund * I.part_ld * es));
+    I.part_ld = (I.hi.ncell + kPartBlk - 1) / kPartBlk * kPartBlk;
+    // job groups: as many jobs as keep a group's part of a plane within the
+    // 32-bit offsets of a buffer view, and no more than the jobs there are
+    I.part_jg = 0;
+    while ((1 << I.part_jg) < n_bund && ((size_t)I.part_ld << (I.part_jg + 1)) * es < (1ull << 31)) ++I.part_jg;
+    HIPCHK(pp.alloc(&pt, (size_t)kNAcc * part_plane_len(n_bund, I.part_jg, I.part_ld) * es));
     I.d_part = pt;
     I.d_store = nullptr;
     I.stored = false;
@@ -547,6 +552,7 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
       d.outv = I.d_outv;
       d.part = I.d_part;
       d.part_ld = I.part_ld;
+      d.part_jg = I.part_jg;
       d.store_u = (!adj && h->order == 2) ? I.d_store : nullptr;
       d.corr = adj ? nullptr : I.d_corr;
       d.tgrad = I.d_tgrad;

@@ -18,27 +18,32 @@ struct FinShape {
   static constexpr int VW = 16 / (int)sizeof(T);       // cells per load
   static constexpr int NG = kFinCells / VW;             // cell groups per block
   static constexpr int S = kFinThreads / NG;            // job slices
-  static_assert(NG * S == kFinThreads && kPartAlign % VW == 0, "finalize shape");
+  static_assert(NG * S == kFinThreads && kPartBlk % VW == 0, "finalize shape");
 };
 
+// pl: the block's cell block of job 0 (a job group's blocks follow at
+// kPartBlk strides, the next group's 2^jg * part_ld elements on), c0: the
+// thread's first cell within it
 template <typename T>
-__device__ __forceinline__ void job_sum_vec(const T* pl, int n_jobs, int ld, int c0, int js, double* acc) {
+__device__ __forceinline__ void job_sum_vec(const T* pl, int n_jobs, int jg, int part_ld, int c0, int js,
+                                            double* acc) {
   using Sh = FinShape<T>;
   typedef T V __attribute__((ext_vector_type(Sh::VW)));
+  auto at = [&](int j) { return pl + part_job(j, jg, part_ld) + c0; };
 #pragma unroll
   for (int e = 0; e < Sh::VW; ++e) acc[e] = 0.0;
   int j = js;
   for (; j + 7 * Sh::S < n_jobs; j += 8 * Sh::S) {
     V v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const V*>(pl + (size_t)(j + u * Sh::S) * ld + c0);
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const V*>(at(j + u * Sh::S));
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int e = 0; e < Sh::VW; ++e) acc[e] += (double)v[u][e];
   }
   for (; j < n_jobs; j += Sh::S) {
-    const V v = *reinterpret_cast<const V*>(pl + (size_t)j * ld + c0);
+    const V v = *reinterpret_cast<const V*>(at(j));
 #pragma unroll
     for (int e = 0; e < Sh::VW; ++e) acc[e] += (double)v[e];
   }
@@ -48,7 +53,7 @@ __device__ __forceinline__ void job_sum_vec(const T* pl, int n_jobs, int ld, int
 // in LDS, and thread cl < kFinCells returns cell cl's total (pairwise over the
 // slices in a fixed order); the others return 0.
 template <typename T>
-__device__ __forceinline__ double plane_total(const T* pl, int n_jobs, int ld, int ncell, int cbase,
+__device__ __forceinline__ double plane_total(const T* pl, int n_jobs, int jg, int part_ld, int ncell, int cbase,
                                               double (*slc)[kFinCells]) {
   using Sh = FinShape<T>;
   const int t = threadIdx.x;
@@ -56,7 +61,7 @@ __device__ __forceinline__ double plane_total(const T* pl, int n_jobs, int ld, i
   const int c0 = cbase + gi * Sh::VW;
   double acc[Sh::VW];
   if (c0 < ncell) {
-    job_sum_vec(pl, n_jobs, ld, c0, js, acc);
+    job_sum_vec(pl + ((size_t)cbase << jg), n_jobs, jg, part_ld, gi * Sh::VW, js, acc);
   } else {
 #pragma unroll
     for (int e = 0; e < Sh::VW; ++e) acc[e] = 0.0;
@@ -123,15 +128,16 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
   const int cl = threadIdx.x;  // the cell of threads < kFinCells
   const int cbase = bi.y * kFinCells;
   const int c = cbase + cl;
-  const size_t plane = (size_t)I.n_jobs * I.part_ld;
+  const size_t plane = (size_t)part_plane_len(I.n_jobs, I.part_jg, I.part_ld);
   const T* part = reinterpret_cast<const T*>(I.part);
   const bool adj = (A.flags & FIN_ADJ) != 0, withq = (A.flags & FIN_Q) != 0;
   const int nq = withq ? (adj ? 1 : I.dim) : 0;
   // ---- per-cell totals of every needed plane (inactive cells' entries are
   //      gathered with their neighbours and dropped below)
   double tot[4];
-  tot[0] = plane_total(part, I.n_jobs, I.part_ld, I.ncell, cbase, slc);
-  for (int d = 0; d < nq; ++d) tot[1 + d] = plane_total(part + (size_t)(1 + d) * plane, I.n_jobs, I.part_ld, I.ncell, cbase, slc);
+  tot[0] = plane_total(part, I.n_jobs, I.part_jg, I.part_ld, I.ncell, cbase, slc);
+  for (int d = 0; d < nq; ++d)
+    tot[1 + d] = plane_total(part + (size_t)(1 + d) * plane, I.n_jobs, I.part_jg, I.part_ld, I.ncell, cbase, slc);
   const bool in_blk = cl < kFinCells && c < I.ncell;
   const bool act = in_blk && F.active[c];
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // sum dT^2, max |x|, sum d|q|^2, max |q| (+inf: non-finite)

@@ -129,8 +129,11 @@ struct InstDev {
   const void* xf;           // tau-gradient pass: forward (Delta T, Q) pairs per position
   const void* ubf;          // [B][n_bface] inflow u of every boundary face (K); zeros for the adjoint
   void* outv;               // [n_grp][n_out_entries_of_octant] outflow stream values
-  void* part;               // [kNAcc][n_jobs][part_ld] partial sums (sweep precision)
-  int part_ld;              // row stride of part: ncell rounded up to a multiple of 4
+  void* part;               // [kNAcc] planes of partial sums (sweep precision), each in groups of
+                            //   2^part_jg jobs, cell-block major inside a group:
+                            //   [n_jobs / 2^part_jg][part_ld / kPartBlk][2^part_jg][kPartBlk]
+  int part_ld;              // cells per job in a plane: ncell rounded up to a multiple of kPartBlk
+  int part_jg;              // log2 of the jobs per group (a group's part of a plane < 2 GiB)
   void* store_u;            // [n_grp][ncell][G] angular field u (forward, when stored)
   double* tgrad;            // [n_grp][2] tau-gradient partial sums
   int* status;              // StatusDev
@@ -214,7 +217,22 @@ struct SweepArgs {
 enum { FIN_Q = 1, FIN_CHECK = 2, FIN_ADJ = 4, FIN_QPREV = 8 };
 constexpr int kFinCells = 256;    // cells per finalize block
 constexpr int kFinThreads = 512;  // threads per finalize block: cell groups x job slices
-constexpr int kPartAlign = 4;     // partial-sum rows are padded to this many cells
+constexpr int kPartBlk = 256;     // cells per block of the partial-sum planes (= kFinCells)
+static_assert(kPartBlk == kFinCells, "a finalize block reads one cell block of every job");
+
+// offset (elements) of cell c from a job's first element in a partial-sum
+// plane with 2^jg jobs per group (a negative c gives a negative offset, which
+// buffer views drop), and of a job's first element from the plane's start
+__host__ __device__ constexpr int part_off(int c, int jg) {
+  return ((c >> 8) << (jg + 8)) + (c & (kPartBlk - 1));
+}
+__host__ __device__ constexpr long long part_job(int j, int jg, int part_ld) {
+  return ((long long)(j >> jg) * part_ld << jg) + (long long)(j & ((1 << jg) - 1)) * kPartBlk;
+}
+// elements of one partial-sum plane (whole groups)
+__host__ __device__ constexpr long long part_plane_len(int n_jobs, int jg, int part_ld) {
+  return ((long long)((n_jobs + (1 << jg) - 1) >> jg) << jg) * part_ld;
+}
 
 struct FinArgs {
   const InstDev* inst;

@@ -177,11 +177,14 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     const rsrc_t UBR = mkrsrc(UBF, (unsigned)I.n_bface * (unsigned)sizeof(T));
     const rsrc_t ISR = mkrsrc(ISLOT, (unsigned)ich[nch] * 4u);
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[o * R + r]);
-    const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
-    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
+    const size_t part_plane = (size_t)part_plane_len(I.n_jobs, I.part_jg, I.part_ld);
+    // (a view spans the job's group; a cell outside the grid lands past its
+    // end or in the job's own padding)
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + part_job(jd.jl, I.part_jg, I.part_ld));
+    const unsigned pgrp = (unsigned)(((size_t)I.part_ld << I.part_jg) - (size_t)(jd.jl & ((1 << I.part_jg) - 1)) * kPartBlk);
     rsrc_t PRS[NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
+    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, pgrp * (unsigned)sizeof(T));
     const int zmask = I.ring - 1;
     const int zlag = I.lag;
     // buffer view of this wave's global z ring (I.ring steps x 8 lanes x G)
@@ -436,7 +439,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           for (int a = 0; a < NACC; ++a) {
             T v = T(0);
             for (int q = 0; q < P; ++q) v += stage[((size_t)(q * R + r) * NACC * C + a * C + cc) * 65 + lp];
-            bst(v, PRS[a], cid >= 0 ? cid * (int)sizeof(T) : kOOB);
+            bst(v, PRS[a], cid >= 0 ? part_off(cid, I.part_jg) * (int)sizeof(T) : kOOB);
           }
         }
       }

@@ -281,8 +281,11 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
     GAS T* OUTV = gp(reinterpret_cast<T*>(I.outv) + (size_t)g_loc * I.n_out_stride + cp(I.out_base)[slot]);
-    const size_t part_plane = (size_t)I.n_jobs * I.part_ld;
-    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + (size_t)jd.jl * I.part_ld);
+    const size_t part_plane = (size_t)part_plane_len(I.n_jobs, I.part_jg, I.part_ld);
+    // (a view spans the job's group; a cell outside the grid lands past its
+    // end or in the job's own padding)
+    GAS T* PARTJ = gp(reinterpret_cast<T*>(I.part) + part_job(jd.jl, I.part_jg, I.part_ld));
+    const unsigned pgrp = (unsigned)(((size_t)I.part_ld << I.part_jg) - (size_t)(jd.jl & ((1 << I.part_jg) - 1)) * kPartBlk);
     // buffer views of the chunk loop's global data (sizes in bytes)
     const int out_b = cp(I.out_base)[slot];
     const rsrc_t UBR = mkrsrc(UBF, (unsigned)I.n_bface * (unsigned)sizeof(T));
@@ -290,7 +293,7 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     const rsrc_t OUR = mkrsrc(OUTV, (unsigned)(I.n_out_stride - out_b) * (unsigned)sizeof(T));
     rsrc_t PRS[NACC];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, (unsigned)I.ncell * (unsigned)sizeof(T));
+    for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, pgrp * (unsigned)sizeof(T));
     // 3D: this wave's step-axis buffer (a VR per plane and lane)
     const int n_pl = L3 ? I.n_pl : 1;
     const int zrow = 64 * NR * (int)sizeof(T);  // bytes per plane
@@ -527,7 +530,8 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
           // a row of the lane outside the grid has a cell index past either
           // end of the partial-sum plane, so the buffer's range check drops it
 #pragma unroll
-          for (int k = 0; k < NR; ++k) bst(sm[k], PRS[a], v >= 0 ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
+          for (int k = 0; k < NR; ++k)
+            bst(sm[k], PRS[a], v >= 0 ? part_off(cid0 + k * dy, I.part_jg) * (int)sizeof(T) : kOOB);
         }
       }
     };

@@ -72,8 +72,9 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-SOURCES_2D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_kutil.h")
-SOURCES_3D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_sweep3r_f.hip", "bte_kutil.h")
+SOURCES_2D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_kutil.h", "bte_device.h", "bte_strips.h")
+SOURCES_3D = ("bte_sweep2d.hip", "bte_sweep2d_launch.h", "bte_sweep3r_f.hip", "bte_kutil.h", "bte_device.h",
+              "bte_strips.h")
 
 
 def profiled_traffic(summary: str, kernel: str, files):

@@ -498,10 +498,14 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     I.d_outv = ov;
     char* pt;
     I.part_ld = (I.hi.ncell + kPartBlk - 1) / kPartBlk * kPartBlk;
-    // job groups: as many jobs as keep a group's part of a plane within the
-    // 32-bit offsets of a buffer view, and no more than the jobs there are
+    // job groups: 1D/2D planes, and 3D ones up to 256 MiB, keep one job per
+    // group (each job's cells contiguous); larger 3D ones group as many jobs
+    // as keep a group's part of a plane within the 32-bit offsets of a buffer
+    // view (no more than the jobs there are), so that a finalize block reads
+    // long contiguous runs
     I.part_jg = 0;
-    while ((1 << I.part_jg) < n_bund && ((size_t)I.part_ld << (I.part_jg + 1)) * es < (1ull << 31)) ++I.part_jg;
+    if (h->dim == 3 && (size_t)I.part_ld * n_bund * es > (256ull << 20))
+      while ((1 << I.part_jg) < n_bund && ((size_t)I.part_ld << (I.part_jg + 1)) * es < (1ull << 31)) ++I.part_jg;
     HIPCHK(pp.alloc(&pt, (size_t)kNAcc * part_plane_len(n_bund, I.part_jg, I.part_ld) * es));
     I.d_part = pt;
     I.d_store = nullptr;

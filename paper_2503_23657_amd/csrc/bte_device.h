@@ -226,6 +226,8 @@ static_assert(kPartBlk == kFinCells, "a finalize block reads one cell block of e
 __host__ __device__ constexpr int part_off(int c, int jg) {
   return ((c >> 8) << (jg + 8)) + (c & (kPartBlk - 1));
 }
+// the same as c + (c / kPartBlk) * part_gap(jg), one multiply-add
+__host__ __device__ constexpr int part_gap(int jg) { return ((1 << jg) - 1) * kPartBlk; }
 __host__ __device__ constexpr long long part_job(int j, int jg, int part_ld) {
   return ((long long)(j >> jg) * part_ld << jg) + (long long)(j & ((1 << jg) - 1)) * kPartBlk;
 }

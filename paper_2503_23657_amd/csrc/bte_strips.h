@@ -8,7 +8,7 @@
 #pragma once
 
 #if defined(__HIPCC__)
-#define BTE_HD __host__ __device__
+#define BTE_HD __host__ __device__ __attribute__((always_inline))
 #else
 #define BTE_HD
 #endif

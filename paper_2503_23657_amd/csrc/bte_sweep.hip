@@ -185,6 +185,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
     rsrc_t PRS[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, pgrp * (unsigned)sizeof(T));
+    const int pgap = part_gap(I.part_jg);  // cell c at c + (c >> 8) * pgap (part_off)
     const int zmask = I.ring - 1;
     const int zlag = I.lag;
     // buffer view of this wave's global z ring (I.ring steps x 8 lanes x G)
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs A) {
           for (int a = 0; a < NACC; ++a) {
             T v = T(0);
             for (int q = 0; q < P; ++q) v += stage[((size_t)(q * R + r) * NACC * C + a * C + cc) * 65 + lp];
-            bst(v, PRS[a], cid >= 0 ? part_off(cid, I.part_jg) * (int)sizeof(T) : kOOB);
+            bst(v, PRS[a], cid >= 0 ? (cid + __mul24(cid >> 8, pgap)) * (int)sizeof(T) : kOOB);
           }
         }
       }

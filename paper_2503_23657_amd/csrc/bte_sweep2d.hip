@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     rsrc_t PRS[NACC];
 #pragma unroll
     for (int a = 0; a < NACC; ++a) PRS[a] = mkrsrc(PARTJ + a * part_plane, pgrp * (unsigned)sizeof(T));
+    const int pgap = part_gap(I.part_jg);  // cell c at c + (c >> 8) * pgap (part_off)
     // 3D: this wave's step-axis buffer (a VR per plane and lane)
     const int n_pl = L3 ? I.n_pl : 1;
     const int zrow = 64 * NR * (int)sizeof(T);  // bytes per plane
@@ -529,9 +530,21 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
           for (int q = 1; q < PQ; ++q) sm += wraw[a][mi][q];
           // a row of the lane outside the grid has a cell index past either
           // end of the partial-sum plane, so the buffer's range check drops it
+          if constexpr (!L3) {
+            // 1D/2D planes keep one job per group: the cell index itself
 #pragma unroll
-          for (int k = 0; k < NR; ++k)
-            bst(sm[k], PRS[a], v >= 0 ? part_off(cid0 + k * dy, I.part_jg) * (int)sizeof(T) : kOOB);
+            for (int k = 0; k < NR; ++k) bst(sm[k], PRS[a], v >= 0 ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
+          } else {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              const int c = cid0 + k * dy;
+              int off = v >= 0 ? (c + __mul24(c >> 8, pgap)) * (int)sizeof(T) : kOOB;
+              // (opaque, so that the store stays one instruction rather than
+              // being split into a branch per case of the select)
+              asm volatile("" : "+v"(off));
+              bst(sm[k], PRS[a], off);
+            }
+          }
         }
       }
     };
@@ -587,7 +600,17 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
       T* stg0 = stage + (size_t)(NACC == 1 ? bufi : 0) * plane_sz + (size_t)(p * R + r) * kC2 * RS;
       int* scw = scid + (bufi * R + r) * kC2 * CS;
       int out_cnt = 0;
-      const int s0 = (ch * kC2 + KD) * 64;  // first position prefetched in this chunk
+      // the chunk's prefetch: 3D through the fixed views with a uniform offset
+      // (fewer scalar registers live), 1D/2D through views based at the first
+      // position prefetched in the chunk (immediate offsets per step)
+      const int s0 = (ch * kC2 + KD) * 64;
+      auto cview = [&](auto base, int esz, rsrc_t fixed) BTE_INL {
+        return L3 ? fixed : mkrsrc((const char*)base + (size_t)s0 * esz, 0xFFFFFFFFu);
+      };
+      const rsrc_t rr = cview(REC, 8, RRB), rx = cview(XQ, (int)sizeof(VX), RXB);
+      const rsrc_t rf = MODE == M2_TAUGRAD ? cview(XF, (int)sizeof(VX), RFB) : rx;
+      const rsrc_t rc = MODE == M2_SECOND ? cview(XC, (int)sizeof(VR), RCB) : rx;
+      const int sb = L3 ? s0 : 0;  // offset of the chunk's first prefetched position in its view
       // strip-entry x-inflows of the step about to run (read one step ahead;
       // the chunk's first step reads its own after the chunk barrier)
       // (two register sets by step parity, so no value is copied)
@@ -641,8 +664,12 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         // upwind value of row 0: the lane below's top row of the previous step;
         // lane 0 takes the ring value of this step
         T zc[G];
+        if constexpr (L3) {
+          zc[0] = shr1(rdlane(ghv[0], u), zreg[um][NR - 1]);
+        } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), L3 ? zreg[um][NR - 1] : f[g][NR - 1]);
+          for (int g = 0; g < G; ++g) zc[g] = shr1(rdlane(ghv[g], u), f[g][NR - 1]);
+        }
 
         // a lane entering its strip at the x wall takes its x-inflows as the
         // rows' x-upwind values (after the lane below has had the old top row)
@@ -823,10 +850,10 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         //      fence keeps the loads after the last use of the old values, so
         //      every slot is reloaded in place
         __builtin_amdgcn_sched_barrier(0);
-        RR[sl] = ldrec_b(RRB, lo_rec, (s0 + u * 64) * 8);
-        RX[sl] = ldv<VX>(RXB, lo_xq, (s0 + u * 64) * (int)sizeof(VX));
-        if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(RFB, lo_xq, (s0 + u * 64) * (int)sizeof(VX));
-        if (MODE == M2_SECOND) RC[sl] = ldv<VR>(RCB, lo_xc, (s0 + u * 64) * (int)sizeof(VR));
+        RR[sl] = ldrec_b(rr, lo_rec, (sb + u * 64) * 8);
+        RX[sl] = ldv<VX>(rx, lo_xq, (sb + u * 64) * (int)sizeof(VX));
+        if (MODE == M2_TAUGRAD) RXF[sl] = ldv<VX>(rf, lo_xq, (sb + u * 64) * (int)sizeof(VX));
+        if (MODE == M2_SECOND) RC[sl] = ldv<VR>(rc, lo_xc, (sb + u * 64) * (int)sizeof(VR));
       };
 #pragma unroll
       for (int u = 0; u < kC2; ++u) step(u);

@@ -34,6 +34,7 @@ __all__ = [
     "band_table_synthetic", "band_table_gray", "quad_gl_mu", "quad_octant_gl",
     "face_bc_from_mask", "gaussian_source", "film_1d", "square_2d", "finfet_3d", "finfet_3d_mixed",
     "adjoint_case", "batch_instances", "scattering_mfp", "random_box_2d", "random_box_3d", "multi_hole_2d",
+    "staircase_3d",
 ]
 
 
@@ -321,6 +322,21 @@ def random_box_3d(nx, ny, nz, seed, n_bands=2, n_theta=1, n_phi=1, hole=True, ki
     return Problem("random_box_3d", 3, n, (dx, dx, dx), mask, fbc,
                    np.array([BC_ISOTHERMAL, kinds[1]], dtype=np.int32),
                    np.array(T_walls, dtype=np.float64), v, tau, C, s, w, Q, 300.0)
+
+
+def staircase_3d(kind=1, nx=24, ny=20, nz=12, seed=8, n_bands=2, n_theta=1, n_phi=1):
+    """3D staircase: the block of 8 columns x in [8k, 8k + 8) holds the planes
+    z in [4k - 1, 4k + 4], so neighbouring blocks share one or two planes and
+    the planes in use differ from block to block. Bottom face of every step
+    isothermal (bc 0), every other boundary face bc 1 of the given kind."""
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    for k in range((nx + 7) // 8):
+        m[max(0, 4 * k - 1):min(nz, 4 * k + 5), :, 8 * k:8 * k + 8] = 1
+    mask = m.reshape(-1)
+    base = random_box_3d(nx, ny, nz, seed=seed, n_bands=n_bands, n_theta=n_theta, n_phi=n_phi, hole=False,
+                         kinds=(0, kind))
+    fbc = face_bc_from_mask((nx, ny, nz), 3, mask, lambda i, j, k, f: 0 if f == 4 else 1)
+    return base.replace(name="staircase_3d", mask=mask, face_bc=fbc, Q=base.Q * mask)
 
 
 def finfet_3d(scale=1, seed=2, n_bands=15, n_theta=4, n_phi=4, Q0=1e19, T_ref=300.0,

@@ -1253,8 +1253,13 @@ bte_status check_opts(const bte_opts* o) {
 bte_status fill_report(bte_ctx* h, size_t k, double secs, bte_report* rep, bool adj, const bte_opts& o) {
   const StatusDev& s = h->h_st[k];
   bte_status st = BTE_OK;
-  if (s.nonfinite) st = BTE_ERR_NONFINITE;
-  else if (!s.done) st = BTE_ERR_NOT_CONVERGED;
+  if (s.nonfinite) {
+    st = BTE_ERR_NONFINITE;
+    set_err("a non-finite value appeared (iteration %d)", s.iter);
+  } else if (!s.done) {
+    st = BTE_ERR_NOT_CONVERGED;
+    set_err("not converged after %d iterations (eps_T %.3g, eps_q %.3g)", s.iter, s.eps_T, s.eps_q);
+  }
   (void)o;
   (void)adj;
   if (rep) {

@@ -160,10 +160,12 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   // prefetch distance in steps (divides kC2): a whole chunk while the ring of
   // prefetched records and values fits in ~96 registers (G ordinates' worth
   // of other state scales with it), half a chunk above that; a chunk and half
-  // a chunk time the same on the bench shapes, so registers decide
+  // a chunk time the same on the bench shapes, so registers decide. The 3D
+  // flux sweeps (eight-wave workgroups, four accumulators) take half a chunk:
+  // a whole one spilled to scratch there
   constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1) +
                             (MODE == M2_SECOND ? NR * (int)sizeof(T) / 4 : 0);
-  constexpr int KD = kRingRegs * kC2 * G <= 96 ? kC2 : kC2 / 2;
+  constexpr int KD = (kRingRegs * kC2 * G <= 96 && !(L3 && NACC > 2)) ? kC2 : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
   constexpr int GS = grp_stride(G);

@@ -76,8 +76,8 @@ CASES = [
      (1, 1, 2, 8, 1)),
     ("finfet_rows", lambda: bi.finfet_3d(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
     ("finfet_rows_mixed", lambda: bi.finfet_3d_mixed(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 1, 8, 1)),
-    ("staircase_rows", lambda: _staircase_3d(1), 4, (1, 1, 2, 8, 1)),
-    ("staircase_rows_specular", lambda: _staircase_3d(2), 4, (1, 1, 1, 8, 1)),
+    ("staircase_rows", lambda: bi.staircase_3d(1), 4, (1, 1, 2, 8, 1)),
+    ("staircase_rows_specular", lambda: bi.staircase_3d(2), 4, (1, 1, 1, 8, 1)),
     # specular walls (every boundary but the isothermal bottom, hole faces included)
     ("film_specular", lambda: _film_specular(), 6, (1, 1, 1, 8, 1)),
     ("box_specular", lambda: bi.random_box_2d(23, 19, seed=0, n_bands=2, n_theta=1, n_phi=1, kinds=(0, 2)), 5,
@@ -89,21 +89,6 @@ CASES = [
     ("box3d_specular_rows", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=1, n_phi=1,
                                                       kinds=(0, 2)), 4, (1, 1, 2, 8, 1)),
 ]
-
-
-def _staircase_3d(kind=1):
-    """3D staircase: the block of 8 columns x in [8k, 8k + 8) holds the planes
-    z in [4k - 1, 4k + 4], so consecutive blocks share one or two planes and
-    plane ranges differ per block (isothermal bottom of every step, other
-    faces bc 1 of the given kind)."""
-    nx, ny, nz = 24, 20, 12
-    m = np.zeros((nz, ny, nx), dtype=np.uint8)
-    for k in range(3):
-        m[max(0, 4 * k - 1):min(nz, 4 * k + 5), :, 8 * k:8 * k + 8] = 1
-    mask = m.reshape(-1)
-    base = bi.random_box_3d(nx, ny, nz, seed=8, n_bands=2, n_theta=1, n_phi=1, hole=False, kinds=(0, kind))
-    fbc = bi.face_bc_from_mask((nx, ny, nz), 3, mask, lambda i, j, k, f: 0 if f == 4 else 1)
-    return base.replace(mask=mask, face_bc=fbc, Q=base.Q * mask)
 
 
 def _film_specular():

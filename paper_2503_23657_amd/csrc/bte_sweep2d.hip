@@ -397,6 +397,9 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     // The plane of a period comes from the period table (plane + 1, 0: no
     // period), read a chunk before it is needed.
     VR zreg[L3 ? kC2 : 1], xl, xn;
+    // 3D inflow chunks: the next step's stream values of the lane's rows
+    // (step, lane, plane axis), read from LDS one step ahead
+    T pin[L3 ? NR : 1][3];
     int qL = 0, qS = 0, pL1 = 0, pS1 = 0;  // period and plane + 1 of the next load / store
     const rsrc_t GPR = mkrsrc(L3 ? gp(I.gpre) + (size_t)o * (T_steps + I.n_per) : nullptr,
                               L3 ? (unsigned)(T_steps + I.n_per) * 4u : 0u);
@@ -626,6 +629,24 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         for (int k = 0; k < NR; ++k) dst[k] = ip[k];
       };
       if constexpr (XS) read_xv(RR[0], xv[0]);
+      // 3D: a lane's stream entries (rows ascending, then the step, lane and
+      // plane axes, from its offset), for the step of record rn
+      auto in_read = [&](const int2 rn) BTE_INL {
+        const unsigned fr = (unsigned)rn.y;
+        const int e0 = (int)((fr >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
+        constexpr unsigned kAll = rowmask(B_INX | B_INY | B_INZ, NR, RB);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const unsigned b = fr >> (RB * k);
+          const int ex = e0 + __builtin_popcount(fr & kAll & ((1u << (RB * k)) - 1u));
+          const int ey = ex + ((b & B_INX) ? 1 : 0);
+          const int ez = ey + ((b & B_INY) ? 1 : 0);
+          pin[k][0] = inbuf[min(ex, E - 1)];
+          pin[k][1] = inbuf[min(ey, E - 1)];
+          pin[k][2] = inbuf[min(ez, E - 1)];
+        }
+      };
+      if constexpr (L3 && IN == 2) in_read(RR[0]);
 
       auto step = [&](const int u) BTE_INL {
         const int sl = u % KD;
@@ -704,7 +725,22 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
             }
           }
         }
-        if (IN == 2 && __ballot(fl & kInAll) != 0ull) {
+        if constexpr (L3 && IN == 2) {
+          // 3D inflow chunks: every step takes the selects, with the values
+          // read a step ahead (no LDS wait in the chain); then the next
+          // step's values
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const unsigned b = fl >> (RB * k);
+            const T xu = (b & B_INX) ? pin[k][0] * den[0] : xin[k];
+            const T zu = (b & B_INY) ? pin[k][1] * den[0] : zc[0];
+            const T pu = (b & B_INZ) ? pin[k][2] * den[0] : zr[k];
+            const T fn = fma(a1[0], zu, fma(a0[0], xu, fma(a2[0], pu, S[k])));
+            f[0][k] = fn;
+            zc[0] = fn;
+          }
+          if (u + 1 < kC2) in_read(RR[(u + 1) % KD]);
+        } else if (IN == 2 && __ballot(fl & kInAll) != 0ull) {
           // entries of this lane: rows ascending, then the step, lane and
           // plane axes, from its offset
           const int e0 = (int)((fl >> F2_INOFF_SHIFT) & F2_INOFF_MASK);

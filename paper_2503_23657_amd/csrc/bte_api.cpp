@@ -153,7 +153,7 @@ struct Inst {
   double* d_tgrad = nullptr;
   void* d_corr = nullptr;         // second-order faces: [n_grp][pos_per_oct] correction
   double* d_corr_coef = nullptr;  // [n_grp][3]
-  int* d_bslot = nullptr;         // [ncell*6]
+  int* d_stencil = nullptr;       // [n_oct][pos_per_oct][3*dim] Green-Gauss stencil codes
   int* d_xpre = nullptr;          // 3D rows-per-lane: step-axis wall faces of the first column
   int* d_gpre = nullptr;          // 3D rows-per-lane: lane 0's lane-axis wall faces
   int* d_out_tab = nullptr;       // 3D rows-per-lane: outflow entries per chunk
@@ -309,9 +309,10 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   const bool L3 = h->dim == 3;
   // 3D: NR >= 1 asks for the rows-per-lane layout, NR = 0 for the pencil blocks
   const bool R3 = L3 && pl.NR >= 1;
-  if (h->order == 2 && (pl.G != 1 || h->dim == 3)) {
-    // the correction array and the stored field hold one ordinate per group
-    set_err("second-order faces need 1D/2D grids and plans with G = 1");
+  if (h->order == 2 && (pl.G != 1 || (L3 && !R3))) {
+    // the correction array and the stored field hold one ordinate per group,
+    // in a rows-per-lane layout
+    set_err("second-order faces need plans with G = 1 (in 3D, the rows-per-lane layout)");
     return BTE_ERR_INVALID;
   }
   if (h->has_specular && pl.G != 1) {
@@ -519,11 +520,11 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
       HIPCHK(pp.alloc(&pc, nc));
       HIPCHK(pp.memset(pc, 0, nc));  // positions of no cell stay 0
       I.d_corr = pc;
-      char* ps;
-      HIPCHK(pp.alloc(&ps, (size_t)n_grp_inst * I.hi.ncell * es));
+      char* ps;  // the field, in the same layout
+      HIPCHK(pp.alloc(&ps, nc));
       I.d_store = ps;
       HIPCHK(pp.upload(&I.d_corr_coef, corr_coefficients(h, I.hi)));
-      HIPCHK(pp.upload(&I.d_bslot, I.hi.bslot));
+      HIPCHK(pp.upload(&I.d_stencil, corr_stencil(I.hi, S)));
     }
     // descriptors
     for (int adj = 0; adj < 2; ++adj) {
@@ -615,7 +616,7 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
   const int R = L3 ? 1 : pl.R, P = pl.P, G = pl.G, Cc = pl.C;
   // second-order sweeps carry three planes on flux iterations in 1D too (the
   // y-flux plane then holds zeros): one compiled variant per shape
-  h->nacc_max = std::max(h->order == 2 ? 3 : 1 + h->dim, 2);
+  h->nacc_max = std::max(1 + h->dim, h->order == 2 ? 3 : 2);
   auto al = [](size_t x) { return (x + 15) / 16 * 16; };
   size_t off = 0;
   SweepArgs& sa = h->sa;
@@ -1135,12 +1136,10 @@ bte_status enqueue_corr(bte_ctx* h, hipStream_t st) {
     a.n_grp = I.n_grp;
     a.grp = h->d_gi_f + I.grp0;
     a.coef = I.d_corr_coef;
-    a.bslot = I.d_bslot;
-    a.bf_bc = I.d_bf_bc;
-    a.bc_kind = I.d_bc_kind;
-    a.active = I.d_active;
+    a.stencil = I.d_stencil;
     for (int d = 0; d < 3; ++d) a.h[d] = I.hi.h[d];
-    HIPCHK(launch_corr(h->precision, a, I.hi.ncell, st));
+    a.X0 = nullptr;
+    HIPCHK(launch_corr(h->precision, a, I.sch.pos_per_oct, st));
   }
   return BTE_OK;
 }
@@ -1148,7 +1147,7 @@ bte_status enqueue_corr(bte_ctx* h, hipStream_t st) {
 // n iterations; the last one checks convergence, the last two carry the flux.
 bte_status enqueue_chunk(bte_ctx* h, bool adj, int n, const bte_opts& o, hipStream_t st) {
   const bool second = !adj && h->order == 2;
-  const int nq = second ? 3 : 1 + h->dim;
+  const int nq = second ? std::max(3, 1 + h->dim) : 1 + h->dim;
   for (int k = 0; k < n; ++k) {
     const bool last = k == n - 1, second_last = k == n - 2;
     const bool qit = !adj && (last || second_last);
@@ -1304,19 +1303,16 @@ bte_status init_forward(bte_ctx* h, size_t k, const double* d_Q, const double* d
   if (h->order == 2) {
     // the first sweep's correction: the initial field is the equilibrium at
     // the initial temperature, the same for every ordinate
-    HIPCHK(launch_store_fill(h->precision, I.d_store, I.d_X[0], I.n_grp, I.hi.ncell, st));
     CorrArgs a;
     a.inst = h->d_inst_f;
     a.inst_id = (int)k;
     a.n_grp = I.n_grp;
     a.grp = h->d_gi_f + I.grp0;
     a.coef = I.d_corr_coef;
-    a.bslot = I.d_bslot;
-    a.bf_bc = I.d_bf_bc;
-    a.bc_kind = I.d_bc_kind;
-    a.active = I.d_active;
+    a.stencil = I.d_stencil;
     for (int d = 0; d < 3; ++d) a.h[d] = I.hi.h[d];
-    HIPCHK(launch_corr(h->precision, a, I.hi.ncell, st));
+    a.X0 = I.d_X[0];
+    HIPCHK(launch_corr(h->precision, a, I.sch.pos_per_oct, st));
   }
   return BTE_OK;
 }
@@ -1776,15 +1772,18 @@ bte_status bte_set_order(bte_handle h, int order) {
     set_err("null handle or order not 1 or 2");
     return BTE_ERR_INVALID;
   }
-  if (order == 2 && h->dim == 3) {
-    set_err("second-order faces are built for 1D and 2D grids");
-    return BTE_ERR_INVALID;
-  }
   if (order == h->order) return BTE_OK;
   const int old_order = h->order;
   const Plan old = h->plan;
   Plan p = h->plan;
-  if (order == 2) p.G = 1;
+  if (order == 2) {
+    p.G = 1;
+    if (h->dim == 3 && p.NR < 1) {
+      // the 3D pencil blocks have no second-order sweep: the rows layout
+      p.NR = 1;
+      p.C = kC2;
+    }
+  }
   h->order = order;
   bte_status s = build_plan(h, p);
   if (s != BTE_OK) {

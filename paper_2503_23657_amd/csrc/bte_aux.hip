@@ -378,56 +378,113 @@ __global__ void zero_kernel(unsigned* p, long long n) {
 }
 
 // ---------------------------------------------- second-order faces
-// neighbour of cell c across face f (0..5 = -x, +x, -y, +y, -z, +z), -1 when
-// that face is a boundary (domain edge or inactive cell)
-__device__ __forceinline__ int corr_nb(const InstDev& I, const unsigned char* act, int c, int f) {
-  const int i = c % I.nx, j = (c / I.nx) % I.ny, k = c / (I.nx * I.ny);
-  const int d = f >> 1, up = f & 1;
-  const int n = d == 0 ? I.nx : (d == 1 ? I.ny : I.nz);
-  const int x = (d == 0 ? i : (d == 1 ? j : k)) + (up ? 1 : -1);
-  if (x < 0 || x >= n) return -1;
-  const int nb = c + (up ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? I.nx : I.nx * I.ny));
-  return act[nb] ? nb : -1;
-}
+// The deferred correction of Eq. rhs_b for every position of each group's
+// octant layout (positions of no cell get 0): the Green-Gauss gradient
+// difference between the cell and its upwind neighbour along each grid axis,
+// from the field the last sweep stored in the same layout. The neighbours come
+// from the octant's stencil table (positions, or boundary codes), so that
+// every read but the stencil's field values is in position order. A thread
+// takes one position for kCorrGrp consecutive groups (groups are octant-major:
+// the stencil row is read once per octant met).
+constexpr int kCorrGrp = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(256) corr_kernel(CorrArgs A) {
   const InstDev& I = A.inst[A.inst_id];
   const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
   if (st->done) return;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  const int g = blockIdx.y;
-  if (c >= I.ncell || !A.active[c]) return;
-  const int4 gi = A.grp[g];
-  const int o = gi.y;
-  const T* u = reinterpret_cast<const T*>(I.store_u) + (size_t)g * I.ncell;
-  const T* ubf = reinterpret_cast<const T*>(I.ubf) + (size_t)gi.w * I.n_bface;
-  // Green-Gauss face value of cell x at its face f
-  auto face = [&](int x, int f) -> double {
-    const int nb = corr_nb(I, A.active, x, f);
-    if (nb >= 0) return 0.5 * ((double)u[x] + (double)u[nb]);
-    const int d = f >> 1;
-    const bool entering = (f & 1) == ((o >> d) & 1);
-    const int slot = A.bslot[(size_t)x * 6 + f];
-    if (entering && A.bc_kind[A.bf_bc[slot]] == 0) return (double)ubf[slot];
-    const int ob = corr_nb(I, A.active, x, f ^ 1);
-    return ob >= 0 ? 1.5 * (double)u[x] - 0.5 * (double)u[ob] : (double)u[x];
-  };
-  double corr = 0.0;
-  for (int d = 0; d < I.dim; ++d) {
-    const double gc = (face(c, 2 * d + 1) - face(c, 2 * d)) / A.h[d];
-    const int up = corr_nb(I, A.active, c, 2 * d + ((o >> d) & 1));
-    const double gu = up >= 0 ? (face(up, 2 * d + 1) - face(up, 2 * d)) / A.h[d] : 0.0;
-    corr += A.coef[(size_t)g * 3 + d] * (gc - gu);
+  const long long ppo = I.pos_per_oct;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= ppo) return;
+  const int dim = I.dim;
+  const int n_bface = I.n_bface;
+  const int* __restrict__ stencil = A.stencil;
+  const T* __restrict__ ufld = reinterpret_cast<const T*>(I.store_u);
+  const T* __restrict__ ubf0 = reinterpret_cast<const T*>(I.ubf);
+  T* __restrict__ corr0 = reinterpret_cast<T*>(I.corr);
+  T ih[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ih[d] = T(1) / (T)A.h[d];
+  const int g0 = blockIdx.y * kCorrGrp, g1 = min(g0 + kCorrGrp, A.n_grp);
+  int o = -1;
+  bool cell = false;
+  int en[3] = {-1, -1, -1}, eu[3] = {-1, -1, -1}, euu[3] = {-1, -1, -1};
+  for (int g = g0; g < g1; ++g) {
+    const int4 gi = A.grp[g];
+    if (gi.y != o) {  // uniform: the block's groups share octants
+      o = gi.y;
+      const int* e = stencil + ((size_t)o * ppo + p) * (3 * dim);
+      cell = e[0] != kNoCell;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (d < dim) {
+          en[d] = e[3 * d];
+          eu[d] = e[3 * d + 1];
+          euu[d] = e[3 * d + 2];
+        }
+    }
+    T* out = corr0 + (size_t)g * ppo;
+    if (!cell) {
+      out[p] = T(0);
+      continue;
+    }
+    const T* u = ufld + (size_t)g * ppo;
+    const T* ubf = ubf0 + (size_t)gi.w * n_bface;
+    const T uc = u[p];
+    T corr = T(0);
+    const T h5 = T(0.5), t15 = T(1.5);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d >= dim) break;
+      const T un = en[d] >= 0 ? u[en[d]] : T(0);
+      const T uu = eu[d] >= 0 ? u[eu[d]] : T(0);
+      // face values of the cell: downwind (never an inflow face: the mean
+      // with the neighbour, else the extrapolation from the upwind side) and
+      // upwind (the mean, the isothermal wall value, else the extrapolation
+      // from the downwind side); the cell's own value when the opposite face
+      // is a boundary too
+      const T fd = en[d] >= 0 ? h5 * (uc + un) : (eu[d] >= 0 ? t15 * uc - h5 * uu : uc);
+      const T fu = eu[d] >= 0 ? h5 * (uc + uu) : (eu[d] <= -2 ? ubf[-eu[d] - 2] : (en[d] >= 0 ? t15 * uc - h5 * un : uc));
+      // the upwind cell: its downwind face is shared with this cell
+      T du = T(0);
+      if (eu[d] >= 0) {
+        const T fuu = euu[d] >= 0 ? h5 * (uu + u[euu[d]]) : (euu[d] <= -2 ? ubf[-euu[d] - 2] : t15 * uu - h5 * uc);
+        du = h5 * (uu + uc) - fuu;
+      }
+      // (fd - fu) - du is the gradient difference along the ordinate's
+      // direction times h; along +d it changes sign in odd octants
+      const T dd = ((o >> d) & 1) ? du - (fd - fu) : (fd - fu) - du;
+      corr += (T)A.coef[(size_t)g * 3 + d] * ih[d] * dd;
+    }
+    out[p] = corr;
   }
-  T* out = reinterpret_cast<T*>(I.corr) + (size_t)g * I.pos_per_oct;
-  out[I.pos[(size_t)o * I.ncell + c]] = (T)corr;
 }
 
+// The field before the first sweep: X0 at every position of each group's
+// octant layout (0 at positions of no cell).
 template <typename T>
-__global__ void __launch_bounds__(256) store_fill_kernel(T* store, const double* X, int ncell) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c < ncell) store[(size_t)blockIdx.y * ncell + c] = (T)X[c];
+__global__ void __launch_bounds__(256) corr_fill_kernel(CorrArgs A) {
+  const InstDev& I = A.inst[A.inst_id];
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= I.pos_per_oct) return;
+  const int g0 = blockIdx.y * kCorrGrp, g1 = min(g0 + kCorrGrp, A.n_grp);
+  // the position's cell: the lane-step record of its octant, row p mod nr
+  const int nr = I.nr;
+  const int k = (int)(p % nr);
+  const int rb = I.dim == 3 ? F3_ROW_BITS : F2_ROW_BITS;
+  int o = -1;
+  T v = T(0);
+  for (int g = g0; g < g1; ++g) {
+    const int og = A.grp[g].y;
+    if (og != o) {
+      o = og;
+      const int2 rec = I.sched[(size_t)o * (I.pos_per_oct / nr) + p / nr];
+      const bool on = rec.x >= 0 && ((rec.y >> (rb * k)) & 1);
+      const int dy = I.dim == 3 ? I.dyo[o] : ((o & 2) ? -I.nx : I.nx);
+      v = on ? (T)A.X0[(rec.x >> 5) + k * dy] : T(0);
+    }
+    reinterpret_cast<T*>(I.store_u)[(size_t)g * I.pos_per_oct + p] = v;
+  }
 }
 
 template __global__ void finalize_kernel<float>(FinArgs, const FinInst*);
@@ -501,22 +558,15 @@ hipError_t launch_ubf_init(int prec, const UbfInitArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_corr(int prec, const CorrArgs& a, int ncell, hipStream_t st) {
-  if (a.n_grp <= 0 || ncell <= 0) return hipSuccess;
-  const dim3 grid(nblk(ncell), a.n_grp);
+hipError_t launch_corr(int prec, const CorrArgs& a, long long n_pos, hipStream_t st) {
+  if (a.n_grp <= 0 || n_pos <= 0) return hipSuccess;
+  const dim3 grid(nblk(n_pos), (a.n_grp + kCorrGrp - 1) / kCorrGrp);
+  if (a.X0) {
+    if (prec == BTE_PREC_FP32) hipLaunchKernelGGL(corr_fill_kernel<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(corr_fill_kernel<double>, grid, dim3(256), 0, st, a);
+  }
   if (prec == BTE_PREC_FP32) hipLaunchKernelGGL(corr_kernel<float>, grid, dim3(256), 0, st, a);
   else hipLaunchKernelGGL(corr_kernel<double>, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_store_fill(int prec, void* store, const double* X, int n_grp, int ncell, hipStream_t st) {
-  if (n_grp <= 0 || ncell <= 0) return hipSuccess;
-  const dim3 grid(nblk(ncell), n_grp);
-  if (prec == BTE_PREC_FP32)
-    hipLaunchKernelGGL(store_fill_kernel<float>, grid, dim3(256), 0, st, reinterpret_cast<float*>(store), X, ncell);
-  else
-    hipLaunchKernelGGL(store_fill_kernel<double>, grid, dim3(256), 0, st, reinterpret_cast<double*>(store), X,
-                       ncell);
   return hipGetLastError();
 }
 

@@ -115,9 +115,10 @@ struct InstDev {
   int e_max;        // max inflow entries of one wave slot in one chunk (all axes)
   int o_max;        // max outflow entries of one wave slot in one chunk (all axes)
   int band_dummy;   // unused padding
-  long long pos_per_oct;  // R*T*64
+  long long pos_per_oct;  // positions of one octant's layout: R*(T + kPad2)*64*nr (rows per lane),
+                          //   R*(T + kPad2)*64 (3D pencil blocks)
   // schedule (per octant, R slots): cell index (-1 idle/inactive) and flags
-  const int2* sched;        // [n_oct][R][T][64] (cell, flags)
+  const int2* sched;        // [n_oct][R][T + kPad2][64] (cell, flags)
   const int* pos;           // [n_oct][ncell] position of cell c in octant o's layout (-1 inactive)
   // inflow stream: boundary-face slots in consumption order, per (octant, slot)
   const int* in_slot;       // concatenated
@@ -134,7 +135,9 @@ struct InstDev {
                             //   [n_jobs / 2^part_jg][part_ld / kPartBlk][2^part_jg][kPartBlk]
   int part_ld;              // cells per job in a plane: ncell rounded up to a multiple of kPartBlk
   int part_jg;              // log2 of the jobs per group (a group's part of a plane < 2 GiB)
-  void* store_u;            // [n_grp][ncell][G] angular field u (forward, when stored)
+  void* store_u;            // [n_grp][ncell][G] angular field u (forward, when stored for the
+                            //   adjoint); second-order faces: [n_grp][pos_per_oct] in the octant's
+                            //   skewed layout
   double* tgrad;            // [n_grp][2] tau-gradient partial sums
   int* status;              // StatusDev
   int lag;                  // 3D: clock lag between a z-front write and its read
@@ -147,8 +150,8 @@ struct InstDev {
   int in_E;                 // entries per chunk row of in_tab (multiple of 64, <= 256)
   const int* in_tab;        // [n_oct][R][T/kC2 + 2][in_E] inflow face slot of each stream entry (-1 pad)
   const int* chunk_fl;      // [n_oct][R][T/kC2 + 1] CF2_* flags of each chunk (0 pad)
-  // second-order faces (1D/2D, one ordinate per group): the deferred
-  // correction of each group's source, in its octant's skewed layout
+  // second-order faces (rows-per-lane layouts, one ordinate per group): the
+  // deferred correction of each group's source, in its octant's skewed layout
   void* corr;               // [n_grp][pos_per_oct] sweep precision
   // 3D rows-per-lane layout
   int ax[3];                // grid axis of the step, lane and plane axes
@@ -306,12 +309,14 @@ struct CorrArgs {
   int n_grp;                 // groups of the instance
   const int4* grp;           // [n_grp] (band, octant, local group, inflow-table row)
   const double* coef;        // [n_grp][3] -t0 w0 v_b s_d / 2 per grid axis (0: padding group)
-  const int* bslot;          // [ncell*6] boundary-face slot of each face, or -1
-  const int* bf_bc;          // [n_bface]
-  const int* bc_kind;        // [n_bc]
-  const unsigned char* active;
+  const int* stencil;        // [n_oct][pos_per_oct][3*dim] neighbour positions or boundary codes
+                             //   (downwind, upwind, upwind's upwind per axis; -1 boundary,
+                             //   -(2 + slot) isothermal inflow wall, kNoCell first: no cell)
   double h[3];
+  const double* X0;          // [ncell] equilibrium field of every ordinate, filled in first (before the
+                             //   first sweep), or NULL: the field the last sweep stored
 };
+constexpr int kNoCell = (int)0x80000000;  // stencil code of a position of no cell
 
 struct InitArgs {
   const InstDev* inst;

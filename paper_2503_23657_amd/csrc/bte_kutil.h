@@ -92,6 +92,28 @@ __device__ __forceinline__ V ldv(rsrc_t r, int voff, int soff) {
   }
 }
 
+// store of a vector of V at byte offsets voff (per lane) + soff (uniform); an
+// offset past the buffer drops the store
+template <typename V>
+__device__ __forceinline__ void stv(const V& v, rsrc_t r, int voff, int soff) {
+  constexpr int B = (int)sizeof(V);
+  static_assert(B == 4 || B == 8 || B % 16 == 0, "vector stores of 4 or 8 bytes or whole 16-byte parts");
+  if constexpr (B == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  } else if constexpr (B == 8) {
+    typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, voff, soff, 0);
+  } else {
+    typedef unsigned u4_t __attribute__((ext_vector_type(4)));
+    struct Parts {
+      u4_t q[B / 16];
+    };
+    const Parts t = __builtin_bit_cast(Parts, v);
+#pragma unroll
+    for (int i = 0; i < B / 16; ++i) __builtin_amdgcn_raw_buffer_store_b128(t.q[i], r, voff + 16 * i, soff, 0);
+  }
+}
+
 // as ldv, at device scope (cache policy sc1: the load misses the CU's vector
 // cache and reads L2), for data the same wave stored earlier
 template <typename V>

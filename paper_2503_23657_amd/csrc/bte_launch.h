@@ -41,7 +41,6 @@ hipError_t launch_ubf_init(int prec, const UbfInitArgs& a, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // second-order faces: the correction of every group from the stored field,
 // and the stored field set to the initial temperature deviation X
-hipError_t launch_corr(int prec, const CorrArgs& a, int ncell, hipStream_t st);
-hipError_t launch_store_fill(int prec, void* store, const double* X, int n_grp, int ncell, hipStream_t st);
+hipError_t launch_corr(int prec, const CorrArgs& a, long long n_pos, hipStream_t st);
 
 }  // namespace bte

@@ -1017,4 +1017,37 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
   return true;
 }
 
+std::vector<int> corr_stencil(const HostInst& hi, const Schedule& s) {
+  const int dim = hi.dim, W = 3 * dim;
+  const long long ppo = s.pos_per_oct;
+  std::vector<int> out((size_t)s.n_oct * ppo * W, kNoCell);
+  const int st[3] = {1, hi.n[0], hi.n[0] * hi.n[1]};
+  for (int o = 0; o < s.n_oct; ++o) {
+    const int* pos = s.pos.data() + (size_t)o * hi.ncell;
+    for (int c = 0; c < hi.ncell; ++c) {
+      if (!hi.active[c] || pos[c] < 0) continue;
+      const int q[3] = {c % hi.n[0], (c / hi.n[0]) % hi.n[1], c / (hi.n[0] * hi.n[1])};
+      int* e = out.data() + ((size_t)o * ppo + pos[c]) * W;
+      for (int d = 0; d < dim; ++d) {
+        const int sg = ((o >> d) & 1) ? -1 : 1;  // the ordinate's direction along d
+        // cell x's neighbour at distance k*sg along d (x's coordinate along d
+        // is qd), as a position, or the face code when that face is a boundary
+        auto code = [&](int x, int qd, int k) {
+          const int y = qd + k * sg;
+          const int f = 2 * d + ((k * sg) > 0 ? 1 : 0);
+          if (y >= 0 && y < hi.n[d] && hi.active[x + k * sg * st[d]]) return pos[x + k * sg * st[d]];
+          const int slot = hi.bslot[(size_t)x * 6 + f];
+          // only an upwind face is an inflow face
+          if (k < 0 && slot >= 0 && hi.bc_kind[hi.bf_bc[slot]] == BTE_BC_ISOTHERMAL) return -(2 + slot);
+          return -1;
+        };
+        e[3 * d] = code(c, q[d], 1);
+        e[3 * d + 1] = code(c, q[d], -1);
+        e[3 * d + 2] = e[3 * d + 1] >= 0 ? code(c - sg * st[d], q[d] - sg, -1) : -1;
+      }
+    }
+  }
+  return out;
+}
+
 }  // namespace bte

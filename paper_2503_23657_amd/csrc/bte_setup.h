@@ -121,6 +121,16 @@ bool build_schedule(const HostInst& hi, const Plan& plan, Schedule& s, std::stri
 // 3D rows-per-lane schedule (false, with err, when the problem does not fit).
 bool build_schedule_3r(const HostInst& hi, const Plan& plan, Schedule& s, std::string& err);
 
+// Second-order faces: the Green-Gauss stencil of every position of each
+// octant's layout, [n_oct][pos_per_oct][3*dim] codes, three per grid axis d:
+// the cell's downwind neighbour along d, its upwind neighbour, and the upwind
+// neighbour's own upwind neighbour. A code >= 0 is the neighbour's position in
+// the same octant's layout; -1 a boundary face (domain edge or inactive
+// neighbour) that is not an isothermal inflow; -(2 + slot) an isothermal wall
+// the ordinate enters through (its boundary-face slot). A position of no cell
+// has kNoCell as its first code.
+std::vector<int> corr_stencil(const HostInst& hi, const Schedule& s);
+
 // sum over incoming directions of w |s . n| for a face normal to axis d.
 double half_range(const std::vector<Ordinate>& ords, int d);
 

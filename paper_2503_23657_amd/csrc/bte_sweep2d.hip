@@ -93,23 +93,6 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
 }
 
-// store a vector of V at byte offsets voff (per lane) + soff (uniform); an
-// offset past the buffer drops the store
-template <typename V>
-__device__ __forceinline__ void stv(const V& v, rsrc_t r, int voff, int soff) {
-  constexpr int B = (int)sizeof(V);
-  if constexpr (B == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-  } else if constexpr (B == 8) {
-    typedef unsigned u2_t __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, voff, soff, 0);
-  } else {
-    static_assert(B == 16, "stores of 4, 8 or 16 bytes");
-    typedef unsigned u4_t __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), r, voff, soff, 0);
-  }
-}
-
 constexpr int min_c(int a, int b) { return a < b ? a : b; }
 // largest power of two <= x (1 for x < 1)
 constexpr int pow2_floor(int x) {
@@ -131,7 +114,7 @@ constexpr unsigned rowmask(unsigned bits, int nr, int rb = F2_ROW_BITS) {
 // discretization"; Eq. rhs_b): each cell's source gains the group's correction
 // term computed from the previous iterate (read per step from the group's
 // skewed correction array), and the new angular field is stored for the next
-// correction
+// correction in the same skewed layout (one vector store per lane-step)
 enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2, M2_SECOND = 3 };
 
 // L3: the 3D rows-per-lane layout (see bte_device.h): the same kernel with
@@ -147,8 +130,8 @@ enum { M2_PLAIN = 0, M2_STORE = 1, M2_TAUGRAD = 2, M2_SECOND = 3 };
 template <typename T, int G, int NR, int P, int NACC, int MODE, bool L3 = false>
 __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   using namespace s2d;
-  static_assert(!L3 || (NR <= 2 && G == 1 && MODE != M2_SECOND),
-                "3D rows-per-lane: NR <= 2, one ordinate per lane, first-order faces");
+  static_assert(!L3 || (NR <= 2 && G == 1), "3D rows-per-lane: NR <= 2, one ordinate per lane");
+  static_assert(MODE != M2_SECOND || G == 1, "second-order faces: one ordinate per lane");
   constexpr int RB = L3 ? F3_ROW_BITS : F2_ROW_BITS;  // flag bits per row
   constexpr unsigned B_ACT = L3 ? F3_ACT : F2_ACT;
   constexpr unsigned B_INX = L3 ? F3_INX : F2_INX;
@@ -161,11 +144,11 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   // prefetched records and values fits in ~96 registers (G ordinates' worth
   // of other state scales with it), half a chunk above that; a chunk and half
   // a chunk time the same on the bench shapes, so registers decide. The 3D
-  // flux sweeps (eight-wave workgroups, four accumulators) take half a chunk:
-  // a whole one spilled to scratch there
+  // flux and second-order sweeps (eight-wave workgroups; four accumulators,
+  // or the correction ring) take half a chunk: a whole one spilled to scratch
   constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1) +
                             (MODE == M2_SECOND ? NR * (int)sizeof(T) / 4 : 0);
-  constexpr int KD = (kRingRegs * kC2 * G <= 96 && !(L3 && NACC > 2)) ? kC2 : kC2 / 2;
+  constexpr int KD = (kRingRegs * kC2 * G <= 96 && !(L3 && (NACC > 2 || MODE == M2_SECOND))) ? kC2 : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
   constexpr int GS = grp_stride(G);
@@ -279,6 +262,11 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
                                 (long long)r * Tp * 64)
                            : nullptr;
     const int lo_xc = lane * (int)sizeof(VR);
+    // the group's stored field, in the same layout
+    GAS VR* XS = MODE == M2_SECOND ? gp(reinterpret_cast<VR*>(reinterpret_cast<T*>(I.store_u) +
+                                                               (size_t)g_loc * I.pos_per_oct) +
+                                         (long long)r * Tp * 64)
+                                   : nullptr;
     const GAS T* UBF = gp(reinterpret_cast<const T*>(I.ubf) + (size_t)ubf_row * I.n_bface);
     const int Ei = I.in_E;  // this instance's entries per chunk row of in_tab (<= E)
     const GAS int* ITAB = gp(I.in_tab + slot * (nch + 2) * Ei);
@@ -372,6 +360,7 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     const rsrc_t RXB = mkrsrc(XQ, nposs * (unsigned)sizeof(VX));
     const rsrc_t RFB = MODE == M2_TAUGRAD ? mkrsrc(XF, nposs * (unsigned)sizeof(VX)) : RXB;
     const rsrc_t RCB = MODE == M2_SECOND ? mkrsrc(XC, nposs * (unsigned)sizeof(VR)) : RXB;
+    const rsrc_t RSB = MODE == M2_SECOND ? mkrsrc(XS, nposs * (unsigned)sizeof(VR)) : RXB;
     int2 RR[KD];
     VX RX[KD];
     VX RXF[KD];
@@ -533,17 +522,21 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
           VR sm = wraw[a][mi][0];
 #pragma unroll
           for (int q = 1; q < PQ; ++q) sm += wraw[a][mi][q];
-          // a row of the lane outside the grid has a cell index past either
-          // end of the partial-sum plane, so the buffer's range check drops it
           if constexpr (!L3) {
-            // 1D/2D planes keep one job per group: the cell index itself
+            // 1D/2D planes keep one job per group: the cell index itself. The
+            // lane axis is the grid's slowest, so a row of the lane outside
+            // the grid has a cell index past either end of the plane (or in
+            // the job's padding) and the buffer's range check drops it
 #pragma unroll
             for (int k = 0; k < NR; ++k) bst(sm[k], PRS[a], v >= 0 ? (cid0 + k * dy) * (int)sizeof(T) : kOOB);
           } else {
+            // 3D: the lane axis may be a faster grid axis, where the index of
+            // a row past the grid's end is a cell of the next line: rows
+            // outside the grid (record bit k clear) are not stored
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
               const int c = cid0 + k * dy;
-              int off = v >= 0 ? (c + __mul24(c >> 8, pgap)) * (int)sizeof(T) : kOOB;
+              int off = (v >= 0 && ((v >> k) & 1)) ? (c + __mul24(c >> 8, pgap)) * (int)sizeof(T) : kOOB;
               // (opaque, so that the store stays one instruction rather than
               // being split into a branch per case of the select)
               asm volatile("" : "+v"(off));
@@ -774,7 +767,10 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
               T fn;
               if constexpr (L3)  // accumulated in the plane-link value's register
                 fn = fma(a1[g], zc[g],
-                         fma(a0[g], xin[k], fma(kS, xq[2 * k], fma(cQ, xq[2 * k + 1], a2[g] * zr[k]))));
+                         fma(a0[g], xin[k],
+                             fma(kS, xq[2 * k],
+                                 fma(cQ, xq[2 * k + 1],
+                                     MODE == M2_SECOND ? fma(a2[g], zr[k], RC[sl][k]) : a2[g] * zr[k]))));
               else
                 fn = fma(a1[g], zc[g], fma(a0[g], f[g][k], S[k]));
               f[g][k] = fn;
@@ -835,7 +831,13 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         }
 
         // ---- stored angular field / tau-gradient sums
-        if ((MODE == M2_STORE || MODE == M2_SECOND) && rec.x >= 0) {
+        if constexpr (MODE == M2_SECOND) {
+          VR v;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) v[k] = f[0][k] * inv[0];
+          stv<VR>(v, RSB, lo_xc, (ch * kC2 + u) * 64 * (int)sizeof(VR));
+        }
+        if (MODE == M2_STORE && rec.x >= 0) {
 #pragma unroll
           for (int k = 0; k < NR; ++k)
             if ((fl >> (RB * k)) & B_ACT) {

@@ -114,14 +114,16 @@ static int occ2d_one(int block, size_t lds) {
 
 // 3D rows-per-lane variants: one ordinate per lane, NR in {1, 2}, P in
 // {1, 2, 4, 8}, (NACC, mode) in {(1, plain), (4, plain: flux iterations),
-// (1, store), (2, tau-gradient)}
+// (1, store), (2, tau-gradient), (1 and 4, second order)}
 #define BTE3R_CASE(T_, NR_, P_, N_, M_, FN, ...) \
   case BTE2D_KEY(NR_, P_, N_, M_): return FN<T_, 1, NR_, P_, N_, M_, true>(__VA_ARGS__);
 #define BTE3R_CASES_P(T_, NR_, P_, FN, ...)       \
   BTE3R_CASE(T_, NR_, P_, 1, 0, FN, __VA_ARGS__) \
   BTE3R_CASE(T_, NR_, P_, 4, 0, FN, __VA_ARGS__) \
   BTE3R_CASE(T_, NR_, P_, 1, 1, FN, __VA_ARGS__) \
-  BTE3R_CASE(T_, NR_, P_, 2, 2, FN, __VA_ARGS__)
+  BTE3R_CASE(T_, NR_, P_, 2, 2, FN, __VA_ARGS__) \
+  BTE3R_CASE(T_, NR_, P_, 1, 3, FN, __VA_ARGS__) \
+  BTE3R_CASE(T_, NR_, P_, 4, 3, FN, __VA_ARGS__)
 #define BTE3R_DISPATCH(T_, FN, ...)               \
   switch (BTE2D_KEY(NR, P, nacc, mode)) {         \
     BTE3R_CASES_P(T_, 1, 1, FN, __VA_ARGS__)      \

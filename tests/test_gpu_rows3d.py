@@ -3,7 +3,8 @@ shapes, against the FP64 oracle at 1e-10 of max|T - T_ref| (fixed iteration
 counts, both paths).
 
 Geometries: the staircase (blocks of 8 columns whose plane ranges differ and
-overlap by one or two planes, with diffuse or specular walls), boxes 4 and 3
+overlap by one or two planes, with diffuse or specular walls), a box with
+odd-length axes (a partial last lane with two rows per lane), boxes 4 and 3
 cells thick, the FinFET at a quarter of its size per axis; plans with 1 to 8
 waves per workgroup and 1 or 2 rows per lane, and the pencil layout."""
 import numpy as np
@@ -68,6 +69,20 @@ def test_eight_waves_two_rows_fp64_rejected(hip_lib):
     with pytest.raises(hip_lib.BTEError, match="LDS"):
         s.set_plan(G=1, P=8, NR=2)
     s.close()
+
+
+@pytest.mark.parametrize("kinds", [(0, 1), (0, 2)], ids=["diffuse", "specular"])
+def test_odd_axes_two_rows(hip_lib, kinds):
+    """Two rows per lane on a box whose every axis has odd length: the last
+    lane's second row lies outside the grid whichever axis the lanes run
+    along, and its partial sums must not land on a cell of the next line."""
+    p = bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=2, n_phi=1, kinds=kinds)
+    r = oracle.solve(p, tol=0.0, max_iters=5)
+    for plan, prec, bar in ((dict(G=1, P=1, NR=2), "fp64", 1e-10), (dict(G=1, P=2, NR=2), "fp64", 1e-10),
+                            (dict(G=1, P=4, NR=2), "fp64", 1e-10), (dict(G=1, P=8, NR=2), "fp32", 1e-4)):
+        T, q, got = _run(hip_lib, p, plan=plan, iters=5, precision=prec)
+        assert got["NR"] == 2
+        _check(p, T, q, r, bar=bar)
 
 
 def test_thin_boxes_fp64(hip_lib):

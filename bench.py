@@ -141,6 +141,8 @@ def main():
                     help="headline workload (the square runs as an extra field of the default line)")
     ap.add_argument("--plan", type=str, default=None,
                     help="fixed kernel plan 'G,R,P,C,NR' for the headline workload")
+    ap.add_argument("--order", type=int, choices=(1, 2), default=1,
+                    help="face reconstruction of the headline workload (2: second-order faces; for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +190,8 @@ def main():
         summary, files, dim = "sweep2d_square256_hbm_counters.md", SOURCES_2D, 2
     solver = bte.Solver(p, precision="fp32")
     Q = torch.tensor(p.Q, dtype=torch.float64, device=dev)
+    if args.order == 2:
+        solver.set_order(2)
     plan_arg(solver)
     plan = solver.plan()
     log("plan", plan)
@@ -201,6 +205,15 @@ def main():
     extra = {}
     if args.workload == "finfet" and not args.no_extra:
         solver.close()
+        # ------------------------- the same domain with second-order faces
+        s3o = bte.Solver(p, precision="fp32")
+        s3o.set_order(2)
+        K3o = 8
+        dt3o = timed_iterations(s3o, Q, K3o, 2)
+        extra["finfet_second_order"] = dict(updates_per_s=n_upd * K3o / dt3o, ms_per_step=dt3o / K3o * 1e3,
+                                            steps=K3o, plan=s3o.plan(), sweep_ms=s3o.time_sweep(n_launches=3)[0])
+        s3o.close()
+        log(f"finfet, second order: {n_upd * K3o / dt3o:.4e} updates/s")
         # ------------------------------------------- the 2D square
         p2 = bi.square_2d(256)
         s2 = bte.Solver(p2, precision="fp32", plan=dict(G=1, R=1, P=4, NR=4))

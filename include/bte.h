@@ -235,9 +235,11 @@ bte_status bte_set_tau(bte_handle h, const double* h_tau);
    second-order scheme. Green-Gauss face values: the mean of the two cells at
    an interior face, the wall value at an isothermal face the ordinate enters
    through, the linear extrapolation from the cell and its neighbour across
-   the opposite face at any other boundary face. Order 2 is built for 1D and
-   2D grids (BTE_ERR_INVALID on 3D), forces plans with G = 1, keeps the
-   angular field and a correction per ordinate in device memory, and has no
+   the opposite face at any other boundary face. Order 2 forces plans with
+   G = 1 and, in 3D, the rows-per-lane layout (a pencil plan moves to it;
+   bte_set_plan with a pencil plan then returns BTE_ERR_INVALID); it keeps the
+   angular field and a correction per ordinate, and a stencil table per
+   octant, in device memory (bte_workspace_bytes counts them), and has no
    adjoint (bte_adjoint returns BTE_ERR_STATE). Drops any solver state. */
 bte_status bte_set_order(bte_handle h, int order);
 

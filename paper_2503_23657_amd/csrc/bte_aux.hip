@@ -384,17 +384,33 @@ __global__ void zero_kernel(unsigned* p, long long n) {
 // from the field the last sweep stored in the same layout. The neighbours come
 // from the octant's stencil table (positions, or boundary codes), so that
 // every read but the stencil's field values is in position order. A thread
-// takes one position for kCorrGrp consecutive groups (groups are octant-major:
-// the stencil row is read once per octant met).
+// takes one position for kCorrGrp consecutive groups (groups are
+// octant-major).
 constexpr int kCorrGrp = 16;
+
+// Workgroups go to the chip's 8 XCDs in turn. The correction kernel remaps
+// its dispatch order so that each XCD takes a contiguous range of (group
+// chunk, position) blocks: the neighbour values a wave gathers, a step or a
+// plane period away, were then loaded into the same XCD's L2 by the blocks
+// beside it.
+__device__ __forceinline__ void xcd_blocks(int& bx, int& by) {
+  const int nx = gridDim.x, total = nx * gridDim.y;
+  const int lin = blockIdx.x + blockIdx.y * nx;
+  const int per = total / 8;
+  const int l = lin < per * 8 ? (lin % 8) * per + lin / 8 : lin;
+  bx = l % nx;
+  by = l / nx;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) corr_kernel(CorrArgs A) {
   const InstDev& I = A.inst[A.inst_id];
   const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
   if (st->done) return;
+  int bx, by;
+  xcd_blocks(bx, by);
   const long long ppo = I.pos_per_oct;
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long p = (long long)bx * 256 + threadIdx.x;
   if (p >= ppo) return;
   const int dim = I.dim;
   const int n_bface = I.n_bface;
@@ -405,58 +421,96 @@ __global__ void __launch_bounds__(256) corr_kernel(CorrArgs A) {
   T ih[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) ih[d] = T(1) / (T)A.h[d];
-  const int g0 = blockIdx.y * kCorrGrp, g1 = min(g0 + kCorrGrp, A.n_grp);
-  int o = -1;
-  bool cell = false;
-  int en[3] = {-1, -1, -1}, eu[3] = {-1, -1, -1}, euu[3] = {-1, -1, -1};
-  for (int g = g0; g < g1; ++g) {
-    const int4 gi = A.grp[g];
-    if (gi.y != o) {  // uniform: the block's groups share octants
-      o = gi.y;
-      const int* e = stencil + ((size_t)o * ppo + p) * (3 * dim);
-      cell = e[0] != kNoCell;
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (d < dim) {
-          en[d] = e[3 * d];
-          eu[d] = e[3 * d + 1];
-          euu[d] = e[3 * d + 2];
-        }
-    }
-    T* out = corr0 + (size_t)g * ppo;
-    if (!cell) {
-      out[p] = T(0);
-      continue;
-    }
-    const T* u = ufld + (size_t)g * ppo;
-    const T* ubf = ubf0 + (size_t)gi.w * n_bface;
-    const T uc = u[p];
-    T corr = T(0);
+  const int g0 = by * kCorrGrp, g1 = min(g0 + kCorrGrp, A.n_grp);
+  // the correction of group g from its field values: the cell, and per axis
+  // its downwind and upwind neighbours and the upwind one's upwind neighbour
+  auto corr_of = [&](int g, int o, const int* en, const int* eu, const int* euu, T uc, const T* un, const T* uu,
+                     const T* uuu) -> T {
+    const T* ubf = ubf0 + (size_t)A.grp[g].w * n_bface;
     const T h5 = T(0.5), t15 = T(1.5);
+    T corr = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (d >= dim) break;
-      const T un = en[d] >= 0 ? u[en[d]] : T(0);
-      const T uu = eu[d] >= 0 ? u[eu[d]] : T(0);
       // face values of the cell: downwind (never an inflow face: the mean
       // with the neighbour, else the extrapolation from the upwind side) and
       // upwind (the mean, the isothermal wall value, else the extrapolation
       // from the downwind side); the cell's own value when the opposite face
       // is a boundary too
-      const T fd = en[d] >= 0 ? h5 * (uc + un) : (eu[d] >= 0 ? t15 * uc - h5 * uu : uc);
-      const T fu = eu[d] >= 0 ? h5 * (uc + uu) : (eu[d] <= -2 ? ubf[-eu[d] - 2] : (en[d] >= 0 ? t15 * uc - h5 * un : uc));
+      const T fd = en[d] >= 0 ? h5 * (uc + un[d]) : (eu[d] >= 0 ? t15 * uc - h5 * uu[d] : uc);
+      const T fu = eu[d] >= 0 ? h5 * (uc + uu[d])
+                              : (eu[d] <= -2 ? ubf[-eu[d] - 2] : (en[d] >= 0 ? t15 * uc - h5 * un[d] : uc));
       // the upwind cell: its downwind face is shared with this cell
       T du = T(0);
       if (eu[d] >= 0) {
-        const T fuu = euu[d] >= 0 ? h5 * (uu + u[euu[d]]) : (euu[d] <= -2 ? ubf[-euu[d] - 2] : t15 * uu - h5 * uc);
-        du = h5 * (uu + uc) - fuu;
+        const T fuu = euu[d] >= 0 ? h5 * (uu[d] + uuu[d])
+                                  : (euu[d] <= -2 ? ubf[-euu[d] - 2] : t15 * uu[d] - h5 * uc);
+        du = h5 * (uu[d] + uc) - fuu;
       }
       // (fd - fu) - du is the gradient difference along the ordinate's
       // direction times h; along +d it changes sign in odd octants
       const T dd = ((o >> d) & 1) ? du - (fd - fu) : (fd - fu) - du;
       corr += (T)A.coef[(size_t)g * 3 + d] * ih[d] * dd;
     }
-    out[p] = corr;
+    return corr;
+  };
+  // groups in batches of kCorrBatch of one octant: every field value of a
+  // batch is loaded before any is used, so the gathers overlap
+  constexpr int kCorrBatch = 4;
+  for (int gb = g0; gb < g1; gb += kCorrBatch) {
+    const int nb = min(kCorrBatch, g1 - gb);
+    const int o = A.grp[gb].y;
+    bool same = true;
+    for (int i = 1; i < nb; ++i) same = same && A.grp[gb + i].y == o;
+    const int* e = stencil + ((size_t)o * ppo + p) * (3 * dim);
+    const bool cell = e[0] != kNoCell;
+    int en[3] = {-1, -1, -1}, eu[3] = {-1, -1, -1}, euu[3] = {-1, -1, -1};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d < dim) {
+        en[d] = e[3 * d];
+        eu[d] = e[3 * d + 1];
+        euu[d] = e[3 * d + 2];
+      }
+    if (same && nb == kCorrBatch) {
+      T uc[kCorrBatch], un[kCorrBatch][3], uu[kCorrBatch][3], uuu[kCorrBatch][3];
+#pragma unroll
+      for (int i = 0; i < kCorrBatch; ++i) {
+        const T* u = ufld + (size_t)(gb + i) * ppo;
+        uc[i] = cell ? u[p] : T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          un[i][d] = cell && en[d] >= 0 ? u[en[d]] : T(0);
+          uu[i][d] = cell && eu[d] >= 0 ? u[eu[d]] : T(0);
+          uuu[i][d] = cell && eu[d] >= 0 && euu[d] >= 0 ? u[euu[d]] : T(0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kCorrBatch; ++i)
+        corr0[(size_t)(gb + i) * ppo + p] = cell ? corr_of(gb + i, o, en, eu, euu, uc[i], un[i], uu[i], uuu[i]) : T(0);
+    } else {
+      for (int g = gb; g < gb + nb; ++g) {
+        const int og = A.grp[g].y;
+        const int* eg = stencil + ((size_t)og * ppo + p) * (3 * dim);
+        const bool cg = eg[0] != kNoCell;
+        int gn[3] = {-1, -1, -1}, gu[3] = {-1, -1, -1}, guu[3] = {-1, -1, -1};
+        T un[3] = {}, uu[3] = {}, uuu[3] = {};
+        const T* u = ufld + (size_t)g * ppo;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (d < dim) {
+            gn[d] = eg[3 * d];
+            gu[d] = eg[3 * d + 1];
+            guu[d] = eg[3 * d + 2];
+            if (cg) {
+              un[d] = gn[d] >= 0 ? u[gn[d]] : T(0);
+              uu[d] = gu[d] >= 0 ? u[gu[d]] : T(0);
+              uuu[d] = gu[d] >= 0 && guu[d] >= 0 ? u[guu[d]] : T(0);
+            }
+          }
+        corr0[(size_t)g * ppo + p] = cg ? corr_of(g, og, gn, gu, guu, u[p], un, uu, uuu) : T(0);
+      }
+    }
   }
 }
 

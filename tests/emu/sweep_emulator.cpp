@@ -390,9 +390,17 @@ int main(int argc, char** argv) {
     const int TP = T + nper;  // gpre row: wall slots per step, then the period table
     // plane + 1 of period q of octant o (0: none)
     auto ptab = [&](int o, int q) { return q >= 0 && q < nper ? S.gpre[(size_t)o * TP + T + q] : 0; };
+    // the job's partial-sum planes as the kernel writes them: every row of a
+    // lane-step inside the grid (grid bit k of the record) at cell index
+    // cid0 + k * dy, active or not; rows outside the grid are not written
+    // (their index would be a cell of the next line when the lane axis is x
+    // or y); the finalize then reads the active cells
+    std::vector<double> jp0(ncell), jp1(ncell);
     for (size_t bu = 0; bu < gs.bundle_first.size(); ++bu) {
       const int o = adj ? (gs.bundle_oct[bu] ^ (n_oct - 1)) : gs.bundle_oct[bu];
       const int dyc = (((o >> S.ax[1]) & 1) ? -1 : 1) * stride[S.ax[1]];
+      std::fill(jp0.begin(), jp0.end(), 0.0);
+      std::fill(jp1.begin(), jp1.end(), 0.0);
       for (int p = 0; p < P; ++p) {
         const int grp = gs.bundle_first[bu] + p;
         const double* gt = cf.data() + (size_t)grp * GS;
@@ -455,9 +463,13 @@ int main(int argc, char** argv) {
               const double fn = gt[go_a(G, S.ax[2])] * zu + gt[go_a(G, S.ax[1])] * yu + gt[go_a(G, S.ax[0])] * xu + S_;
               fnew[(size_t)l * NR + k] = fn;
               zc = fn;
+              if ((gm >> k) & 1) {
+                const int idx = cid0 + k * dyc;
+                if (idx < 0 || idx >= ncell) { printf("partial-sum row outside the plane\n"); exit(2); }
+                jp0[idx] += gt[go_wacc(G, 0)] * fn;
+                jp1[idx] += gt[go_wacc(G, 1)] * fn;
+              }
               if (act) {
-                acc0[cell] += gt[go_wacc(G, 0)] * fn;
-                acc1[cell] += gt[go_wacc(G, 1)] * fn;
                 if (store) (*store)[(size_t)grp * ncell + cell] = fn * gt[go_inv(G)];
                 if (tg) {
                   const double uf = (*stored)[(size_t)grp * ncell + cell];
@@ -501,6 +513,11 @@ int main(int argc, char** argv) {
           }
         }
       }
+      for (int c = 0; c < ncell; ++c)
+        if (hi.active[c]) {
+          acc0[c] += jp0[c];
+          acc1[c] += jp1[c];
+        }
     }
   };
   auto run_sweep = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,

@@ -76,6 +76,12 @@ CASES = [
      (1, 1, 2, 8, 1)),
     ("finfet_rows", lambda: bi.finfet_3d(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 2, 8, 1)),
     ("finfet_rows_mixed", lambda: bi.finfet_3d_mixed(scale=4, n_bands=2, n_theta=1, n_phi=1), 3, (1, 1, 1, 8, 1)),
+    # two rows per lane on odd-length axes: the last lane's second row lies
+    # outside the grid whichever axis the lanes run along
+    ("box3d_rows_odd_nr2", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=2, n_phi=1), 4,
+     (1, 1, 2, 8, 2)),
+    ("box3d_rows_odd_nr2_specular", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=2, n_phi=1,
+                                                             kinds=(0, 2)), 4, (1, 1, 1, 8, 2)),
     ("staircase_rows", lambda: bi.staircase_3d(1), 4, (1, 1, 2, 8, 1)),
     ("staircase_rows_specular", lambda: bi.staircase_3d(2), 4, (1, 1, 1, 8, 1)),
     # specular walls (every boundary but the isothermal bottom, hole faces included)

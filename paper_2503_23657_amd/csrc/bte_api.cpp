@@ -142,6 +142,8 @@ struct Inst {
   int* d_out_base = nullptr;
   int* d_pre_slot = nullptr;
   int* d_ofk = nullptr;
+  int* d_ent_df = nullptr;        // [n_oct][n_out_stride] diffuse face of each out-stream entry, or -1
+  double* d_wsum = nullptr;       // [n_oct][B][n_dface] per-octant sums of the diffuse-wall update
   int2* d_grp_ob = nullptr;
   void* d_xq[2] = {nullptr, nullptr};
   void* d_xqa[2] = {nullptr, nullptr};
@@ -470,6 +472,23 @@ bte_status build_plan_impl(bte_ctx* h, const Plan& pl_in) {
     HIPCHK(pp.upload(&I.d_out_base, S.out_base));
     HIPCHK(pp.upload(&I.d_pre_slot, S.pre_slot));
     HIPCHK(pp.upload(&I.d_ofk, S.ofk));
+    // diffuse-wall update: the diffuse face of each out-stream entry of each
+    // octant (-1: another face), and the per-octant band sums of those faces
+    I.d_ent_df = nullptr;
+    I.d_wsum = nullptr;
+    if (!I.hi.dface.empty()) {
+      const int nbf = (int)I.hi.bf_cell.size();
+      std::vector<int> df_of(nbf, -1);
+      for (size_t i = 0; i < I.hi.dface.size(); ++i) df_of[I.hi.dface[i]] = (int)i;
+      std::vector<int> ent((size_t)n_oct * S.n_out_stride, -1);
+      for (int oo = 0; oo < n_oct; ++oo)
+        for (int f = 0; f < nbf; ++f) {
+          const int e = S.ofk[(size_t)oo * nbf + f];
+          if (e >= 0 && df_of[f] >= 0) ent[(size_t)oo * S.n_out_stride + e] = df_of[f];
+        }
+      HIPCHK(pp.upload(&I.d_ent_df, ent));
+      HIPCHK(pp.alloc(&I.d_wsum, (size_t)n_oct * h->B * I.hi.dface.size()));
+    }
     I.d_xpre = nullptr;
     I.d_gpre = nullptr;
     I.d_out_tab = nullptr;
@@ -1096,9 +1115,12 @@ bte_status enqueue_walls(bte_ctx* h, bool adj, hipStream_t st) {
     w.B = h->B;
     w.rows = h->ubf_rows;
     w.dface_axis = I.d_dface_axis;
+    w.ent_df = I.d_ent_df;
+    w.wsum = I.d_wsum;
+    w.n_out = I.sch.n_out_stride;
     w.oct_xor = adj ? (1 << h->dim) - 1 : 0;
     w.scale = adj ? I.d_adj_scale : nullptr;
-    HIPCHK(launch_wall_update(h->precision, w, st));
+    HIPCHK(launch_wall_update(h->precision, w, 1 << h->dim, st));
   }
   return BTE_OK;
 }

@@ -249,6 +249,33 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(FinArgs A, const 
   }
 }
 
+// Lagged diffuse walls, in two passes so that every read of the out-stream is
+// coalesced. First one thread per (octant, band, out-stream entry of that
+// octant's schedule): the sum over the octant's groups of that band of the
+// entry's value, kept per (octant, band, diffuse face). Then one thread per
+// (band, diffuse face): the octants' sums in octant order, scaled into the
+// face's inflow value.
+template <typename T>
+__global__ void __launch_bounds__(256) wall_sum_kernel(WallArgs A) {
+  const InstDev& I = A.inst[A.inst_id];
+  const StatusDev* st = reinterpret_cast<const StatusDev*>(I.status);
+  if (st->done) return;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)I.n_oct * A.B * A.n_out) return;
+  const int k = (int)(t % A.n_out);
+  const int ob = (int)(t / A.n_out);
+  const int b = ob % A.B, o = ob / A.B;
+  const int df = A.ent_df[(size_t)o * A.n_out + k];
+  if (df < 0) return;
+  // o: the octant whose schedule emitted the entries; its groups belong to
+  // octant o ^ oct_xor (the transposed sweeps run the flipped schedule)
+  const int2 gr = A.grp_ob[(o ^ A.oct_xor) * A.B + b];
+  const T* outv = reinterpret_cast<const T*>(I.outv);
+  double s = 0.0;
+  for (int g = 0; g < gr.y; ++g) s += (double)outv[(size_t)(gr.x + g) * A.n_out + k];
+  A.wsum[((size_t)o * A.B + b) * A.n_dface + df] = s;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) wall_update_kernel(WallArgs A) {
   const InstDev& I = A.inst[A.inst_id];
@@ -258,16 +285,9 @@ __global__ void __launch_bounds__(256) wall_update_kernel(WallArgs A) {
   if (t >= A.n_dface * A.B) return;
   const int b = t / A.n_dface, df = t - b * A.n_dface;
   const int slot = A.dface_slot[df];
-  const T* outv = reinterpret_cast<const T*>(I.outv);
   double s = 0.0;
-  for (int o = 0; o < I.n_oct; ++o) {
-    // o: the octant whose schedule emitted the entries; its groups belong to
-    // octant o ^ oct_xor (the transposed sweeps run the flipped schedule)
-    const int k = A.ofk[(size_t)o * I.n_bface + slot];
-    if (k < 0) continue;
-    const int2 gr = A.grp_ob[(o ^ A.oct_xor) * A.B + b];
-    for (int g = 0; g < gr.y; ++g) s += (double)outv[(size_t)(gr.x + g) * I.n_out_stride + k];
-  }
+  for (int o = 0; o < I.n_oct; ++o)
+    if (A.ofk[(size_t)o * I.n_bface + slot] >= 0) s += A.wsum[((size_t)o * A.B + b) * A.n_dface + df];
   T* ubf = const_cast<T*>(reinterpret_cast<const T*>(I.ubf));
   // a diffuse wall's inflow is the same for every ordinate of the band
   const double sc = A.scale ? A.scale[b * 3 + A.dface_axis[df]] : 1.0;
@@ -543,6 +563,8 @@ __global__ void __launch_bounds__(256) corr_fill_kernel(CorrArgs A) {
 
 template __global__ void finalize_kernel<float>(FinArgs, const FinInst*);
 template __global__ void finalize_kernel<double>(FinArgs, const FinInst*);
+template __global__ void wall_sum_kernel<float>(WallArgs);
+template __global__ void wall_sum_kernel<double>(WallArgs);
 template __global__ void wall_update_kernel<float>(WallArgs);
 template __global__ void wall_update_kernel<double>(WallArgs);
 template __global__ void spec_update_kernel<float>(SpecArgs);
@@ -563,13 +585,17 @@ hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st) {
+hipError_t launch_wall_update(int prec, const WallArgs& a, int n_oct, hipStream_t st) {
   const long long n = (long long)a.n_dface * a.B;
   if (n == 0) return hipSuccess;
-  if (prec == BTE_PREC_FP32)
+  const long long ns = (long long)n_oct * a.B * a.n_out;
+  if (prec == BTE_PREC_FP32) {
+    hipLaunchKernelGGL(wall_sum_kernel<float>, dim3(nblk(ns)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(wall_update_kernel<float>, dim3(nblk(n)), dim3(256), 0, st, a);
-  else
+  } else {
+    hipLaunchKernelGGL(wall_sum_kernel<double>, dim3(nblk(ns)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(wall_update_kernel<double>, dim3(nblk(n)), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -271,6 +271,9 @@ struct WallArgs {
   const int* dface_axis;     // [n_dface] grid axis of each diffuse face
   int oct_xor;               // 0: forward; n_oct - 1: transposed sweeps (groups sweep the flipped octant)
   const double* scale;       // [B][3] factor per band and face axis (transposed sweeps), or NULL
+  const int* ent_df;         // [n_oct][n_out] diffuse face of each out-stream entry, or -1
+  double* wsum;              // [n_oct][B][n_dface] per-octant sums
+  int n_out;                 // out-stream entries per octant (the stride of outv's rows)
 };
 
 // Lagged specular-wall values (Eq. 7): the inflow of ordinate a at a specular

@@ -31,7 +31,7 @@ hipError_t launch_sweep3r(int prec, int NR, int P, int nacc, int mode, const Swe
 int sweep3r_blocks_per_cu(int prec, int NR, int P, int nacc, int mode, int block, size_t lds);
 
 hipError_t launch_finalize(int prec, const FinArgs& a, const FinInst* fi, hipStream_t st);
-hipError_t launch_wall_update(int prec, const WallArgs& a, hipStream_t st);
+hipError_t launch_wall_update(int prec, const WallArgs& a, int n_oct, hipStream_t st);
 hipError_t launch_spec_update(int prec, const SpecArgs& a, hipStream_t st);
 hipError_t launch_init_state(int prec, const InitArgs& a, int ncell, hipStream_t st);
 hipError_t launch_output(const double* X, const unsigned char* active, int n, double T_ref,

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int R = A.R;
+  const int R = L3 ? 1 : A.R;  // (3D rows plans have one wave slot per ordinate group)
   const int r = wave % R;
   const int p = wave / R;
   const int rprev = (r + R - 1) % R;
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
     for (int m = 0; m < kEPL; ++m) {
       if (m < NE) {
         const int s0 = ITAB[m * 64 + lane];
-        my_inb[m * 64 + lane] = s0 >= 0 ? UBF[s0] : T(0);
+        my_inb[m * 64 + lane] = s0 >= 0 ? UBF[s0] * (L3 ? den[0] : T(1)) : T(0);
         const int s1 = ITAB[Ei + m * 64 + lane];
         inval[m] = s1 >= 0 ? UBF[s1] : T(0);
         slot_n[m] = ITAB[2 * Ei + m * 64 + lane];
@@ -560,8 +560,12 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
                               L3 ? (unsigned)((nch + 2) * I.out_E) * 4u : 0u);
     const CAS int* OCH = L3 ? cp(I.out_chunk) + (size_t)o * (nch + 1) : nullptr;
     auto out_load = [&](int c) BTE_INL {
+      // entry m of the lane at (c * out_E + m * 64 + lane) * 4; an entry
+      // past the row (m >= NOE) gets an offset past the buffer (uniform, so
+      // no per-lane mask is kept)
+      const int lo = (c * I.out_E + lane) * 4;
 #pragma unroll
-      for (int m = 0; m < kOPL; ++m) oe[m] = bld<int>(OTR, m < NOE ? (c * I.out_E + m * 64 + lane) * 4 : kOOB);
+      for (int m = 0; m < kOPL; ++m) oe[m] = bld<int>(OTR, lo + (m < NOE ? m * 256 : kOOB));
     };
     if constexpr (L3) {
       out_load(0);
@@ -623,7 +627,10 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
       };
       if constexpr (XS) read_xv(RR[0], xv[0]);
       // 3D: a lane's stream entries (rows ascending, then the step, lane and
-      // plane axes, from its offset), for the step of record rn
+      // plane axes, from its offset), for the step of record rn. The offset
+      // of an axis without an inflow may point up to six entries past the
+      // chunk's buffer, still inside the workgroup's LDS (the next buffer or
+      // the staging area); that value is never selected
       auto in_read = [&](const int2 rn) BTE_INL {
         const unsigned fr = (unsigned)rn.y;
         const int e0 = (int)((fr >> F2_INOFF_SHIFT) & F2_INOFF_MASK);
@@ -634,9 +641,9 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
           const int ex = e0 + __builtin_popcount(fr & kAll & ((1u << (RB * k)) - 1u));
           const int ey = ex + ((b & B_INX) ? 1 : 0);
           const int ez = ey + ((b & B_INY) ? 1 : 0);
-          pin[k][0] = inbuf[min(ex, E - 1)];
-          pin[k][1] = inbuf[min(ey, E - 1)];
-          pin[k][2] = inbuf[min(ez, E - 1)];
+          pin[k][0] = inbuf[ex];
+          pin[k][1] = inbuf[ey];
+          pin[k][2] = inbuf[ez];
         }
       };
       if constexpr (L3 && IN == 2) in_read(RR[0]);
@@ -725,9 +732,9 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
             const unsigned b = fl >> (RB * k);
-            const T xu = (b & B_INX) ? pin[k][0] * den[0] : xin[k];
-            const T zu = (b & B_INY) ? pin[k][1] * den[0] : zc[0];
-            const T pu = (b & B_INZ) ? pin[k][2] * den[0] : zr[k];
+            const T xu = (b & B_INX) ? pin[k][0] : xin[k];
+            const T zu = (b & B_INY) ? pin[k][1] : zc[0];
+            const T pu = (b & B_INZ) ? pin[k][2] : zr[k];
             const T fn = fma(a1[0], zu, fma(a0[0], xu, fma(a2[0], pu, S[k])));
             f[0][k] = fn;
             zc[0] = fn;
@@ -881,7 +888,8 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
         //      reads 0); load the face slots of chunk ch+3
         if (u >= kC2 - kEPL) {
           const int m = kC2 - 1 - u;
-          my_inb[((ch + 1) & 1) * E + (m < NE ? m : 0) * 64 + lane] = inval[m];
+          // (3D: stored scaled into the lane's variable, read once per use)
+          my_inb[((ch + 1) & 1) * E + (m < NE ? m : 0) * 64 + lane] = L3 ? inval[m] * den[0] : inval[m];
           inval[m] = bld<T>(UBR, slot_n[m] * (int)sizeof(T));
           slot_n[m] = bld<int>(ITR, m < NE && ch + 3 < nch + 2 ? ((ch + 3) * Ei + m * 64 + lane) * 4 : kOOB);
         }

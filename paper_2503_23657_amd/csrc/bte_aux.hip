@@ -11,8 +11,9 @@ namespace bte {
 
 // The finalize gathers the jobs' partial sums of kFinCells cells with
 // 16-byte loads: a thread holds VW = 16 / sizeof(T) neighbouring cells and a
-// slice of the jobs (j = js, js + S, ...), eight loads in flight; the S slices
-// of a cell are then added in LDS, pairwise in a fixed order.
+// slice of the jobs (j = js, js + S, ...), kFinLoads loads in flight; the S
+// slices of a cell are then added in LDS, pairwise in a fixed order.
+constexpr int kFinLoads = 8;
 template <typename T>
 struct FinShape {
   static constexpr int VW = 16 / (int)sizeof(T);       // cells per load
@@ -33,12 +34,12 @@ __device__ __forceinline__ void job_sum_vec(const T* pl, int n_jobs, int jg, int
 #pragma unroll
   for (int e = 0; e < Sh::VW; ++e) acc[e] = 0.0;
   int j = js;
-  for (; j + 7 * Sh::S < n_jobs; j += 8 * Sh::S) {
-    V v[8];
+  for (; j + (kFinLoads - 1) * Sh::S < n_jobs; j += kFinLoads * Sh::S) {
+    V v[kFinLoads];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const V*>(at(j + u * Sh::S));
+    for (int u = 0; u < kFinLoads; ++u) v[u] = *reinterpret_cast<const V*>(at(j + u * Sh::S));
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kFinLoads; ++u)
 #pragma unroll
       for (int e = 0; e < Sh::VW; ++e) acc[e] += (double)v[u][e];
   }

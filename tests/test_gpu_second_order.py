@@ -128,6 +128,23 @@ def test_masks_3d_second_order_fixed_iterations(hip_lib, make):
     s.close()
 
 
+def test_finfet_quarter_all_bands_second_order(hip_lib):
+    """The FinFET-like mask at a quarter of its size per axis with all 15 bands
+    and 128 directions (the bench's band and direction counts), FP64 at 1e-10
+    and FP32 sweeps at 1e-4, three iterations."""
+    p = bi.finfet_3d(scale=4)
+    assert p.B == 15 and p.M == 128
+    r = oracle.solve(p, tol=0.0, max_iters=3, order=2, threads=oracle.num_threads())
+    act = p.mask > 0
+    for prec, bar in (("fp64", 1e-10), ("fp32", 1e-4)):
+        s = _solver(hip_lib, p, prec)
+        T, q, _ = s.solve(torch.tensor(p.Q, device="cuda"), tol=0.0, max_iters=3, check_every=3)
+        assert _rel(T.cpu().numpy(), r["T"], p) < bar, prec
+        qs = np.abs(r["q"][act]).max()
+        assert np.abs(q.cpu().numpy()[act] - r["q"][act]).max() < bar * qs, prec
+        s.close()
+
+
 def test_box_3d_second_order_converged_fp64_and_fp32(hip_lib):
     p = bi.random_box_3d(12, 10, 9, seed=4, n_bands=3, n_theta=2, n_phi=2, kinds=(0, 1))
     r = oracle.solve(p, tol=1e-12, order=2)

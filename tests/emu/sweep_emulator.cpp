@@ -92,6 +92,17 @@ int main(int argc, char** argv) {
   const int n_oct = S.n_oct, T = S.T, W = S.W;
   const int nch = T / Cc;
   std::vector<double> outv((size_t)gs.band.size() * S.n_out_stride, 0.0);
+  // second-order faces (argv[2] = "--order2"; rows-per-lane layouts, G = 1):
+  // each group's correction and stored field in its octant's position layout
+  // (position ((r*(T + kPad2) + t)*64 + l)*NR + k), as the kernels keep them
+  const bool second = argc > 2 && std::string(argv[2]) == "--order2";
+  if (second && (G != 1 || (dim == 3 && !S.l3r))) { printf("second order needs G = 1 and a rows layout\n"); return 1; }
+  const long long ppo = S.pos_per_oct;
+  std::vector<double> so_corr, so_fld;
+  if (second) {
+    so_corr.assign((size_t)gs.band.size() * ppo, 0.0);
+    so_fld.assign((size_t)gs.band.size() * ppo, 0.0);
+  }
   // one sweep: returns per-cell sums of wacc[0] and wacc[1] terms; optionally
   // stores u (forward) or accumulates the tau-gradient sums (adjoint)
   auto sweep = [&](const std::vector<double>& Xs, const std::vector<double>& Qs, const std::vector<double>& cf,
@@ -319,7 +330,9 @@ int main(int argc, char** argv) {
                 const unsigned b = fl >> (F2_ROW_BITS * k);
                 const bool act = (b & F2_ACT) != 0;
                 const int cell = act ? cid0 + k * dyc : -1;
-                const double S_ = act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0;
+                const long long pos = (((long long)r * Tp + tau_) * 64 + l) * NR + k;
+                const double S_ = (act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0) +
+                                  (second && !adj ? so_corr[(size_t)grp * ppo + pos] : 0.0);
                 const unsigned below = fl & kInAll & ((1u << (F2_ROW_BITS * k)) - 1u);
                 const int ex = e0 + __builtin_popcount(below);
                 const int ey = ex + ((b & F2_INX) ? 1 : 0);
@@ -333,6 +346,7 @@ int main(int argc, char** argv) {
                   const double fn = gt[go_a(G, 1) + gg] * zu + gt[go_a(G, 0) + gg] * xu + S_;
                   fnew[((size_t)l * NR + k) * G + gg] = fn;
                   zc[gg] = fn;
+                  if (second && !adj) so_fld[(size_t)grp * ppo + pos] = fn * gt[go_inv(G)];
                   a0s += gt[go_wacc(G, 0) + gg] * fn;
                   a1s += gt[go_wacc(G, 1) + gg] * fn;
                   if (act && store) (*store)[((size_t)grp * ncell + cell) * G + gg] = fn * gt[go_inv(G) + gg];
@@ -450,7 +464,9 @@ int main(int argc, char** argv) {
               if ((b & F3_ACT) && !((gm >> k) & 1)) { printf("bad grid mask\n"); exit(2); }
               const bool act = (b & F3_ACT) != 0;
               const int cell = act ? cid0 + k * dyc : -1;
-              const double S_ = act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0;
+              const long long pos = ((long long)t * 64 + l) * NR + k;
+              const double S_ = (act ? kS * Xs[cell] + cQ * Qs[cell] : 0.0) +
+                                (second && !adj ? so_corr[(size_t)grp * ppo + pos] : 0.0);
               const unsigned below = fl & kInAll & ((1u << (FB * k)) - 1u);
               const int ex = e0 + __builtin_popcount(below);
               const int ey = ex + ((b & F3_INX) ? 1 : 0);
@@ -463,6 +479,7 @@ int main(int argc, char** argv) {
               const double fn = gt[go_a(G, S.ax[2])] * zu + gt[go_a(G, S.ax[1])] * yu + gt[go_a(G, S.ax[0])] * xu + S_;
               fnew[(size_t)l * NR + k] = fn;
               zc = fn;
+              if (second && !adj) so_fld[(size_t)grp * ppo + pos] = fn * gt[go_inv(G)];
               if ((gm >> k) & 1) {
                 const int idx = cid0 + k * dyc;
                 if (idx < 0 || idx >= ncell) { printf("partial-sum row outside the plane\n"); exit(2); }
@@ -576,13 +593,72 @@ int main(int argc, char** argv) {
       }
     }
   };
+  // second-order correction of every position of every group from the stored
+  // field, through the library's stencil table (as the correction kernel).
+  // The emulated sweep carries f = den * u (the kernels carry w0 * f), so the
+  // coefficient of axis d is -t0 v_b s_d / 2
+  std::vector<int> stencil;
+  std::vector<double> cc;
+  if (second) {
+    stencil = corr_stencil(hi, S);
+    cc.assign((size_t)gs.band.size() * 3, 0.0);
+    for (size_t g = 0; g < gs.band.size(); ++g) {
+      const int a = gs.ords[g];
+      if (a < 0) continue;
+      for (int d = 0; d < dim; ++d) cc[g * 3 + d] = -t0 * v[gs.band[g]] * ords[a].s[d] / 2.0;
+    }
+  }
+  auto correction = [&]() {
+    const int W3 = 3 * dim;
+    for (size_t g = 0; g < gs.band.size(); ++g) {
+      const int o = gs.oct[g];
+      const int band = gs.band[g];
+      const int urow = has_spec ? band * Mf + std::max(0, gs.ords[g]) : band;
+      const double* u = so_fld.data() + g * ppo;
+      for (long long p = 0; p < ppo; ++p) {
+        const int* e = stencil.data() + ((size_t)o * ppo + p) * W3;
+        double corr = 0.0;
+        if (e[0] != kNoCell) {
+          const double uc = u[p];
+          for (int d = 0; d < dim; ++d) {
+            const int en = e[3 * d], eu = e[3 * d + 1], euu = e[3 * d + 2];
+            const double un = en >= 0 ? u[en] : 0.0, uu = eu >= 0 ? u[eu] : 0.0;
+            const double fd = en >= 0 ? 0.5 * (uc + un) : (eu >= 0 ? 1.5 * uc - 0.5 * uu : uc);
+            const double fu = eu >= 0 ? 0.5 * (uc + uu)
+                                      : (eu <= -2 ? ubf[(size_t)urow * nbf + (-eu - 2)] : (en >= 0 ? 1.5 * uc - 0.5 * un : uc));
+            double du = 0.0;
+            if (eu >= 0) {
+              const double fuu = euu >= 0 ? 0.5 * (uu + u[euu])
+                                          : (euu <= -2 ? ubf[(size_t)urow * nbf + (-euu - 2)] : 1.5 * uu - 0.5 * uc);
+              du = 0.5 * (uu + uc) - fuu;
+            }
+            const double dd = ((o >> d) & 1) ? du - (fd - fu) : (fd - fu) - du;
+            corr += cc[g * 3 + d] / hi.h[d] * dd;
+          }
+        }
+        so_corr[g * ppo + p] = corr;
+      }
+    }
+  };
+  if (second) {
+    // the first correction: the equilibrium field of the initial state
+    for (size_t g = 0; g < gs.band.size(); ++g) {
+      const int o = gs.oct[g];
+      for (int c = 0; c < ncell; ++c) {
+        const int p = S.pos[(size_t)o * ncell + c];
+        if (hi.active[c] && p >= 0) so_fld[g * ppo + p] = X[c];
+      }
+    }
+    correction();
+  }
   std::vector<double> acc0, acc1;
   for (int it = 0; it < iters; ++it) {
     run_sweep(X, Q, coef, false, ubf, acc0, acc1, nullptr, nullptr, nullptr, nullptr);
     update_walls(false, ubf);
+    if (second) correction();
     X = acc0;
   }
-  if (argc > 2) {
+  if (argc > 2 && !second) {
     // adjoint with dJ/dT read from argv[2] (ncell doubles)
     std::vector<double> g(ncell);
     FILE* fg = fopen(argv[2], "rb");

@@ -115,6 +115,32 @@ def test_emulated_sweep_matches_oracle(emu, tmp_path, name, make, iters, plan):
     assert np.abs(T[act] - r["T"][act]).max() < 1e-11 * np.abs(r["T"][act] - p.T_ref).max()
 
 
+# second-order faces: the emulated sweep adds each position's correction and
+# stores the field per position, and the correction comes from the library's
+# stencil table (corr_stencil), as in the kernels
+SECOND = [
+    ("film", lambda: bi.film_1d(n_cells=50, n_mu=8), (1, 1, 1, 8, 1)),
+    ("holes_diffuse_nr2", lambda: bi.multi_hole_2d(37, 70, seed=6, n_bands=2, n_theta=2, n_phi=1, kinds=(0, 1)),
+     (1, 1, 2, 8, 2)),
+    ("holes_specular", lambda: bi.multi_hole_2d(37, 70, seed=6, n_bands=2, n_theta=2, n_phi=1, kinds=(0, 2)),
+     (1, 1, 1, 8, 1)),
+    ("box3d_odd_nr2", lambda: bi.random_box_3d(11, 9, 13, seed=1, n_bands=2, n_theta=2, n_phi=1), (1, 1, 2, 8, 2)),
+    ("staircase_specular", lambda: bi.staircase_3d(2, n_bands=2, n_theta=1, n_phi=1), (1, 1, 1, 8, 1)),
+]
+
+
+@pytest.mark.parametrize("name,make,plan", SECOND, ids=[c[0] for c in SECOND])
+def test_emulated_second_order_matches_oracle(emu, tmp_path, name, make, plan):
+    p = make()
+    path = str(tmp_path / "in.bin")
+    _write(p, 5, plan, path)
+    out = subprocess.run([emu, path, "--order2"], capture_output=True, text=True, check=True).stdout.split()
+    T = np.array([float(x) for x in out])
+    r = oracle.solve(p, tol=0.0, max_iters=5, order=2)
+    act = p.mask > 0
+    assert np.abs(T[act] - r["T"][act]).max() < 1e-11 * np.abs(r["T"][act] - p.T_ref).max()
+
+
 @pytest.mark.parametrize("plan", [(2, 1, 1, 8, 1), (1, 1, 2, 8, 2)])
 def test_emulated_adjoint_matches_unrolled(emu, tmp_path, plan):
     p = bi.square_2d(8, L=0.06e-6, n_bands=3, n_theta=1, n_phi=1)

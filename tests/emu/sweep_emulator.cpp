@@ -4,8 +4,9 @@
 // suite to check that host logic against the oracle without a GPU: it mirrors
 // what each lane reads (own previous value, the lane below, the previous strip's
 // ring, the boundary stream) at each clock step of the schedule.
-// Usage: sweep_emulator problem.bin [dJdT.bin]
-//   prints T after n iterations, or, with dJ/dT, the adjoint gradients.
+// Usage: sweep_emulator problem.bin [dJdT.bin | --order2]
+//   prints T after n iterations, or, with dJ/dT, the adjoint gradients;
+//   --order2: second-order faces (deferred correction, rows layouts, G = 1).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>

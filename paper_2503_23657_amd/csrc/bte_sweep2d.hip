@@ -146,9 +146,12 @@ __global__ void __launch_bounds__(L3 ? 512 : 256) sweep2d_kernel(SweepArgs A) {
   // a chunk time the same on the bench shapes, so registers decide. The 3D
   // flux and second-order sweeps (eight-wave workgroups; four accumulators,
   // or the correction ring) take half a chunk: a whole one spilled to scratch
+  // (a quarter chunk for the second-order flux sweep, which has both)
   constexpr int kRingRegs = 2 + NV * (int)sizeof(T) / 4 * (MODE == M2_TAUGRAD ? 2 : 1) +
                             (MODE == M2_SECOND ? NR * (int)sizeof(T) / 4 : 0);
-  constexpr int KD = (kRingRegs * kC2 * G <= 96 && !(L3 && (NACC > 2 || MODE == M2_SECOND))) ? kC2 : kC2 / 2;
+  constexpr int KD = (L3 && NACC > 2 && MODE == M2_SECOND) ? kC2 / 4
+                     : (kRingRegs * kC2 * G <= 96 && !(L3 && (NACC > 2 || MODE == M2_SECOND))) ? kC2
+                                                                                              : kC2 / 2;
   using VX = typename Vec<T, NV>::type;
   using VR = typename Vec<T, NR>::type;
   constexpr int GS = grp_stride(G);

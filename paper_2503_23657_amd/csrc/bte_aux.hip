@@ -273,6 +273,8 @@ __global__ void __launch_bounds__(256) wall_sum_kernel(WallArgs A) {
   const int2 gr = A.grp_ob[(o ^ A.oct_xor) * A.B + b];
   const T* outv = reinterpret_cast<const T*>(I.outv);
   double s = 0.0;
+  // (unrolled so that the loads are in flight together; the sum keeps group order)
+#pragma unroll 8
   for (int g = 0; g < gr.y; ++g) s += (double)outv[(size_t)(gr.x + g) * A.n_out + k];
   A.wsum[((size_t)o * A.B + b) * A.n_dface + df] = s;
 }
